@@ -1,0 +1,197 @@
+"""Seeded synthetic inputs shared by the tests, the benchmark and the CPU oracle.
+
+This module holds no arithmetic of the solver method: it only draws the
+per-column horizontal coefficients K_T and the right-hand sides f, and names
+the five workloads.  Both the HIP path and the oracle receive these arrays as
+plain inputs.
+
+Random numbers come from SplitMix64 (Steele, Lea and Flood, "Fast splittable
+pseudorandom number generators", OOPSLA 2014), used as a counter-based
+generator: the n-th output (n = 0, 1, ...) of a stream started from state s0 is
+mix(s0 + (n + 1) * GAMMA), with GAMMA = 0x9E3779B97F4A7C15 and the published
+finaliser
+
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EB
+    z =  z ^ (z >> 31)
+
+Stream s of seed S starts from state S + s * 2**32.  Stream 0 draws K_T,
+stream 1 + r draws right-hand side r, stream 2**31 draws the sizes of the
+batched instances.  Values are generated in the canonical order
+g = (j * nx + i) * nz + k (z-contiguous, the host order), so they do not depend
+on the device layout.
+
+Uniform U[0,1): (x >> 11) * 2**-53.  U[-1,1]: 2U - 1.  N(0,1): Box-Muller on the
+pair (1 - U[2m], U[2m+1]), cos branch.
+"""
+
+from __future__ import annotations
+
+import dataclasses
+import math
+
+import numpy as np
+
+GAMMA = 0x9E3779B97F4A7C15
+_M1 = np.uint64(0xBF58476D1CE4E5B9)
+_M2 = np.uint64(0x94D049BB133111EB)
+_MASK64 = (1 << 64) - 1
+_CHUNK = 1 << 22
+
+STREAM_KH = 0
+STREAM_SIZES = 1 << 31
+
+
+def stream_state(seed: int, stream: int) -> int:
+    """Initial SplitMix64 state of stream `stream` for seed `seed`."""
+    return (int(seed) + int(stream) * (1 << 32)) & _MASK64
+
+
+def splitmix64(seed: int, stream: int, start: int, count: int) -> np.ndarray:
+    """Outputs start .. start+count-1 of the stream, as uint64."""
+    s0 = np.uint64(stream_state(seed, stream))
+    out = np.empty(count, dtype=np.uint64)
+    g = np.uint64(GAMMA)
+    with np.errstate(over="ignore"):
+        for c0 in range(0, count, _CHUNK):
+            c1 = min(count, c0 + _CHUNK)
+            n = np.arange(start + c0 + 1, start + c1 + 1, dtype=np.uint64)
+            z = s0 + n * g
+            z = (z ^ (z >> np.uint64(30))) * _M1
+            z = (z ^ (z >> np.uint64(27))) * _M2
+            out[c0:c1] = z ^ (z >> np.uint64(31))
+    return out
+
+
+def uniform01(seed: int, stream: int, count: int, start: int = 0) -> np.ndarray:
+    x = splitmix64(seed, stream, start, count)
+    return (x >> np.uint64(11)).astype(np.float64) * (2.0 ** -53)
+
+
+def uniform_pm1(seed: int, stream: int, count: int) -> np.ndarray:
+    return 2.0 * uniform01(seed, stream, count) - 1.0
+
+
+def normal(seed: int, stream: int, count: int) -> np.ndarray:
+    u = uniform01(seed, stream, 2 * count)
+    u1 = 1.0 - u[0::2]
+    u2 = u[1::2]
+    return np.sqrt(-2.0 * np.log(u1)) * np.cos(2.0 * math.pi * u2)
+
+
+# ---------------------------------------------------------------------------
+# Coefficient and right-hand-side draws
+# ---------------------------------------------------------------------------
+
+def kh_constant(nx: int, ny: int, value: float = 1.0) -> np.ndarray:
+    return np.full(nx * ny, float(value))
+
+
+def kh_uniform(seed: int, nx: int, ny: int, lo: float = 0.5, hi: float = 2.0) -> np.ndarray:
+    """Per-column K_T ~ U[lo, hi], canonical order j*nx + i."""
+    return lo + (hi - lo) * uniform01(seed, STREAM_KH, nx * ny)
+
+
+def kh_lognormal(seed: int, nx: int, ny: int, s: float = 0.5) -> np.ndarray:
+    """Per-column K_T = exp(s * N(0,1)), canonical order j*nx + i."""
+    return np.exp(s * normal(seed, STREAM_KH, nx * ny))
+
+
+def rhs(seed: int, r: int, nx: int, ny: int, nz: int) -> np.ndarray:
+    """Right-hand side number r, f ~ U[-1,1], canonical order (j*nx+i)*nz+k."""
+    return uniform_pm1(seed, 1 + r, nx * ny * nz)
+
+
+def quadratic_faces(nz: int) -> np.ndarray:
+    """Vertical faces z_k = (k/nz)^2, k = 0..nz: finest at the bottom."""
+    k = np.arange(nz + 1, dtype=np.float64)
+    return (k / nz) ** 2
+
+
+def uniform_faces(nz: int) -> np.ndarray:
+    return np.arange(nz + 1, dtype=np.float64) / nz
+
+
+# ---------------------------------------------------------------------------
+# Layout helpers (pure data movement)
+# ---------------------------------------------------------------------------
+
+def canonical_to_xcontig(a: np.ndarray, nx: int, ny: int, nz: int, ldx: int) -> np.ndarray:
+    """(j*nx+i)*nz+k order -> x-contiguous (j*nz+k)*ldx+i order, padding zeroed."""
+    v = np.asarray(a).reshape(ny, nx, nz).transpose(0, 2, 1)
+    out = np.zeros((ny, nz, ldx), dtype=np.asarray(a).dtype)
+    out[:, :, :nx] = v
+    return out.reshape(-1)
+
+
+def xcontig_to_canonical(a: np.ndarray, nx: int, ny: int, nz: int, ldx: int) -> np.ndarray:
+    v = np.asarray(a).reshape(ny, nz, ldx)[:, :, :nx]
+    return np.ascontiguousarray(v.transpose(0, 2, 1)).reshape(-1)
+
+
+# ---------------------------------------------------------------------------
+# The five workloads
+# ---------------------------------------------------------------------------
+
+@dataclasses.dataclass(frozen=True)
+class Workload:
+    name: str
+    nx: int
+    ny: int
+    nz: int
+    nlevels: int
+    kv: float
+    sigma: float
+    seed: int
+    kh_model: str          # "const", "uniform", "lognormal"
+    rtol: float
+    nrhs: int = 1
+
+    @property
+    def unknowns(self) -> int:
+        return self.nx * self.ny * self.nz
+
+    def kh(self) -> np.ndarray:
+        if self.kh_model == "const":
+            return kh_constant(self.nx, self.ny)
+        if self.kh_model == "uniform":
+            return kh_uniform(self.seed, self.nx, self.ny)
+        if self.kh_model == "lognormal":
+            return kh_lognormal(self.seed, self.nx, self.ny)
+        raise ValueError(self.kh_model)
+
+    def zfaces(self) -> np.ndarray:
+        return quadratic_faces(self.nz)
+
+    def rhs(self, r: int = 0) -> np.ndarray:
+        return rhs(self.seed, r, self.nx, self.ny, self.nz)
+
+
+SMALL = Workload("periodic-64x64x64-kv1e3", 64, 64, 64, 4, 1e3, 1.0, 1, "const", 1e-5)
+SHARE = Workload("periodic-1024x1024x128-kv1e4-Kuniform", 1024, 1024, 128, 6, 1e4, 1.0, 2,
+                 "uniform", 1e-8)
+LARGEST = Workload("periodic-2048x2048x128-kv1e5-Klognormal", 2048, 2048, 128, 7, 1e5, 1.0, 5,
+                   "lognormal", 1e-8)
+
+
+def coarsen_levels(n: int, nmin: int = 32) -> int:
+    """Levels for a batched instance: coarsen while the size stays >= nmin and even."""
+    levels = 1
+    while n % 2 == 0 and n // 2 >= nmin:
+        n //= 2
+        levels += 1
+    return levels
+
+
+def batched_instances(seed: int = 4, count: int = 64, nrhs: int = 4):
+    """The batched workload: `count` instances with seeded sizes, 4 RHS each."""
+    sizes = (128, 256, 384, 512)
+    depths = (32, 64, 128)
+    u = uniform01(seed, STREAM_SIZES, 2 * count)
+    out = []
+    for i in range(count):
+        n = sizes[min(3, int(4.0 * u[2 * i]))]
+        nz = depths[min(2, int(3.0 * u[2 * i + 1]))]
+        out.append(Workload(f"batch{i}-{n}x{n}x{nz}", n, n, nz, coarsen_levels(n), 1e4, 1.0,
+                            seed * 1000 + i, "uniform", 1e-8, nrhs))
+    return out
