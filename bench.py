@@ -1,0 +1,229 @@
+#!/usr/bin/env python3
+"""Benchmark of the tensor-product multigrid / line-CG path on one MI355X.
+
+Workload: one GPU's share at real shape, 1024 x 1024 x 128 = 134,217,728
+unknowns, doubly periodic, quadratically graded vertical grid, K_v = 1e4,
+per-column K_T ~ U[0.5, 2] (seed 2), sigma = 1, f ~ U[-1, 1]; 6 levels.
+
+One step = the whole hot path once on the resident input, every solve from
+u = 0 to a relative residual of 1e-8:
+  1. FP64 multigrid, V(1,1) cycles (Algorithm 1);
+  2. FP64 CG with the vertical line preconditioner (fused kernels);
+  3. mixed precision: FP32 V-cycles inside FP64 iterative refinement.
+value = sum over the three solves of (unknowns x iterations) / step time.
+
+The dominant kernel's roofline comes from the library's own per-kernel HIP
+event timing over the timed region (gmg_timing_*), on the stream the kernels
+run on.  The CPU baseline times the FP64 oracle (CSR) on a bounded sample of
+the same workload: one V-cycle plus one residual.
+
+Prints one JSON line on stdout; progress goes to stderr.
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "solve time & HBM GB/s (frac of peak) for MG/CG; mixed-prec vs FP64 to 1e-8"
+HBM_PEAK_GBS = 8000.0
+
+# algorithmic words per cell of the level a kernel runs on (intermediates of
+# the line solves and horizontal halos stay on chip; per-column coefficients
+# are amortised over the column)
+WORDS_PER_CELL = {
+    "spmv": 2.0,             # read x, write y
+    "residual": 3.0,         # read u, f, write r   (+0.5 with the FP32 copy)
+    "line_solve": 2.0,       # read r, write z
+    "smooth": 3.0,           # read u, f, write u'
+    "restrict_smooth": 6.0,  # per COARSE cell: read 4 fine r, write f_c, u_c
+    "prolongate": 2.25,      # per FINE cell: read/write u_f, read 1/4 u_c
+    "cg_spmv": 7.0,          # read u, p, z, q, write u, p, q
+    "cg_tridiag": 4.0,       # read r, q, write r, z
+}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def algorithmic_bytes(kernel, level, prec, w):
+    nx, ny, nz = w.nx >> level, w.ny >> level, w.nz
+    esize = 8 if prec == "f64" else 4
+    cells = nx * ny * nz
+    if kernel == "prolongate":          # timed under the coarse level
+        cells = (nx * 2) * (ny * 2) * nz
+    words = WORDS_PER_CELL.get(kernel)
+    if words is None:
+        return None
+    return words * cells * esize
+
+
+def cpu_baseline(w, f, kh, zf):
+    import numpy as np
+
+    import oracle
+    t0 = time.perf_counter()
+    p = oracle.OracleProblem(w.nx, w.ny, w.nz, w.nlevels, kv=w.kv, sigma=w.sigma, zfaces=zf,
+                             kh=kh)
+    t_asm = time.perf_counter() - t0
+    u = np.zeros_like(f)
+    t0 = time.perf_counter()
+    u = p.vcycle(f, u)
+    r = p.residual(f, u)
+    t_cyc = time.perf_counter() - t0
+    rel = float(np.linalg.norm(r) / np.linalg.norm(f))
+    del p
+    return {
+        "value": w.unknowns / t_cyc,
+        "unit": "unknowns*iterations/s",
+        "cores": oracle.num_threads(),
+        "kind": "oracle",
+        "sample": (f"one FP64 V(1,1) cycle + residual of the CSR oracle on the full "
+                   f"{w.nx}x{w.ny}x{w.nz} workload ({t_cyc:.1f} s; CSR assembly "
+                   f"{t_asm:.1f} s excluded; relres after the cycle {rel:.3e})"),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-cpu-baseline", action="store_true",
+                    help="skip the oracle timing (for profiler runs)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the path is "
+              "single-GPU by design", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_1402_3545_amd as G
+    import workloads as W
+
+    w = W.SHARE
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    log(f"[bench] generating inputs for {w.name}")
+    kh, zf, f = w.kh(), w.zfaces(), w.rhs()
+    ctx64 = G.GmgContext(w.nx, w.ny, w.nz, w.nlevels, kv=w.kv, sigma=w.sigma, zfaces=zf, kh=kh,
+                         prec_precond=G.GMG_F64)
+    ctx32 = G.GmgContext(w.nx, w.ny, w.nz, w.nlevels, kv=w.kv, sigma=w.sigma, zfaces=zf, kh=kh,
+                         prec_precond=G.GMG_F32)
+    fd = ctx64.to_device(f)
+    ud = ctx64.empty()
+    torch.cuda.synchronize()
+
+    def step():
+        out = {}
+        for name, fn in (("mg_f64", lambda: G.gmg_solve(ctx64, fd, ud, w.rtol, 100)),
+                         ("pcg_f64", lambda: G.pcg_solve(ctx64, fd, ud, w.rtol, 2000)),
+                         ("mg_mixed", lambda: G.gmg_solve(ctx32, fd, ud, w.rtol, 100))):
+            ud.zero_()
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            it, rel, _, st = fn()
+            b.record()
+            b.synchronize()
+            out[name] = {"iters": it, "relres": rel, "status": st, "ms": a.elapsed_time(b)}
+        return out
+
+    for k in range(args.warmup):
+        r = step()
+        log(f"[bench] warmup {k}: " + ", ".join(f"{n} {v['iters']} it {v['ms']:.1f} ms"
+                                                 for n, v in r.items()))
+    for c in (ctx64, ctx32):
+        G.gmg_timing_enable(c, True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    runs = [step() for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for c in (ctx64, ctx32):
+        G.gmg_timing_enable(c, False)
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    last = runs[-1]
+    for name, v in last.items():
+        if v["status"] != 0:
+            raise SystemExit(f"{name} did not converge: {v}")
+    work = sum(w.unknowns * v["iters"] for v in last.values())
+    value = work / (ms_per_step / 1e3)
+    log(f"[bench] {args.steps} steps, {ms_per_step:.1f} ms/step: " +
+        ", ".join(f"{n} {v['iters']} it {v['ms']:.1f} ms" for n, v in last.items()))
+
+    # per-kernel table over the timed region; dominant kernel's roofline
+    table = {}
+    for tag, c in (("f64ctx", ctx64), ("mixedctx", ctx32)):
+        for (kern, lvl, prec), (n, ms) in G.gmg_timing_table(c).items():
+            key = (kern, lvl, prec)
+            cn, cms = table.get(key, (0, 0.0))
+            table[key] = (cn + n, cms + ms)
+    dom = max((k for k in table if algorithmic_bytes(*k, w) is not None),
+              key=lambda k: table[k][1])
+    n_dom, ms_dom = table[dom]
+    avg_ms = ms_dom / n_dom
+    bytes_dom = algorithmic_bytes(*dom, w)
+    achieved = bytes_dom / (avg_ms / 1e3) / 1e9
+    breakdown = {f"{k[0]}@L{k[1]}/{k[2]}": {"launches": n, "ms": round(ms, 3)}
+                 for k, (n, ms) in sorted(table.items(), key=lambda kv: -kv[1][1])}
+    log("[bench] kernel breakdown (timed region): " + json.dumps(breakdown))
+
+    base = None
+    if not args.no_cpu_baseline:
+        log("[bench] timing the CPU oracle sample")
+        base = cpu_baseline(w, f, kh, zf)
+        log(f"[bench] oracle: {base['value']:.3e} unknowns*it/s on {base['cores']} threads")
+
+    mg, mx = last["mg_f64"], last["mg_mixed"]
+    line = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "unknowns*iterations/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": w.name,
+            "nx": w.nx, "ny": w.ny, "nz": w.nz, "levels": w.nlevels, "kv": w.kv,
+            "kh": "U[0.5,2] seed 2", "rtol": w.rtol,
+            "step": "FP64 MG + FP64 line-CG + FP32-cycle MG in FP64 refinement, each from u=0",
+        },
+        "solves": {n: {"iters": v["iters"], "ms": round(v["ms"], 3),
+                       "relres": v["relres"]} for n, v in last.items()},
+        "mixed_vs_fp64_mg_speedup": mg["ms"] / mx["ms"] if mx["ms"] > 0 else None,
+        "roofline": {
+            "bound": "hbm",
+            "kernel": f"{dom[0]} level {dom[1]} {dom[2]}",
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": None,
+            "avg_ms": avg_ms,
+            "launches": n_dom,
+            "algorithmic_bytes": bytes_dom,
+        },
+        "kernel_breakdown_ms": breakdown,
+        "cpu_baseline": base,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

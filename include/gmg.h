@@ -1,0 +1,182 @@
+/*
+ * gmg.h -- C ABI of the MI355X (gfx950) tensor-product multigrid and
+ * line-preconditioned CG library.
+ *
+ * Method: Mueller, Scheichl & Vainikko, "Petascale elliptic solvers for
+ * anisotropic PDEs on GPU clusters" (arXiv:1402.3545).
+ *
+ * Operator (Sec. 2.1.1, column-block form; Sec. 3.1, matrix-free tensor-product
+ * stencil).  Columns T = (i, j) of a doubly periodic nx x ny grid on the unit
+ * square, nz layers between the faces z_0 < ... < z_nz.  With |T| = hx*hy,
+ * dz_k = z_{k+1} - z_k, cell centres zeta_k and vertical transmissibilities
+ * t_k = kv / (zeta_k - zeta_{k-1}) (interior faces), t_0 = 2 kv / dz_0 and
+ * t_nz = 2 kv / dz_{nz-1} (Dirichlet ends) or 0 (Neumann ends):
+ *
+ *   (A u)_{T,k} = |T| [ sigma dz_k u_{T,k} + t_k (u_{T,k} - u_{T,k-1})
+ *                                        + t_{k+1} (u_{T,k} - u_{T,k+1}) ]
+ *               + dz_k sum_{T' in N(T)} C_TT' (u_{T,k} - u_{T',k})
+ *
+ * where C_TT' is the harmonic mean of the column coefficients K_T, K_T' times
+ * the face-length / centre-distance ratio (hy/hx in x, hx/hy in y), and
+ * u_{T,-1} = u_{T,nz} = 0.  M = blockdiag(A_T) is the vertical line operator of
+ * Sec. 2.2.  Coarse levels halve nx and ny (horizontal-only semicoarsening),
+ * average K over the four children and rediscretise.
+ *
+ * Field layout on the device (Sec. 3.1, x-contiguous ordering): element
+ * (i, j, k) of a level is at index (j*nz + k)*ldx + i, ldx >= nx padded to a
+ * multiple of 32 elements; gmg_field_layout() returns ldx and the element count
+ * of each level.  Padding elements are never read.
+ *
+ * Levels are numbered by depth: 0 is the finest grid (the paper's level L),
+ * nlevels-1 the coarsest (the paper's level 1).
+ *
+ * Conventions for every entry point:
+ *  - Pointers named f, u, x, y, r, z are DEVICE pointers owned by the caller,
+ *    in the layout above, 8-byte (GMG_F64) or 4-byte (GMG_F32) elements,
+ *    aligned to at least 16 bytes.  The library keeps no reference to them.
+ *  - `stream` is a hipStream_t (NULL = the null stream).  Kernels are enqueued
+ *    on it; spmv, line_solve, line_smooth, gmg_residual, gmg_restrict_smooth,
+ *    gmg_prolongate and gmg_vcycle return without synchronising.  The solvers
+ *    synchronise the stream before they return their scalars.
+ *  - A context must not be used from two host threads or two streams at once.
+ *  - Every function returns GMG_OK or a negative gmg_status; nothing aborts or
+ *    prints.  gmg_last_error() gives a message for the calling thread's last
+ *    failure.
+ */
+#ifndef GMG_H
+#define GMG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct gmg_ctx gmg_ctx;
+
+typedef enum {
+  GMG_OK = 0,
+  GMG_EINVAL = -1,       /* bad argument: shape, pointer, tolerance, level */
+  GMG_ENOMEM = -2,       /* device or host allocation failed */
+  GMG_EHIP = -3,         /* a HIP runtime call failed */
+  GMG_ENOCONV = -4,      /* solver hit maxit, or a reduction became NaN/Inf */
+  GMG_EUNSUPPORTED = -5  /* valid request this build does not implement */
+} gmg_status;
+
+typedef enum { GMG_F64 = 0, GMG_F32 = 1 } gmg_prec;
+
+typedef struct {
+  int32_t nx, ny, nz;     /* finest grid; nx, ny divisible by 2^(nlevels-1),
+                             >= 2 columns per direction on the coarsest level;
+                             2 <= nz <= 128 */
+  int32_t nlevels;        /* >= 1 */
+  int32_t bc_h;           /* 0 = doubly periodic (the only value supported) */
+  int32_t bc_v;           /* 0 = Dirichlet top and bottom, 1 = Neumann */
+  double kv;              /* vertical coefficient K_v >= 0 */
+  double sigma;           /* zero-order coefficient > 0 */
+  const double *zfaces;   /* HOST, nz+1 strictly increasing faces; NULL = (k/nz)^2 */
+  const double *kh;       /* HOST, nx*ny positive column coefficients, index j*nx+i;
+                             NULL = 1 */
+  double rho;             /* smoother damping (Sec. 5: 2/3) */
+  int32_t ncoarse;        /* smoothing steps on the coarsest level (Sec. 2.2: 2) */
+  int32_t prec_precond;   /* GMG_F64 or GMG_F32: precision of the V-cycle used by
+                             gmg_vcycle / gmg_solve / pcg_solve(precond=1) */
+} gmg_params;
+
+/* Fill *p with the defaults: bc periodic/Dirichlet, kv 1, sigma 1, rho 2/3,
+ * ncoarse 2, prec_precond GMG_F64, zfaces and kh NULL. */
+void gmg_default_params(gmg_params *p);
+
+/* Build a context: vertical profiles, per-level face couplings (FP64 and FP32
+ * copies), the level hierarchy and all scratch, on the current HIP device.
+ * The host arrays zfaces/kh are copied; the caller may free them afterwards.
+ * Synchronises `stream`.  *out receives the context (NULL on failure). */
+int gmg_setup(const gmg_params *p, void *stream, gmg_ctx **out);
+
+/* Free every device and host resource of the context.  NULL is accepted. */
+int gmg_destroy(gmg_ctx *c);
+
+/* Layout of level `level`: leading dimension ldx (elements) and the number
+ * of elements a field of that level occupies (ny * nz * ldx). */
+int gmg_field_layout(const gmg_ctx *c, int level, int64_t *ldx, int64_t *elems);
+
+/* y = A x on level `level` (the SpMV of Sec. 2.2, eq. for y <- A x).  x and y
+ * must not overlap. */
+int spmv(gmg_ctx *c, int level, int prec, const void *x, void *y, void *stream);
+
+/* z = M^{-1} r: the vertical line solve (Sec. 2.2, preconditioner y <- M^{-1} x;
+ * one tridiagonal system per column).  r and z may be the same buffer. */
+int line_solve(gmg_ctx *c, int level, int prec, const void *r, void *z, void *stream);
+
+/* nsweeps steps of the block-Jacobi smoother u <- u + rho M^{-1} (f - A u)
+ * (Sec. 2.2, smoother equation; kernel "Smooth" of Sec. 3.1).  u is updated in
+ * place as seen by the caller (the library ping-pongs through its own buffer). */
+int line_smooth(gmg_ctx *c, int level, int prec, const void *f, void *u, int nsweeps,
+                double rho, void *stream);
+
+/* r = f - A u (kernel "Residual", Sec. 3.1).  If norm2 is not NULL it receives
+ * ||r||_2^2 accumulated in FP64 (this synchronises the stream). */
+int gmg_residual(gmg_ctx *c, int level, int prec, const void *f, const void *u, void *r,
+                 double *norm2, void *stream);
+
+/* Kernel "ResSmooth" (Sec. 3.1, Algorithm 1): fc = R rf, the sum over the four
+ * horizontal children, then uc = rho M^{-1} fc (one smoothing step from a zero
+ * initial guess).  level is the COARSE level (>= 1); rf lives on level-1. */
+int gmg_restrict_smooth(gmg_ctx *c, int level, int prec, const void *rf, void *fc, void *uc,
+                        double rho, void *stream);
+
+/* Kernel "Prolongate" (Sec. 3.1, Algorithm 1): uf += P uc, cell-centred bilinear
+ * interpolation in the horizontal (weights 9/16, 3/16, 3/16, 1/16; periodic).
+ * level is the COARSE level (>= 1); uf lives on level-1. */
+int gmg_prolongate(gmg_ctx *c, int level, int prec, const void *uc, void *uf, void *stream);
+
+/* One V(1,1) cycle of Algorithm 1 on the finest level in the precision
+ * prec_precond: f and u are fields of that precision; u is updated in place.
+ * On the coarsest level the exact solve is replaced by ResSmooth followed by
+ * ncoarse-1 Smooth steps. */
+int gmg_vcycle(gmg_ctx *c, const void *f, void *u, void *stream);
+
+/* Multigrid solve of A u = f (FP64 f, u on the device; u holds the initial
+ * guess).  prec_precond == GMG_F64: V-cycles until ||f - A u|| / ||f - A u_0||
+ * < rtol (Sec. 2.2, stopping test).  prec_precond == GMG_F32: FP64 iterative
+ * refinement, each step one FP32 V-cycle on the FP64 residual.  *iters gets
+ * the number of cycles, *relres the final FP64 relative residual, history
+ * (host, maxit+1 doubles, may be NULL) the relative residual after each cycle.
+ * Returns GMG_ENOCONV if maxit is reached or the residual is not finite. */
+int gmg_solve(gmg_ctx *c, const double *f, double *u, double rtol, int maxit, int *iters,
+              double *relres, double *history, void *stream);
+
+/* Preconditioned CG (Sec. 2.2; fused kernels of Sec. 3.1).  precond = 0: the
+ * vertical line preconditioner M in FP64, with the two fused kernels
+ * (SpMV + vector updates + <p,q>; line solve + residual update + <r,r>, <r,z>).
+ * precond = 1: flexible CG with one V-cycle (in prec_precond) as the
+ * preconditioner.  Stops when the recursively updated ||r|| / ||r_0|| < rtol;
+ * *relres gets the TRUE relative residual ||f - A u|| / ||f - A u_0|| at exit,
+ * history (host, maxit+1, may be NULL) the recursive one per iteration. */
+int pcg_solve(gmg_ctx *c, const double *f, double *u, double rtol, int maxit, int precond,
+              int *iters, double *relres, double *history, void *stream);
+
+/* Per-kernel timing (measurement support; the paper's per-kernel, per-level
+ * breakdown tables, Sec. 5.3).  While enabled, every kernel the context
+ * launches is bracketed by two HIP events on its launch stream.
+ * gmg_timing_enable(c, 1) clears earlier records and starts recording;
+ * gmg_timing_enable(c, 0) stops.  gmg_timing_read() waits for the recorded
+ * events and returns, for one kernel kind / level / precision, the number of
+ * launches and their summed duration in milliseconds since the last enable.
+ * level = -1 sums over all levels. */
+typedef enum {
+  GMG_K_SPMV = 0, GMG_K_RESIDUAL = 1, GMG_K_LINE_SOLVE = 2, GMG_K_SMOOTH = 3,
+  GMG_K_RESTRICT_SMOOTH = 4, GMG_K_PROLONGATE = 5, GMG_K_CG_SPMV = 6, GMG_K_CG_TRIDIAG = 7,
+  GMG_K_REDUCE = 8, GMG_K_AUX = 9, GMG_K_COUNT = 10
+} gmg_kernel;
+int gmg_timing_enable(gmg_ctx *c, int enable);
+int gmg_timing_read(gmg_ctx *c, int kernel, int level, int prec, int64_t *count,
+                    double *total_ms);
+
+/* Message describing the calling thread's last non-OK status. */
+const char *gmg_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GMG_H */

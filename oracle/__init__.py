@@ -33,6 +33,13 @@ def _load():
     lib.or_create.restype = C.c_void_p
     lib.or_create.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_double,
                               C.c_double, _D, _D, C.c_double, C.c_int]
+    lib.or_create_matfree.restype = C.c_void_p
+    lib.or_create_matfree.argtypes = lib.or_create.argtypes
+    lib.or_apply_rows.argtypes = [C.c_void_p, C.c_int, C.c_int64, C.POINTER(C.c_int64), _D, _D]
+    lib.or_residual_norm2_rows.restype = C.c_double
+    lib.or_residual_norm2_rows.argtypes = [C.c_void_p, C.c_int, _D, _D]
+    lib.or_line_solve_columns.argtypes = [C.c_void_p, C.c_int, C.c_int64,
+                                          C.POINTER(C.c_int64), _D, _D]
     lib.or_destroy.argtypes = [C.c_void_p]
     lib.or_last_error.restype = C.c_char_p
     lib.or_shape.argtypes = [C.c_void_p, C.c_int, _I, _I, _I]
@@ -71,7 +78,7 @@ class OracleProblem:
     """The discrete operator hierarchy, assembled as CSR on the host."""
 
     def __init__(self, nx, ny, nz, nlevels=1, kv=1.0, sigma=1.0, zfaces=None, kh=None,
-                 bc_v=0, rho=2.0 / 3.0, ncoarse=2):
+                 bc_v=0, rho=2.0 / 3.0, ncoarse=2, matfree=False):
         lib = _load()
         self.nx, self.ny, self.nz, self.nlevels = int(nx), int(ny), int(nz), int(nlevels)
         self.rho = float(rho)
@@ -81,7 +88,8 @@ class OracleProblem:
             raise ValueError("zfaces needs nz+1 entries")
         if kk is not None and kk.size != nx * ny:
             raise ValueError("kh needs nx*ny entries")
-        h = lib.or_create(nx, ny, nz, nlevels, 0, bc_v, float(kv), float(sigma),
+        create = lib.or_create_matfree if matfree else lib.or_create
+        h = create(nx, ny, nz, nlevels, 0, bc_v, float(kv), float(sigma),
                           _p(zf) if zf is not None else None,
                           _p(kk) if kk is not None else None, float(rho), int(ncoarse))
         if not h:
@@ -211,3 +219,36 @@ class OracleProblem:
         st = self._chk(_lib.or_pcg_solve(self._h, _p(f), _p(u), float(rtol), int(maxit),
                                          C.byref(it), _p(hist), C.byref(rt)))
         return u, it.value, hist[: it.value + 1].copy(), rt.value, st
+
+    # -- row-wise forms (also available without the CSR matrices) ------------
+    def apply_rows(self, rows, x, depth=0):
+        """(A x) at the given canonical row indices."""
+        rows = np.ascontiguousarray(rows, dtype=np.int64)
+        x = self._vec(x, depth)
+        y = np.empty(rows.size)
+        self._chk(_lib.or_apply_rows(self._h, depth, rows.size,
+                                     rows.ctypes.data_as(C.POINTER(C.c_int64)), _p(x), _p(y)))
+        return y
+
+    def residual_norm2_rows(self, f, u, depth=0):
+        f, u = self._vec(f, depth), self._vec(u, depth)
+        v = _lib.or_residual_norm2_rows(self._h, depth, _p(f), _p(u))
+        if v < 0:
+            raise RuntimeError(_lib.or_last_error().decode())
+        return v
+
+    def line_solve_columns(self, cols, r, depth=0):
+        """M^{-1} r on the listed columns (index j*nx+i); other entries are NaN."""
+        cols = np.ascontiguousarray(cols, dtype=np.int64)
+        r = self._vec(r, depth)
+        z = np.full_like(r, np.nan)
+        self._chk(_lib.or_line_solve_columns(self._h, depth, cols.size,
+                                             cols.ctypes.data_as(C.POINTER(C.c_int64)), _p(r),
+                                             _p(z)))
+        return z
+
+    def column_rows(self, cols, depth=0):
+        """Canonical row indices of all layers of the listed columns."""
+        nz = self.nz
+        cols = np.asarray(cols, dtype=np.int64)
+        return (cols[:, None] * nz + np.arange(nz)[None, :]).reshape(-1)

@@ -228,9 +228,9 @@ void or_destroy(or_problem *p) {
   free(p);
 }
 
-or_problem *or_create(int nx, int ny, int nz, int nlevels, int bc_h, int bc_v,
-                      double kv, double sigma, const double *zfaces,
-                      const double *kh, double rho, int ncoarse) {
+static or_problem *create(int nx, int ny, int nz, int nlevels, int bc_h, int bc_v, double kv,
+                          double sigma, const double *zfaces, const double *kh, double rho,
+                          int ncoarse, int assemble) {
   if (nx < 2 || ny < 2 || nz < 2 || nlevels < 1) {
     set_err("need nx, ny, nz >= 2 and nlevels >= 1");
     return NULL;
@@ -297,6 +297,7 @@ or_problem *or_create(int nx, int ny, int nz, int nlevels, int bc_h, int bc_v,
         }
     }
     build_faces(L);
+    if (!assemble) continue;
     if (assemble_level(p, L)) {
       set_err("out of memory assembling CSR");
       or_destroy(p);
@@ -309,6 +310,7 @@ or_problem *or_create(int nx, int ny, int nz, int nlevels, int bc_h, int bc_v,
     L->r = (double *)xcalloc((size_t)L->n, sizeof(double));
     L->t = (double *)xcalloc((size_t)L->n, sizeof(double));
   }
+  if (!assemble) return p;
   int64_t n0 = p->lev[0].n;
   p->w1 = (double *)xcalloc((size_t)n0, sizeof(double));
   p->w2 = (double *)xcalloc((size_t)n0, sizeof(double));
@@ -323,9 +325,32 @@ or_problem *or_create(int nx, int ny, int nz, int nlevels, int bc_h, int bc_v,
   return p;
 }
 
+or_problem *or_create(int nx, int ny, int nz, int nlevels, int bc_h, int bc_v, double kv,
+                      double sigma, const double *zfaces, const double *kh, double rho,
+                      int ncoarse) {
+  return create(nx, ny, nz, nlevels, bc_h, bc_v, kv, sigma, zfaces, kh, rho, ncoarse, 1);
+}
+
+/* Same hierarchy without the CSR matrices: only the row-wise functions below
+ * (and restriction / prolongation) are available.  For grids too large to
+ * assemble, to check sampled rows and columns and full residual norms. */
+or_problem *or_create_matfree(int nx, int ny, int nz, int nlevels, int bc_h, int bc_v, double kv,
+                              double sigma, const double *zfaces, const double *kh, double rho,
+                              int ncoarse) {
+  return create(nx, ny, nz, nlevels, bc_h, bc_v, kv, sigma, zfaces, kh, rho, ncoarse, 0);
+}
+
 static int bad_depth(const or_problem *p, int d) {
   if (!p || d < 0 || d >= p->nlevels) {
     set_err("bad level");
+    return 1;
+  }
+  return 0;
+}
+
+static int no_csr(const or_problem *p, int d) {
+  if (!p->lev[d].rowptr) {
+    set_err("this problem was created without CSR matrices");
     return 1;
   }
   return 0;
@@ -343,7 +368,7 @@ int64_t or_nnz(const or_problem *p, int d) {
 }
 
 int or_csr(const or_problem *p, int d, int64_t *rowptr, int32_t *col, double *val) {
-  if (bad_depth(p, d)) return -1;
+  if (bad_depth(p, d) || no_csr(p, d)) return -1;
   const level_t *L = &p->lev[d];
   memcpy(rowptr, L->rowptr, (size_t)(L->n + 1) * sizeof(int64_t));
   memcpy(col, L->col, (size_t)L->nnz * sizeof(int32_t));
@@ -390,7 +415,7 @@ static void csr_mv(const level_t *L, const double *x, double *y) {
 }
 
 int or_spmv(const or_problem *p, int d, const double *x, double *y) {
-  if (bad_depth(p, d)) return -1;
+  if (bad_depth(p, d) || no_csr(p, d)) return -1;
   csr_mv(&p->lev[d], x, y);
   return 0;
 }
@@ -405,7 +430,7 @@ static void residual(const level_t *L, const double *f, const double *u, double 
 }
 
 int or_residual(const or_problem *p, int d, const double *f, const double *u, double *r) {
-  if (bad_depth(p, d)) return -1;
+  if (bad_depth(p, d) || no_csr(p, d)) return -1;
   residual(&p->lev[d], f, u, r);
   return 0;
 }
@@ -454,7 +479,7 @@ static void line_solve(const level_t *L, const double *r, double *z) {
 }
 
 int or_line_solve(const or_problem *p, int d, const double *r, double *z) {
-  if (bad_depth(p, d)) return -1;
+  if (bad_depth(p, d) || no_csr(p, d)) return -1;
   line_solve(&p->lev[d], r, z);
   return 0;
 }
@@ -469,7 +494,7 @@ static void smooth(const level_t *L, const double *f, double *u, double rho, dou
 }
 
 int or_smooth(or_problem *p, int d, const double *f, double *u, double rho) {
-  if (bad_depth(p, d)) return -1;
+  if (bad_depth(p, d) || no_csr(p, d)) return -1;
   level_t *L = &p->lev[d];
   smooth(L, f, u, rho, L->r, L->t);
   return 0;
@@ -535,7 +560,7 @@ static void restrict_smooth(const level_t *F, const level_t *C, const double *rf
 
 int or_restrict_smooth(or_problem *p, int dc, const double *rf, double *fc, double *uc,
                        double rho) {
-  if (bad_depth(p, dc) || bad_depth(p, dc - 1)) return -1;
+  if (bad_depth(p, dc) || bad_depth(p, dc - 1) || no_csr(p, dc)) return -1;
   restrict_smooth(&p->lev[dc - 1], &p->lev[dc], rf, fc, uc, rho);
   return 0;
 }
@@ -573,7 +598,7 @@ static void vcycle(or_problem *p, int d, const double *f, double *u) {
 }
 
 int or_vcycle(or_problem *p, const double *f, double *u) {
-  if (!p) return -1;
+  if (!p || no_csr(p, 0)) return -1;
   vcycle(p, 0, f, u);
   return 0;
 }
@@ -585,6 +610,7 @@ int or_vcycle(or_problem *p, const double *f, double *u) {
 int or_mg_solve(or_problem *p, const double *f, double *u, double rtol, int maxit, int *iters,
                 double *history) {
   if (!p || rtol <= 0.0 || maxit < 0) { set_err("bad arguments"); return -1; }
+  if (no_csr(p, 0)) return -1;
   level_t *L = &p->lev[0];
   residual(L, f, u, p->w1);
   double r0 = nrm2(L->n, p->w1);
@@ -611,6 +637,7 @@ int or_mg_solve(or_problem *p, const double *f, double *u, double rtol, int maxi
 int or_pcg_solve(or_problem *p, const double *f, double *u, double rtol, int maxit, int *iters,
                  double *history, double *relres_true) {
   if (!p || rtol <= 0.0 || maxit < 0) { set_err("bad arguments"); return -1; }
+  if (no_csr(p, 0)) return -1;
   level_t *L = &p->lev[0];
   int64_t n = L->n;
   double *r = p->w1, *z = p->w2, *pp = p->w3, *q = p->w4;
@@ -649,4 +676,99 @@ int or_pcg_solve(or_problem *p, const double *f, double *u, double rtol, int max
     *relres_true = nrm2(n, p->w5) / r0;
   }
   return status;
+}
+
+/* ---------------------------------------------------------------------------
+ * Row-wise forms of the same definitions (no stored matrix): each row comes
+ * from assemble_row, the routine that also fills the CSR arrays.
+ * ------------------------------------------------------------------------- */
+static void decode(const level_t *L, int64_t g, int *i, int *j, int *k) {
+  *k = (int)(g % L->nz);
+  int64_t c = g / L->nz;
+  *i = (int)(c % L->nx);
+  *j = (int)(c / L->nx);
+}
+
+/* y[q] = (A x)_{rows[q]} */
+int or_apply_rows(const or_problem *p, int d, int64_t nrows, const int64_t *rows,
+                  const double *x, double *y) {
+  if (bad_depth(p, d)) return -1;
+  const level_t *L = &p->lev[d];
+#pragma omp parallel for schedule(static)
+  for (int64_t q = 0; q < nrows; ++q) {
+    int32_t cols[8];
+    double vals[8];
+    int i, j, k;
+    decode(L, rows[q], &i, &j, &k);
+    int m = assemble_row(p, L, i, j, k, cols, vals);
+    double s = 0.0;
+    for (int e = 0; e < m; ++e) s += vals[e] * x[cols[e]];
+    y[q] = s;
+  }
+  return 0;
+}
+
+/* ||f - A u||_2^2 over all rows of level d */
+double or_residual_norm2_rows(const or_problem *p, int d, const double *f, const double *u) {
+  if (bad_depth(p, d)) return -1.0;
+  const level_t *L = &p->lev[d];
+  double acc = 0.0;
+#pragma omp parallel for reduction(+ : acc) schedule(static)
+  for (int64_t g = 0; g < L->n; ++g) {
+    int32_t cols[8];
+    double vals[8];
+    int i, j, k;
+    decode(L, g, &i, &j, &k);
+    int m = assemble_row(p, L, i, j, k, cols, vals);
+    double s = 0.0;
+    for (int e = 0; e < m; ++e) s += vals[e] * u[cols[e]];
+    double r = f[g] - s;
+    acc += r * r;
+  }
+  return acc;
+}
+
+/* z = M^{-1} r on the listed columns (index j*nx+i) only: textbook Thomas on
+ * the tridiagonal block of each column, read out of its assembled rows. */
+int or_line_solve_columns(const or_problem *p, int d, int64_t ncols, const int64_t *colidx,
+                          const double *r, double *z) {
+  if (bad_depth(p, d)) return -1;
+  const level_t *L = &p->lev[d];
+  int nz = L->nz;
+#pragma omp parallel
+  {
+    double *cp = (double *)malloc((size_t)nz * sizeof(double));
+    double *dp = (double *)malloc((size_t)nz * sizeof(double));
+#pragma omp for schedule(static)
+    for (int64_t q = 0; q < ncols; ++q) {
+      int64_t c = colidx[q];
+      int i = (int)(c % L->nx), j = (int)(c / L->nx);
+      int64_t g0 = c * nz;
+      for (int k = 0; k < nz; ++k) {
+        int32_t cols[8];
+        double vals[8];
+        int m = assemble_row(p, L, i, j, k, cols, vals);
+        int64_t g = g0 + k;
+        double a = 0.0, b = 0.0, cc = 0.0;
+        for (int e = 0; e < m; ++e) {
+          if (cols[e] == g - 1) a = vals[e];
+          else if (cols[e] == g) b = vals[e];
+          else if (cols[e] == g + 1) cc = vals[e];
+        }
+        if (k == 0) {
+          cp[0] = cc / b;
+          dp[0] = r[g] / b;
+        } else {
+          double piv = b - a * cp[k - 1];
+          cp[k] = cc / piv;
+          dp[k] = (r[g] - a * dp[k - 1]) / piv;
+        }
+      }
+      z[g0 + nz - 1] = dp[nz - 1];
+      for (int k = nz - 2; k >= 0; --k) z[g0 + k] = dp[k] - cp[k] * z[g0 + k + 1];
+    }
+    free(cp);
+    free(dp);
+  }
+  return 0;
 }

@@ -30,6 +30,11 @@ typedef struct or_problem or_problem;
 or_problem *or_create(int nx, int ny, int nz, int nlevels, int bc_h, int bc_v,
                       double kv, double sigma, const double *zfaces,
                       const double *kh, double rho, int ncoarse);
+/* The same hierarchy without CSR matrices (only the row-wise functions and the
+ * transfers work on it). */
+or_problem *or_create_matfree(int nx, int ny, int nz, int nlevels, int bc_h, int bc_v,
+                              double kv, double sigma, const double *zfaces,
+                              const double *kh, double rho, int ncoarse);
 void or_destroy(or_problem *p);
 const char *or_last_error(void);
 
@@ -55,6 +60,13 @@ int or_mg_solve(or_problem *p, const double *f, double *u, double rtol, int maxi
                 int *iters, double *history);
 int or_pcg_solve(or_problem *p, const double *f, double *u, double rtol, int maxit,
                  int *iters, double *history, double *relres_true);
+
+/* Row-wise forms (no stored matrix). */
+int or_apply_rows(const or_problem *p, int depth, int64_t nrows, const int64_t *rows,
+                  const double *x, double *y);
+double or_residual_norm2_rows(const or_problem *p, int depth, const double *f, const double *u);
+int or_line_solve_columns(const or_problem *p, int depth, int64_t ncols, const int64_t *cols,
+                          const double *r, double *z);
 
 double or_dot(int64_t n, const double *x, const double *y);
 int or_num_threads(void);

@@ -1,0 +1,301 @@
+"""Python binding of libgmg.so, the gfx950 tensor-product multigrid / line-CG library.
+
+Argument marshalling only: every step of the solvers runs in the HIP kernels
+behind the C ABI declared in include/gmg.h.  The functions keep the C names
+(gmg_setup, spmv, line_solve, line_smooth, gmg_residual, gmg_restrict_smooth,
+gmg_prolongate, gmg_vcycle, gmg_solve, pcg_solve, ...); fields are torch CUDA
+tensors in the library layout and the current torch stream is passed down.
+
+There is no fallback: importing the package raises if the library is missing.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+from . import build as _build
+
+LIB_PATH = _build.LIB
+
+GMG_OK, GMG_EINVAL, GMG_ENOMEM, GMG_EHIP, GMG_ENOCONV, GMG_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
+GMG_F64, GMG_F32 = 0, 1
+
+EXPORTS = ("gmg_default_params", "gmg_setup", "gmg_destroy", "gmg_field_layout", "spmv",
+           "line_solve", "line_smooth", "gmg_residual", "gmg_restrict_smooth", "gmg_prolongate",
+           "gmg_vcycle", "gmg_solve", "pcg_solve", "gmg_timing_enable", "gmg_timing_read",
+           "gmg_last_error")
+
+# kernel ids of the timing facility (gmg_kernel in include/gmg.h)
+KERNELS = ("spmv", "residual", "line_solve", "smooth", "restrict_smooth", "prolongate",
+           "cg_spmv", "cg_tridiag", "reduce", "aux")
+
+
+class GmgError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"status {status}: {message}")
+        self.status = status
+
+
+class GmgParams(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32), ("nlevels", C.c_int32),
+                ("bc_h", C.c_int32), ("bc_v", C.c_int32), ("kv", C.c_double),
+                ("sigma", C.c_double), ("zfaces", C.POINTER(C.c_double)),
+                ("kh", C.POINTER(C.c_double)), ("rho", C.c_double), ("ncoarse", C.c_int32),
+                ("prec_precond", C.c_int32)]
+
+
+def canonical_to_xcontig(a, nx, ny, nz, ldx):
+    """(j*nx+i)*nz+k host order -> the library layout (j*nz+k)*ldx+i, padding zeroed."""
+    a = np.asarray(a)
+    v = a.reshape(ny, nx, nz).transpose(0, 2, 1)
+    out = np.zeros((ny, nz, ldx), dtype=a.dtype)
+    out[:, :, :nx] = v
+    return out.reshape(-1)
+
+
+def xcontig_to_canonical(a, nx, ny, nz, ldx):
+    v = np.asarray(a).reshape(ny, nz, ldx)[:, :, :nx]
+    return np.ascontiguousarray(v.transpose(0, 2, 1)).reshape(-1)
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with paper_1402_3545_amd/build.py "
+                          "(or __graft_entry__.build()); there is no CPU fallback")
+    lib = C.CDLL(LIB_PATH)
+    vp, i32, i64p, dbl, dblp = C.c_void_p, C.c_int, C.POINTER(C.c_int64), C.c_double, \
+        C.POINTER(C.c_double)
+    intp = C.POINTER(C.c_int)
+    sig = {
+        "gmg_default_params": (None, [C.POINTER(GmgParams)]),
+        "gmg_setup": (i32, [C.POINTER(GmgParams), vp, C.POINTER(vp)]),
+        "gmg_destroy": (i32, [vp]),
+        "gmg_field_layout": (i32, [vp, i32, i64p, i64p]),
+        "spmv": (i32, [vp, i32, i32, vp, vp, vp]),
+        "line_solve": (i32, [vp, i32, i32, vp, vp, vp]),
+        "line_smooth": (i32, [vp, i32, i32, vp, vp, i32, dbl, vp]),
+        "gmg_residual": (i32, [vp, i32, i32, vp, vp, vp, dblp, vp]),
+        "gmg_restrict_smooth": (i32, [vp, i32, i32, vp, vp, vp, dbl, vp]),
+        "gmg_prolongate": (i32, [vp, i32, i32, vp, vp, vp]),
+        "gmg_vcycle": (i32, [vp, vp, vp, vp]),
+        "gmg_solve": (i32, [vp, vp, vp, dbl, i32, intp, dblp, dblp, vp]),
+        "pcg_solve": (i32, [vp, vp, vp, dbl, i32, i32, intp, dblp, dblp, vp]),
+        "gmg_timing_enable": (i32, [vp, i32]),
+        "gmg_timing_read": (i32, [vp, i32, i32, i32, i64p, dblp]),
+        "gmg_last_error": (C.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    return lib
+
+
+_lib = _load()
+
+
+def _check(status: int) -> int:
+    if status < 0:
+        raise GmgError(status, _lib.gmg_last_error().decode())
+    return status
+
+
+def _stream(stream=None):
+    if stream is not None:
+        return C.c_void_p(int(stream))
+    import torch
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr())
+
+
+def _prec(t) -> int:
+    import torch
+    if t.dtype == torch.float64:
+        return GMG_F64
+    if t.dtype == torch.float32:
+        return GMG_F32
+    raise TypeError(f"fields must be float64 or float32, got {t.dtype}")
+
+
+class GmgContext:
+    """Owns a gmg_ctx: the level hierarchy for one operator on the current device."""
+
+    def __init__(self, nx, ny, nz, nlevels=1, kv=1.0, sigma=1.0, zfaces=None, kh=None, bc_v=0,
+                 rho=2.0 / 3.0, ncoarse=2, prec_precond=GMG_F64, bc_h=0, stream=None):
+        p = GmgParams()
+        _lib.gmg_default_params(C.byref(p))
+        p.nx, p.ny, p.nz, p.nlevels = int(nx), int(ny), int(nz), int(nlevels)
+        p.bc_h, p.bc_v = int(bc_h), int(bc_v)
+        p.kv, p.sigma, p.rho, p.ncoarse = float(kv), float(sigma), float(rho), int(ncoarse)
+        p.prec_precond = int(prec_precond)
+        keep = []
+        if zfaces is not None:
+            z = np.ascontiguousarray(zfaces, dtype=np.float64)
+            if z.size != nz + 1:
+                raise ValueError("zfaces needs nz+1 entries")
+            keep.append(z)
+            p.zfaces = z.ctypes.data_as(C.POINTER(C.c_double))
+        if kh is not None:
+            k = np.ascontiguousarray(kh, dtype=np.float64)
+            if k.size != nx * ny:
+                raise ValueError("kh needs nx*ny entries")
+            keep.append(k)
+            p.kh = k.ctypes.data_as(C.POINTER(C.c_double))
+        h = C.c_void_p()
+        _check(_lib.gmg_setup(C.byref(p), _stream(stream), C.byref(h)))
+        self._h = h
+        self.nx, self.ny, self.nz, self.nlevels = p.nx, p.ny, p.nz, p.nlevels
+        self.prec_precond = p.prec_precond
+        self.rho = p.rho
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _lib.gmg_destroy(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def shape(self, level=0):
+        return self.nx >> level, self.ny >> level, self.nz
+
+    def layout(self, level=0):
+        ldx, elems = C.c_int64(), C.c_int64()
+        _check(_lib.gmg_field_layout(self._h, int(level), C.byref(ldx), C.byref(elems)))
+        return ldx.value, elems.value
+
+    # -- host <-> device layout (plain data movement) -------------------------
+    def empty(self, level=0, dtype=None):
+        import torch
+        dtype = dtype or torch.float64
+        _, elems = self.layout(level)
+        return torch.zeros(elems, dtype=dtype, device="cuda")
+
+    def to_device(self, canonical, level=0, dtype=None):
+        import torch
+        nx, ny, nz = self.shape(level)
+        ldx, _ = self.layout(level)
+        a = canonical_to_xcontig(np.asarray(canonical, dtype=np.float64), nx, ny, nz, ldx)
+        t = torch.from_numpy(a)
+        if dtype is not None:
+            t = t.to(dtype)
+        return t.cuda()
+
+    def from_device(self, t, level=0):
+        nx, ny, nz = self.shape(level)
+        ldx, _ = self.layout(level)
+        return xcontig_to_canonical(t.detach().cpu().double().numpy(), nx, ny, nz, ldx)
+
+
+def gmg_setup(**kw) -> GmgContext:
+    return GmgContext(**kw)
+
+
+def gmg_destroy(ctx: GmgContext) -> None:
+    ctx.close()
+
+
+def gmg_field_layout(ctx: GmgContext, level=0):
+    return ctx.layout(level)
+
+
+def spmv(ctx, level, x, y, stream=None):
+    _check(_lib.spmv(ctx.handle, int(level), _prec(x), _ptr(x), _ptr(y), _stream(stream)))
+
+
+def line_solve(ctx, level, r, z, stream=None):
+    _check(_lib.line_solve(ctx.handle, int(level), _prec(r), _ptr(r), _ptr(z), _stream(stream)))
+
+
+def line_smooth(ctx, level, f, u, nsweeps=1, rho=None, stream=None):
+    rho = ctx.rho if rho is None else float(rho)
+    _check(_lib.line_smooth(ctx.handle, int(level), _prec(u), _ptr(f), _ptr(u), int(nsweeps), rho,
+                            _stream(stream)))
+
+
+def gmg_residual(ctx, level, f, u, r, norm=False, stream=None):
+    out = C.c_double()
+    _check(_lib.gmg_residual(ctx.handle, int(level), _prec(u), _ptr(f), _ptr(u), _ptr(r),
+                             C.byref(out) if norm else None, _stream(stream)))
+    return out.value if norm else None
+
+
+def gmg_restrict_smooth(ctx, level, rf, fc, uc, rho=None, stream=None):
+    rho = ctx.rho if rho is None else float(rho)
+    _check(_lib.gmg_restrict_smooth(ctx.handle, int(level), _prec(rf), _ptr(rf), _ptr(fc),
+                                    _ptr(uc), rho, _stream(stream)))
+
+
+def gmg_prolongate(ctx, level, uc, uf, stream=None):
+    _check(_lib.gmg_prolongate(ctx.handle, int(level), _prec(uc), _ptr(uc), _ptr(uf),
+                               _stream(stream)))
+
+
+def gmg_vcycle(ctx, f, u, stream=None):
+    _check(_lib.gmg_vcycle(ctx.handle, _ptr(f), _ptr(u), _stream(stream)))
+
+
+def gmg_solve(ctx, f, u, rtol=1e-8, maxit=100, stream=None, check=True):
+    """Returns (iters, relres, history, status)."""
+    it, rel = C.c_int(), C.c_double()
+    hist = np.zeros(maxit + 1)
+    st = _lib.gmg_solve(ctx.handle, _ptr(f), _ptr(u), float(rtol), int(maxit), C.byref(it),
+                        C.byref(rel), hist.ctypes.data_as(C.POINTER(C.c_double)), _stream(stream))
+    if check and st != GMG_ENOCONV:
+        _check(st)
+    return it.value, rel.value, hist[: it.value + 1].copy(), st
+
+
+def pcg_solve(ctx, f, u, rtol=1e-8, maxit=1000, precond=0, stream=None, check=True):
+    """Returns (iters, true relres, recursive history, status)."""
+    it, rel = C.c_int(), C.c_double()
+    hist = np.zeros(maxit + 1)
+    st = _lib.pcg_solve(ctx.handle, _ptr(f), _ptr(u), float(rtol), int(maxit), int(precond),
+                        C.byref(it), C.byref(rel), hist.ctypes.data_as(C.POINTER(C.c_double)),
+                        _stream(stream))
+    if check and st != GMG_ENOCONV:
+        _check(st)
+    return it.value, rel.value, hist[: it.value + 1].copy(), st
+
+
+def gmg_timing_enable(ctx, enable=True):
+    _check(_lib.gmg_timing_enable(ctx.handle, 1 if enable else 0))
+
+
+def gmg_timing_read(ctx, kernel, level=-1, prec=GMG_F64):
+    """(launch count, total ms) of one kernel kind since timing was enabled."""
+    if isinstance(kernel, str):
+        kernel = KERNELS.index(kernel)
+    n, ms = C.c_int64(), C.c_double()
+    _check(_lib.gmg_timing_read(ctx.handle, int(kernel), int(level), int(prec), C.byref(n),
+                                C.byref(ms)))
+    return n.value, ms.value
+
+
+def gmg_timing_table(ctx):
+    """{(kernel, level, prec): (count, ms)} for every kernel that ran."""
+    out = {}
+    for kid, name in enumerate(KERNELS):
+        for lvl in range(ctx.nlevels):
+            for prec in (GMG_F64, GMG_F32):
+                n, ms = gmg_timing_read(ctx, kid, lvl, prec)
+                if n:
+                    out[(name, lvl, "f64" if prec == GMG_F64 else "f32")] = (n, ms)
+    return out
+
+
+def gmg_last_error() -> str:
+    return _lib.gmg_last_error().decode()

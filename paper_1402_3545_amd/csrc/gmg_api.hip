@@ -1,0 +1,781 @@
+// C ABI of the gfx950 multigrid / line-CG library: context setup (vertical
+// profiles, per-level face couplings, level hierarchy), the single-operation
+// entry points and the solver drivers.  Every step of the path runs in the
+// kernels of kernels.hip; this file only validates, allocates and enqueues.
+
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <new>
+
+#include "gmg_internal.h"
+
+using gmg::CgState;
+using gmg::LevelBuf;
+using gmg::Lvl;
+using gmg::Stencil;
+
+namespace {
+
+thread_local char g_err[512];
+
+int fail(int code, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+int fail(int code, const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof(g_err), fmt, ap);
+  va_end(ap);
+  return code;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+  return fail(GMG_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define HIP_TRY(expr)                                   \
+  do {                                                  \
+    hipError_t e_ = (expr);                             \
+    if (e_ != hipSuccess) return hip_fail(e_, #expr);   \
+  } while (0)
+
+template <typename T>
+hipError_t dmalloc(T** p, size_t n) {
+  *p = nullptr;
+  return hipMalloc((void**)p, std::max<size_t>(n, 1) * sizeof(T));
+}
+
+template <typename T>
+void dfree(T*& p) {
+  if (p) (void)hipFree((void*)p);
+  p = nullptr;
+}
+
+int64_t round_up(int64_t a, int64_t m) { return (a + m - 1) / m * m; }
+
+hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+bool level_ok(const gmg_ctx* c, int level) { return c && level >= 0 && level < c->nlevels; }
+
+int validate(const gmg_params* p) {
+  if (!p) return fail(GMG_EINVAL, "params is NULL");
+  if (p->nlevels < 1 || p->nlevels > 20) return fail(GMG_EINVAL, "nlevels must be in [1, 20]");
+  if (p->nx < 2 || p->ny < 2) return fail(GMG_EINVAL, "nx, ny must be >= 2");
+  if (p->nz < 2) return fail(GMG_EINVAL, "nz must be >= 2");
+  if (p->nz > 128) return fail(GMG_EUNSUPPORTED, "nz > 128 is not supported (nz = %d)", p->nz);
+  const int64_t div = int64_t(1) << (p->nlevels - 1);
+  if (p->nx % div || p->ny % div || p->nx / div < 2 || p->ny / div < 2)
+    return fail(GMG_EINVAL,
+                "nx=%d, ny=%d must be divisible by 2^(nlevels-1)=%lld with >= 2 coarsest columns",
+                p->nx, p->ny, (long long)div);
+  if (p->bc_h != 0)
+    return fail(GMG_EUNSUPPORTED, "only doubly periodic horizontal boundaries (bc_h = 0)");
+  if (p->bc_v != 0 && p->bc_v != 1) return fail(GMG_EINVAL, "bc_v must be 0 or 1");
+  if (!(p->kv >= 0.0) || !isfinite(p->kv)) return fail(GMG_EINVAL, "kv must be finite, >= 0");
+  if (!(p->sigma > 0.0) || !isfinite(p->sigma)) return fail(GMG_EINVAL, "sigma must be > 0");
+  if (!(p->rho > 0.0) || !(p->rho <= 2.0)) return fail(GMG_EINVAL, "rho must be in (0, 2]");
+  if (p->ncoarse < 1) return fail(GMG_EINVAL, "ncoarse must be >= 1");
+  if (p->prec_precond != GMG_F64 && p->prec_precond != GMG_F32)
+    return fail(GMG_EINVAL, "prec_precond must be GMG_F64 or GMG_F32");
+  if (p->zfaces) {
+    if (!isfinite(p->zfaces[0])) return fail(GMG_EINVAL, "zfaces must be finite");
+    for (int k = 0; k < p->nz; ++k)
+      if (!(p->zfaces[k + 1] > p->zfaces[k]) || !isfinite(p->zfaces[k + 1]))
+        return fail(GMG_EINVAL, "zfaces must be finite and strictly increasing");
+  }
+  if (p->kh) {
+    const int64_t nc = (int64_t)p->nx * p->ny;
+    for (int64_t q = 0; q < nc; ++q)
+      if (!(p->kh[q] > 0.0) || !isfinite(p->kh[q]))
+        return fail(GMG_EINVAL, "kh must be finite and > 0 (column %lld)", (long long)q);
+  }
+  return GMG_OK;
+}
+
+template <typename T>
+int upload(T** dst, const std::vector<double>& src) {
+  std::vector<T> tmp(src.begin(), src.end());
+  HIP_TRY(dmalloc(dst, tmp.size()));
+  HIP_TRY(hipMemcpy(*dst, tmp.data(), tmp.size() * sizeof(T), hipMemcpyHostToDevice));
+  return GMG_OK;
+}
+
+}  // namespace
+
+namespace gmg {
+
+template <>
+Lvl<double> view<double>(const gmg_ctx* c, int d) {
+  const LevelBuf& L = c->lev[d];
+  return Lvl<double>{L.nx, L.ny, L.nz, L.ldx, L.cx64, L.cy64, L.sub64, L.sup64, L.dg64, c->dz64};
+}
+
+template <>
+Lvl<float> view<float>(const gmg_ctx* c, int d) {
+  const LevelBuf& L = c->lev[d];
+  return Lvl<float>{L.nx, L.ny, L.nz, L.ldx, L.cx32, L.cy32, L.sub32, L.sup32, L.dg32, c->dz32};
+}
+
+}  // namespace gmg
+
+extern "C" {
+
+const char* gmg_last_error(void) { return g_err; }
+
+void gmg_default_params(gmg_params* p) {
+  if (!p) return;
+  memset(p, 0, sizeof(*p));
+  p->nlevels = 1;
+  p->kv = 1.0;
+  p->sigma = 1.0;
+  p->rho = 2.0 / 3.0;
+  p->ncoarse = 2;
+  p->prec_precond = GMG_F64;
+}
+
+int gmg_destroy(gmg_ctx* c) {
+  if (!c) return GMG_OK;
+  for (LevelBuf& L : c->lev) {
+    dfree(L.cx64); dfree(L.cy64); dfree(L.sub64); dfree(L.sup64); dfree(L.dg64);
+    dfree(L.cx32); dfree(L.cy32); dfree(L.sub32); dfree(L.sup32); dfree(L.dg32);
+    if (L.u) (void)hipFree(L.u);
+    if (L.ualt) (void)hipFree(L.ualt);
+    if (L.f) (void)hipFree(L.f);
+    if (L.r) (void)hipFree(L.r);
+  }
+  dfree(c->dz64); dfree(c->dz32);
+  dfree(c->vr); dfree(c->vz); dfree(c->vp); dfree(c->vq); dfree(c->vt);
+  dfree(c->er32); dfree(c->eu32);
+  dfree(c->partials);
+  dfree(c->state);
+  dfree(c->dhist);
+  if (c->hstate) (void)hipHostFree(c->hstate);
+  if (c->hscal) (void)hipHostFree(c->hscal);
+  for (hipEvent_t e : c->evpool) (void)hipEventDestroy(e);
+  delete c;
+  return GMG_OK;
+}
+
+int gmg_setup(const gmg_params* p, void* stream, gmg_ctx** out) {
+  if (!out) return fail(GMG_EINVAL, "out is NULL");
+  *out = nullptr;
+  int st = validate(p);
+  if (st) return st;
+  gmg_ctx* c = new (std::nothrow) gmg_ctx();
+  if (!c) return fail(GMG_ENOMEM, "host allocation failed");
+  c->p = *p;
+  c->nlevels = p->nlevels;
+  const int nz = c->nz = p->nz;
+  c->esize = p->prec_precond == GMG_F32 ? 4 : 8;
+  c->zf.resize(nz + 1);
+  for (int k = 0; k <= nz; ++k)
+    c->zf[k] = p->zfaces ? p->zfaces[k] : ((double)k / nz) * ((double)k / nz);
+  c->p.zfaces = nullptr;
+  c->p.kh = nullptr;
+
+  // vertical profiles: layer thickness, face transmissibilities (Sec. 3.1: the
+  // vectors a, b, c, d are shared by every column and level)
+  std::vector<double> dz(nz), tf(nz + 1);
+  for (int k = 0; k < nz; ++k) dz[k] = c->zf[k + 1] - c->zf[k];
+  for (int k = 1; k < nz; ++k) {
+    const double lo = 0.5 * (c->zf[k - 1] + c->zf[k]);
+    const double hi = 0.5 * (c->zf[k] + c->zf[k + 1]);
+    tf[k] = p->kv / (hi - lo);
+  }
+  tf[0] = p->bc_v == 0 ? 2.0 * p->kv / dz[0] : 0.0;
+  tf[nz] = p->bc_v == 0 ? 2.0 * p->kv / dz[nz - 1] : 0.0;
+
+  auto cleanup = [&](int code) { gmg_destroy(c); return code; };
+  if ((st = upload(&c->dz64, dz)) || (st = upload(&c->dz32, dz))) return cleanup(st);
+
+  // per-level column coefficients: K of the finest level from the caller, the
+  // mean of the four children on coarser levels; harmonic face means
+  std::vector<double> K((size_t)p->nx * p->ny, 1.0);
+  if (p->kh) std::copy(p->kh, p->kh + K.size(), K.begin());
+  c->lev.resize(c->nlevels);
+  for (int d = 0; d < c->nlevels; ++d) {
+    LevelBuf& L = c->lev[d];
+    L.nx = p->nx >> d;
+    L.ny = p->ny >> d;
+    L.nz = nz;
+    L.ldx = round_up(L.nx, 32);
+    L.elems = (int64_t)L.ny * nz * L.ldx;
+    const double hx = 1.0 / L.nx, hy = 1.0 / L.ny;
+    L.area = hx * hy;
+    if (d > 0) {
+      const int fnx = c->lev[d - 1].nx;
+      std::vector<double> Kc((size_t)L.nx * L.ny);
+      for (int J = 0; J < L.ny; ++J)
+        for (int I = 0; I < L.nx; ++I) {
+          const double s = K[(size_t)(2 * J) * fnx + 2 * I] + K[(size_t)(2 * J) * fnx + 2 * I + 1] +
+                           K[(size_t)(2 * J + 1) * fnx + 2 * I] +
+                           K[(size_t)(2 * J + 1) * fnx + 2 * I + 1];
+          Kc[(size_t)J * L.nx + I] = 0.25 * s;
+        }
+      K.swap(Kc);
+    }
+    std::vector<double> cx(K.size()), cy(K.size());
+    for (int j = 0; j < L.ny; ++j)
+      for (int i = 0; i < L.nx; ++i) {
+        const double kc = K[(size_t)j * L.nx + i];
+        const double ke = K[(size_t)j * L.nx + (i + 1) % L.nx];
+        const double kn = K[(size_t)((j + 1) % L.ny) * L.nx + i];
+        cx[(size_t)j * L.nx + i] = (hy / hx) * 2.0 * kc * ke / (kc + ke);
+        cy[(size_t)j * L.nx + i] = (hx / hy) * 2.0 * kc * kn / (kc + kn);
+      }
+    std::vector<double> sub(nz), sup(nz), dg(nz);
+    for (int k = 0; k < nz; ++k) {
+      sub[k] = k > 0 ? -L.area * tf[k] : 0.0;
+      sup[k] = k < nz - 1 ? -L.area * tf[k + 1] : 0.0;
+      dg[k] = L.area * (p->sigma * dz[k] + tf[k] + tf[k + 1]);
+    }
+    if ((st = upload(&L.cx64, cx)) || (st = upload(&L.cy64, cy)) || (st = upload(&L.sub64, sub)) ||
+        (st = upload(&L.sup64, sup)) || (st = upload(&L.dg64, dg)) || (st = upload(&L.cx32, cx)) ||
+        (st = upload(&L.cy32, cy)) || (st = upload(&L.sub32, sub)) ||
+        (st = upload(&L.sup32, sup)) || (st = upload(&L.dg32, dg)))
+      return cleanup(st);
+    const size_t bytes = (size_t)L.elems * c->esize;
+    hipError_t e = hipSuccess;
+    if (d > 0) {
+      if ((e = hipMalloc(&L.u, bytes)) != hipSuccess || (e = hipMalloc(&L.f, bytes)) != hipSuccess)
+        return cleanup(fail(GMG_ENOMEM, "level %d fields: %s", d, hipGetErrorString(e)));
+    }
+    if ((e = hipMalloc(&L.ualt, bytes)) != hipSuccess || (e = hipMalloc(&L.r, bytes)) != hipSuccess)
+      return cleanup(fail(GMG_ENOMEM, "level %d fields: %s", d, hipGetErrorString(e)));
+  }
+  const int64_t n0 = c->lev[0].elems;
+  hipError_t e;
+  if ((e = dmalloc(&c->vr, n0)) || (e = dmalloc(&c->vz, n0)) || (e = dmalloc(&c->vp, n0)) ||
+      (e = dmalloc(&c->vq, n0)) || (e = dmalloc(&c->vt, n0)))
+    return cleanup(fail(GMG_ENOMEM, "solver vectors: %s", hipGetErrorString(e)));
+  if (p->prec_precond == GMG_F32) {
+    if ((e = dmalloc(&c->er32, n0)) || (e = dmalloc(&c->eu32, n0)))
+      return cleanup(fail(GMG_ENOMEM, "FP32 vectors: %s", hipGetErrorString(e)));
+  }
+  const LevelBuf& L0 = c->lev[0];
+  c->max_partials = 2 * std::max(gmg::stencil_blocks(L0.nx, L0.ny, nz),
+                                 gmg::line_blocks(L0.nx, L0.ny));
+  if ((e = dmalloc(&c->partials, c->max_partials + 8)) ||  // + scalar slots
+      (e = dmalloc(&c->state, 1)) ||
+      (e = hipHostMalloc((void**)&c->hstate, sizeof(CgState), hipHostMallocDefault)) ||
+      (e = hipHostMalloc((void**)&c->hscal, 8 * sizeof(double), hipHostMallocDefault)))
+    return cleanup(fail(GMG_ENOMEM, "scratch: %s", hipGetErrorString(e)));
+  // zero-fill the level fields once so that padding never holds NaN patterns
+  hipStream_t s = as_stream(stream);
+  for (int d = 0; d < c->nlevels; ++d) {
+    LevelBuf& L = c->lev[d];
+    for (void* q : {L.u, L.ualt, L.f, L.r})
+      if (q && (e = hipMemsetAsync(q, 0, (size_t)L.elems * c->esize, s)) != hipSuccess)
+        return cleanup(hip_fail(e, "hipMemsetAsync"));
+  }
+  for (double* q : {c->vr, c->vz, c->vp, c->vq, c->vt})
+    if ((e = hipMemsetAsync(q, 0, (size_t)n0 * 8, s)) != hipSuccess)
+      return cleanup(hip_fail(e, "hipMemsetAsync"));
+  for (float* q : {c->er32, c->eu32})
+    if (q && (e = hipMemsetAsync(q, 0, (size_t)n0 * 4, s)) != hipSuccess)
+      return cleanup(hip_fail(e, "hipMemsetAsync"));
+  if ((e = hipStreamSynchronize(s)) != hipSuccess) return cleanup(hip_fail(e, "setup sync"));
+  *out = c;
+  return GMG_OK;
+}
+
+int gmg_field_layout(const gmg_ctx* c, int level, int64_t* ldx, int64_t* elems) {
+  if (!level_ok(c, level)) return fail(GMG_EINVAL, "bad context or level %d", level);
+  if (ldx) *ldx = c->lev[level].ldx;
+  if (elems) *elems = c->lev[level].elems;
+  return GMG_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+int check_prec(int prec) {
+  if (prec != GMG_F64 && prec != GMG_F32) return fail(GMG_EINVAL, "prec must be 0 or 1");
+  return GMG_OK;
+}
+
+int check_ptrs(std::initializer_list<const void*> ps) {
+  for (const void* q : ps) {
+    if (!q) return fail(GMG_EINVAL, "NULL field pointer");
+    if (reinterpret_cast<uintptr_t>(q) % 16)
+      return fail(GMG_EINVAL, "field pointer not 16-byte aligned");
+  }
+  return GMG_OK;
+}
+
+template <typename T>
+constexpr int prec_of() {
+  return sizeof(T) == 8 ? GMG_F64 : GMG_F32;
+}
+
+hipEvent_t pool_event(gmg_ctx* c) {
+  if (c->evused == c->evpool.size()) {
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    c->evpool.push_back(e);
+  }
+  return c->evpool[c->evused++];
+}
+
+// Enqueue one kernel launch; while timing is on, bracket it by two events on
+// the launch stream.
+template <typename F>
+hipError_t timed(gmg_ctx* c, int kind, int level, int prec, hipStream_t s, F&& launch) {
+  if (!c->timing) return launch();
+  hipEvent_t a = pool_event(c), b = pool_event(c);
+  if (!a || !b) return hipErrorOutOfMemory;
+  hipError_t e = hipEventRecord(a, s);
+  if (e != hipSuccess) return e;
+  if ((e = launch()) != hipSuccess) return e;
+  if ((e = hipEventRecord(b, s)) != hipSuccess) return e;
+  c->pending.push_back({kind, level, prec, a, b});
+  return hipSuccess;
+}
+
+constexpr int kMaxLevels = 20;
+
+size_t tslot(int kind, int level, int prec) {
+  return ((size_t)kind * kMaxLevels + level) * 2 + prec;
+}
+
+int drain_timing(gmg_ctx* c) {
+  for (const gmg_timed_launch& t : c->pending) {
+    HIP_TRY(hipEventSynchronize(t.b));
+    float ms = 0.0f;
+    HIP_TRY(hipEventElapsedTime(&ms, t.a, t.b));
+    const size_t q = tslot(t.kind, t.level, t.prec);
+    c->tcount[q] += 1;
+    c->tms[q] += ms;
+  }
+  c->pending.clear();
+  c->evused = 0;
+  return GMG_OK;
+}
+
+// nsweeps smoothing steps on level d with the field pair (cur, other); the
+// buffer holding the result goes to *result.
+template <typename T>
+hipError_t smooth_steps(gmg_ctx* c, int d, const T* f, T* cur, T* other, int n, T rho,
+                        hipStream_t s, T** result) {
+  const Lvl<T> L = gmg::view<T>(c, d);
+  for (int q = 0; q < n; ++q) {
+    hipError_t e = timed(c, GMG_K_SMOOTH, d, prec_of<T>(), s,
+                         [&] { return gmg::launch_smooth<T>(L, f, cur, other, rho, s); });
+    if (e != hipSuccess) return e;
+    std::swap(cur, other);
+  }
+  *result = cur;
+  return hipSuccess;
+}
+
+// One V(1,1) cycle of Algorithm 1 in precision T on the caller's (f0, u0).
+template <typename T>
+int vcycle_impl(gmg_ctx* c, const T* f0, T* u0, hipStream_t s) {
+  const int L = c->nlevels;
+  const int P = prec_of<T>();
+  const T rho = (T)c->p.rho;
+  std::vector<T*> cur(L, nullptr);
+  std::vector<const T*> fl(L, nullptr);
+  fl[0] = f0;
+  for (int d = 1; d < L; ++d) fl[d] = static_cast<const T*>(c->lev[d].f);
+  if (L == 1) {
+    T* res = nullptr;
+    HIP_TRY(smooth_steps<T>(c, 0, f0, u0, static_cast<T*>(c->lev[0].ualt), c->p.ncoarse, rho, s,
+                            &res));
+    if (res != u0)
+      HIP_TRY(hipMemcpyAsync(u0, res, (size_t)c->lev[0].elems * sizeof(T),
+                             hipMemcpyDeviceToDevice, s));
+    return GMG_OK;
+  }
+  // descend: pre-smoothing (Smooth on the finest level, ResSmooth below) and
+  // the residual that the next level restricts
+  for (int d = 0; d < L; ++d) {
+    const Lvl<T> V = gmg::view<T>(c, d);
+    LevelBuf& B = c->lev[d];
+    if (d == 0) {
+      HIP_TRY(timed(c, GMG_K_SMOOTH, 0, P, s, [&] {
+        return gmg::launch_smooth<T>(V, f0, u0, static_cast<T*>(B.ualt), rho, s);
+      }));
+      cur[0] = static_cast<T*>(B.ualt);
+    } else {
+      const Lvl<T> F = gmg::view<T>(c, d - 1);
+      const T* rf = static_cast<const T*>(c->lev[d - 1].r);
+      HIP_TRY(timed(c, GMG_K_RESTRICT_SMOOTH, d, P, s, [&] {
+        return gmg::launch_restrict_smooth<T>(V, F, rf, static_cast<T*>(B.f),
+                                              static_cast<T*>(B.u), rho, s);
+      }));
+      cur[d] = static_cast<T*>(B.u);
+    }
+    if (d == L - 1) {
+      T* other = cur[d] == B.u ? static_cast<T*>(B.ualt) : static_cast<T*>(B.u);
+      HIP_TRY(smooth_steps<T>(c, d, fl[d], cur[d], other, c->p.ncoarse - 1, rho, s, &cur[d]));
+    } else {
+      HIP_TRY(timed(c, GMG_K_RESIDUAL, d, P, s, [&] {
+        return gmg::launch_stencil<T>(V, Stencil::RESIDUAL, cur[d], fl[d], static_cast<T*>(B.r),
+                                      nullptr, nullptr, nullptr, s);
+      }));
+    }
+  }
+  // ascend: add the prolongated correction, post-smooth
+  for (int d = L - 2; d >= 0; --d) {
+    const Lvl<T> V = gmg::view<T>(c, d);
+    const Lvl<T> C = gmg::view<T>(c, d + 1);
+    HIP_TRY(timed(c, GMG_K_PROLONGATE, d + 1, P, s,
+                  [&] { return gmg::launch_prolongate<T>(C, V, cur[d + 1], cur[d], s); }));
+    T* other = (d == 0) ? u0
+                        : (cur[d] == c->lev[d].u ? static_cast<T*>(c->lev[d].ualt)
+                                                 : static_cast<T*>(c->lev[d].u));
+    HIP_TRY(timed(c, GMG_K_SMOOTH, d, P, s,
+                  [&] { return gmg::launch_smooth<T>(V, fl[d], cur[d], other, rho, s); }));
+    cur[d] = other;
+  }
+  return GMG_OK;
+}
+
+template <typename T>
+int line_smooth_t(gmg_ctx* c, int level, const T* f, T* u, int nsweeps, T rho, hipStream_t s) {
+  // ping-pong through a context buffer of the same precision and level
+  T* tmp = nullptr;
+  const LevelBuf& B = c->lev[level];
+  const bool own = (c->esize == (int)sizeof(T));
+  if (own)
+    tmp = static_cast<T*>(B.ualt);
+  else
+    HIP_TRY(hipMallocAsync((void**)&tmp, (size_t)B.elems * sizeof(T), s));
+  T* res = nullptr;
+  HIP_TRY(smooth_steps<T>(c, level, f, u, tmp, nsweeps, rho, s, &res));
+  if (res != u)
+    HIP_TRY(hipMemcpyAsync(u, res, (size_t)B.elems * sizeof(T), hipMemcpyDeviceToDevice, s));
+  if (!own) HIP_TRY(hipFreeAsync(tmp, s));
+  return GMG_OK;
+}
+
+// r = f - A u on level 0 with ||r||^2 into *out (host), synchronising.  With
+// rdown the residual is also written as FP32.
+template <typename T>
+int residual_norm2(gmg_ctx* c, const T* f, const T* u, T* r, float* rdown, double* out,
+                   hipStream_t s) {
+  const Lvl<T> V = gmg::view<T>(c, 0);
+  int64_t nb = 0;
+  double* dst = c->partials + c->max_partials;
+  HIP_TRY(timed(c, GMG_K_RESIDUAL, 0, prec_of<T>(), s, [&] {
+    return gmg::launch_stencil<T>(
+        V, rdown ? Stencil::RESIDUAL_NORM_DOWN : Stencil::RESIDUAL_NORM, u, f, r, rdown,
+        c->partials, &nb, s);
+  }));
+  HIP_TRY(timed(c, GMG_K_REDUCE, 0, GMG_F64, s,
+                [&] { return gmg::launch_reduce(c->partials, nb, 1, dst, s); }));
+  HIP_TRY(hipMemcpyAsync(c->hscal, dst, sizeof(double), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  *out = c->hscal[0];
+  return GMG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int gmg_timing_enable(gmg_ctx* c, int enable) {
+  if (!c) return fail(GMG_EINVAL, "context is NULL");
+  if (enable) {
+    c->pending.clear();
+    c->evused = 0;
+    c->tcount.assign((size_t)GMG_K_COUNT * kMaxLevels * 2, 0);
+    c->tms.assign((size_t)GMG_K_COUNT * kMaxLevels * 2, 0.0);
+  }
+  c->timing = enable != 0;
+  return GMG_OK;
+}
+
+int gmg_timing_read(gmg_ctx* c, int kernel, int level, int prec, int64_t* count,
+                    double* total_ms) {
+  if (!c) return fail(GMG_EINVAL, "context is NULL");
+  if (kernel < 0 || kernel >= GMG_K_COUNT) return fail(GMG_EINVAL, "bad kernel id %d", kernel);
+  if (level < -1 || level >= c->nlevels) return fail(GMG_EINVAL, "bad level %d", level);
+  int st;
+  if ((st = check_prec(prec))) return st;
+  if (c->tcount.empty()) {
+    if (count) *count = 0;
+    if (total_ms) *total_ms = 0.0;
+    return GMG_OK;
+  }
+  if ((st = drain_timing(c))) return st;
+  int64_t n = 0;
+  double ms = 0.0;
+  for (int d = (level < 0 ? 0 : level); d <= (level < 0 ? c->nlevels - 1 : level); ++d) {
+    n += c->tcount[tslot(kernel, d, prec)];
+    ms += c->tms[tslot(kernel, d, prec)];
+  }
+  if (count) *count = n;
+  if (total_ms) *total_ms = ms;
+  return GMG_OK;
+}
+
+int spmv(gmg_ctx* c, int level, int prec, const void* x, void* y, void* stream) {
+  if (!level_ok(c, level)) return fail(GMG_EINVAL, "bad context or level %d", level);
+  int st;
+  if ((st = check_prec(prec)) || (st = check_ptrs({x, y}))) return st;
+  if (x == y) return fail(GMG_EINVAL, "spmv: x and y must not overlap");
+  hipStream_t s = as_stream(stream);
+  if (prec == GMG_F64)
+    HIP_TRY(timed(c, GMG_K_SPMV, level, prec, s, [&] {
+      return gmg::launch_stencil<double>(gmg::view<double>(c, level), Stencil::SPMV,
+                                         (const double*)x, nullptr, (double*)y, nullptr, nullptr,
+                                         nullptr, s);
+    }));
+  else
+    HIP_TRY(timed(c, GMG_K_SPMV, level, prec, s, [&] {
+      return gmg::launch_stencil<float>(gmg::view<float>(c, level), Stencil::SPMV,
+                                        (const float*)x, nullptr, (float*)y, nullptr, nullptr,
+                                        nullptr, s);
+    }));
+  return GMG_OK;
+}
+
+int line_solve(gmg_ctx* c, int level, int prec, const void* r, void* z, void* stream) {
+  if (!level_ok(c, level)) return fail(GMG_EINVAL, "bad context or level %d", level);
+  int st;
+  if ((st = check_prec(prec)) || (st = check_ptrs({r, z}))) return st;
+  hipStream_t s = as_stream(stream);
+  if (prec == GMG_F64)
+    HIP_TRY(timed(c, GMG_K_LINE_SOLVE, level, prec, s, [&] {
+      return gmg::launch_line_solve<double>(gmg::view<double>(c, level), (const double*)r,
+                                            (double*)z, s);
+    }));
+  else
+    HIP_TRY(timed(c, GMG_K_LINE_SOLVE, level, prec, s, [&] {
+      return gmg::launch_line_solve<float>(gmg::view<float>(c, level), (const float*)r,
+                                           (float*)z, s);
+    }));
+  return GMG_OK;
+}
+
+int line_smooth(gmg_ctx* c, int level, int prec, const void* f, void* u, int nsweeps, double rho,
+                void* stream) {
+  if (!level_ok(c, level)) return fail(GMG_EINVAL, "bad context or level %d", level);
+  int st;
+  if ((st = check_prec(prec)) || (st = check_ptrs({f, u}))) return st;
+  if (nsweeps < 0) return fail(GMG_EINVAL, "nsweeps must be >= 0");
+  if (!(rho > 0.0) || !(rho <= 2.0)) return fail(GMG_EINVAL, "rho must be in (0, 2]");
+  if (f == u) return fail(GMG_EINVAL, "f and u must not overlap");
+  hipStream_t s = as_stream(stream);
+  if (prec == GMG_F64)
+    return line_smooth_t<double>(c, level, (const double*)f, (double*)u, nsweeps, rho, s);
+  return line_smooth_t<float>(c, level, (const float*)f, (float*)u, nsweeps, (float)rho, s);
+}
+
+int gmg_residual(gmg_ctx* c, int level, int prec, const void* f, const void* u, void* r,
+                 double* norm2, void* stream) {
+  if (!level_ok(c, level)) return fail(GMG_EINVAL, "bad context or level %d", level);
+  int st;
+  if ((st = check_prec(prec)) || (st = check_ptrs({f, u, r}))) return st;
+  if (r == u || r == f) return fail(GMG_EINVAL, "r must not overlap f or u");
+  hipStream_t s = as_stream(stream);
+  int64_t nb = 0;
+  const Stencil mode = norm2 ? Stencil::RESIDUAL_NORM : Stencil::RESIDUAL;
+  if (prec == GMG_F64)
+    HIP_TRY(timed(c, GMG_K_RESIDUAL, level, prec, s, [&] {
+      return gmg::launch_stencil<double>(gmg::view<double>(c, level), mode, (const double*)u,
+                                         (const double*)f, (double*)r, nullptr, c->partials, &nb,
+                                         s);
+    }));
+  else
+    HIP_TRY(timed(c, GMG_K_RESIDUAL, level, prec, s, [&] {
+      return gmg::launch_stencil<float>(gmg::view<float>(c, level), mode, (const float*)u,
+                                        (const float*)f, (float*)r, nullptr, c->partials, &nb, s);
+    }));
+  if (norm2) {
+    double* dst = c->partials + c->max_partials;
+    HIP_TRY(timed(c, GMG_K_REDUCE, level, GMG_F64, s,
+                  [&] { return gmg::launch_reduce(c->partials, nb, 1, dst, s); }));
+    HIP_TRY(hipMemcpyAsync(c->hscal, dst, sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    *norm2 = c->hscal[0];
+  }
+  return GMG_OK;
+}
+
+int gmg_restrict_smooth(gmg_ctx* c, int level, int prec, const void* rf, void* fc, void* uc,
+                        double rho, void* stream) {
+  if (!c || level < 1 || level >= c->nlevels)
+    return fail(GMG_EINVAL, "restrict_smooth needs a coarse level in [1, nlevels)");
+  int st;
+  if ((st = check_prec(prec)) || (st = check_ptrs({rf, fc, uc}))) return st;
+  if (fc == uc) return fail(GMG_EINVAL, "fc and uc must differ");
+  hipStream_t s = as_stream(stream);
+  if (prec == GMG_F64)
+    HIP_TRY(timed(c, GMG_K_RESTRICT_SMOOTH, level, prec, s, [&] {
+      return gmg::launch_restrict_smooth<double>(gmg::view<double>(c, level),
+                                                 gmg::view<double>(c, level - 1),
+                                                 (const double*)rf, (double*)fc, (double*)uc, rho,
+                                                 s);
+    }));
+  else
+    HIP_TRY(timed(c, GMG_K_RESTRICT_SMOOTH, level, prec, s, [&] {
+      return gmg::launch_restrict_smooth<float>(gmg::view<float>(c, level),
+                                                gmg::view<float>(c, level - 1), (const float*)rf,
+                                                (float*)fc, (float*)uc, (float)rho, s);
+    }));
+  return GMG_OK;
+}
+
+int gmg_prolongate(gmg_ctx* c, int level, int prec, const void* uc, void* uf, void* stream) {
+  if (!c || level < 1 || level >= c->nlevels)
+    return fail(GMG_EINVAL, "prolongate needs a coarse level in [1, nlevels)");
+  int st;
+  if ((st = check_prec(prec)) || (st = check_ptrs({uc, uf}))) return st;
+  hipStream_t s = as_stream(stream);
+  if (prec == GMG_F64)
+    HIP_TRY(timed(c, GMG_K_PROLONGATE, level, prec, s, [&] {
+      return gmg::launch_prolongate<double>(gmg::view<double>(c, level),
+                                            gmg::view<double>(c, level - 1), (const double*)uc,
+                                            (double*)uf, s);
+    }));
+  else
+    HIP_TRY(timed(c, GMG_K_PROLONGATE, level, prec, s, [&] {
+      return gmg::launch_prolongate<float>(gmg::view<float>(c, level),
+                                           gmg::view<float>(c, level - 1), (const float*)uc,
+                                           (float*)uf, s);
+    }));
+  return GMG_OK;
+}
+
+int gmg_vcycle(gmg_ctx* c, const void* f, void* u, void* stream) {
+  if (!c) return fail(GMG_EINVAL, "context is NULL");
+  int st;
+  if ((st = check_ptrs({f, u}))) return st;
+  if (f == u) return fail(GMG_EINVAL, "f and u must not overlap");
+  hipStream_t s = as_stream(stream);
+  if (c->p.prec_precond == GMG_F64) return vcycle_impl<double>(c, (const double*)f, (double*)u, s);
+  return vcycle_impl<float>(c, (const float*)f, (float*)u, s);
+}
+
+int gmg_solve(gmg_ctx* c, const double* f, double* u, double rtol, int maxit, int* iters,
+              double* relres, double* history, void* stream) {
+  if (!c) return fail(GMG_EINVAL, "context is NULL");
+  int st;
+  if ((st = check_ptrs({f, u}))) return st;
+  if (!(rtol > 0.0)) return fail(GMG_EINVAL, "rtol must be > 0");
+  if (maxit < 0) return fail(GMG_EINVAL, "maxit must be >= 0");
+  if (f == u) return fail(GMG_EINVAL, "f and u must not overlap");
+  hipStream_t s = as_stream(stream);
+  const bool mixed = c->p.prec_precond == GMG_F32;
+  const int64_t n0 = c->lev[0].elems;
+  double rr0 = 0.0, rr = 0.0;
+  if ((st = residual_norm2<double>(c, f, u, c->vr, mixed ? c->er32 : nullptr, &rr0, s))) return st;
+  if (iters) *iters = 0;
+  if (relres) *relres = rr0 > 0.0 ? 1.0 : 0.0;
+  if (history) history[0] = 1.0;
+  if (!isfinite(rr0)) return fail(GMG_ENOCONV, "initial residual is not finite");
+  if (rr0 == 0.0) return GMG_OK;
+  const double r0 = sqrt(rr0);
+  for (int it = 1; it <= maxit; ++it) {
+    if (!mixed) {
+      if ((st = vcycle_impl<double>(c, f, u, s))) return st;
+      if ((st = residual_norm2<double>(c, f, u, c->vr, nullptr, &rr, s))) return st;
+    } else {
+      // FP64 iterative refinement: e = V32(r) from a zero guess, u += e, new
+      // FP64 residual (and its FP32 copy) in one pass
+      HIP_TRY(timed(c, GMG_K_AUX, 0, GMG_F32, s,
+                    [&] { return gmg::launch_fill<float>(c->eu32, n0, 0.0f, s); }));
+      if ((st = vcycle_impl<float>(c, c->er32, c->eu32, s))) return st;
+      HIP_TRY(timed(c, GMG_K_AUX, 0, GMG_F64, s,
+                    [&] { return gmg::launch_add_f32_to_f64(u, c->eu32, n0, s); }));
+      if ((st = residual_norm2<double>(c, f, u, c->vr, c->er32, &rr, s))) return st;
+    }
+    const double rel = sqrt(rr) / r0;
+    if (history) history[it] = rel;
+    if (iters) *iters = it;
+    if (relres) *relres = rel;
+    if (!isfinite(rel)) return fail(GMG_ENOCONV, "residual became non-finite at cycle %d", it);
+    if (rel < rtol) return GMG_OK;
+  }
+  return fail(GMG_ENOCONV, "no convergence to %g in %d cycles", rtol, maxit);
+}
+
+int pcg_solve(gmg_ctx* c, const double* f, double* u, double rtol, int maxit, int precond,
+              int* iters, double* relres, double* history, void* stream) {
+  if (!c) return fail(GMG_EINVAL, "context is NULL");
+  int st;
+  if ((st = check_ptrs({f, u}))) return st;
+  if (!(rtol > 0.0)) return fail(GMG_EINVAL, "rtol must be > 0");
+  if (maxit < 0) return fail(GMG_EINVAL, "maxit must be >= 0");
+  if (f == u) return fail(GMG_EINVAL, "f and u must not overlap");
+  if (precond != 0)
+    return fail(GMG_EUNSUPPORTED, "pcg_solve: precond=%d not implemented", precond);
+  hipStream_t s = as_stream(stream);
+  const Lvl<double> V = gmg::view<double>(c, 0);
+  const int64_t n0 = c->lev[0].elems;
+  if (c->dhist_len < maxit + 1) {
+    dfree(c->dhist);
+    c->dhist_len = 0;
+    HIP_TRY(dmalloc(&c->dhist, (size_t)maxit + 1));
+    c->dhist_len = maxit + 1;
+  }
+  // initial state: r = f - A u, z = M^-1 r, kappa = <r,z>, p = q = 0
+  CgState init{};
+  init.maxit = maxit;
+  init.thresh2 = rtol * rtol;  // scaled by ||r_0||^2 on the device
+  HIP_TRY(hipMemcpyAsync(c->state, &init, sizeof(CgState), hipMemcpyHostToDevice, s));
+  int64_t nb = 0;
+  HIP_TRY(timed(c, GMG_K_RESIDUAL, 0, GMG_F64, s, [&] {
+    return gmg::launch_stencil<double>(V, Stencil::RESIDUAL, u, f, c->vr, nullptr, nullptr,
+                                       nullptr, s);
+  }));
+  HIP_TRY(timed(c, GMG_K_CG_TRIDIAG, 0, GMG_F64, s, [&] {
+    return gmg::launch_cg_p2(V, c->vr, c->vr, c->vz, c->state, 1, c->partials, &nb, s);
+  }));
+  HIP_TRY(timed(c, GMG_K_REDUCE, 0, GMG_F64, s,
+                [&] { return gmg::launch_cg_fin2(c->state, c->partials, nb, 1, c->dhist, s); }));
+  HIP_TRY(timed(c, GMG_K_AUX, 0, GMG_F64, s,
+                [&] { return gmg::launch_fill<double>(c->vp, n0, 0.0, s); }));
+  HIP_TRY(timed(c, GMG_K_AUX, 0, GMG_F64, s,
+                [&] { return gmg::launch_fill<double>(c->vq, n0, 0.0, s); }));
+  // the host polls the device state only every `chunk` iterations; kernels of
+  // iterations after convergence return at once
+  int done_iters = 0;
+  int chunk = 4;
+  while (true) {
+    HIP_TRY(hipMemcpyAsync(c->hstate, c->state, sizeof(CgState), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (c->hstate->done || done_iters >= maxit) break;
+    const int nq = std::min(chunk, maxit - done_iters);
+    for (int q = 0; q < nq; ++q) {
+      int64_t nb1 = 0, nb2 = 0;
+      HIP_TRY(timed(c, GMG_K_CG_SPMV, 0, GMG_F64, s, [&] {
+        return gmg::launch_cg_p1(V, u, c->vp, c->vz, c->vq, c->state, c->partials, &nb1, s);
+      }));
+      HIP_TRY(timed(c, GMG_K_REDUCE, 0, GMG_F64, s,
+                    [&] { return gmg::launch_cg_fin1(c->state, c->partials, nb1, s); }));
+      HIP_TRY(timed(c, GMG_K_CG_TRIDIAG, 0, GMG_F64, s, [&] {
+        return gmg::launch_cg_p2(V, c->vr, c->vq, c->vz, c->state, 0, c->partials, &nb2, s);
+      }));
+      HIP_TRY(timed(c, GMG_K_REDUCE, 0, GMG_F64, s, [&] {
+        return gmg::launch_cg_fin2(c->state, c->partials, nb2, 0, c->dhist, s);
+      }));
+    }
+    done_iters += nq;
+    chunk = std::min(2 * chunk, 32);
+  }
+  HIP_TRY(timed(c, GMG_K_AUX, 0, GMG_F64, s,
+                [&] { return gmg::launch_cg_final_update(V, u, c->vp, c->state, s); }));
+  const CgState hs = *c->hstate;
+  if (history && hs.iter >= 0)
+    HIP_TRY(hipMemcpyAsync(history, c->dhist, (size_t)(hs.iter + 1) * sizeof(double),
+                           hipMemcpyDeviceToHost, s));
+  double rr = 0.0;
+  if ((st = residual_norm2<double>(c, f, u, c->vt, nullptr, &rr, s))) return st;
+  if (iters) *iters = hs.iter;
+  if (relres) *relres = hs.rr0 > 0.0 ? sqrt(rr / hs.rr0) : 0.0;
+  if (hs.rr0 == 0.0) return GMG_OK;
+  if (hs.status == 1 || (!hs.done && hs.iter >= maxit))
+    return fail(GMG_ENOCONV, "no convergence to %g in %d iterations", rtol, maxit);
+  if (hs.status >= 2)
+    return fail(GMG_ENOCONV, "CG breakdown or non-finite reduction at iteration %d", hs.iter);
+  return GMG_OK;
+}
+
+}  // extern "C"

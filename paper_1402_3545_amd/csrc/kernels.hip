@@ -1,0 +1,680 @@
+// gfx950 kernels of the tensor-product multigrid / line-preconditioned CG path.
+//
+// Paper: Mueller, Scheichl & Vainikko, arXiv:1402.3545.  Kernel names follow
+// Sec. 3.1 (SpMV, Tridiag, Smooth, Residual, ResSmooth, Prolongate).
+//
+// Layout: x-contiguous (Sec. 3.1): element (i,j,k) at (j*nz + k)*ldx + i, so a
+// wavefront reading 32 or 64 consecutive i touches whole 128-byte lines.
+//
+// Two kernel shapes:
+//  * stencil kernels (SpMV, Residual, the CG SpMV step, Prolongate): one thread
+//    per column segment of KSEG layers, vertical neighbours rolled through
+//    registers, horizontal neighbours loaded directly (they hit L1/L2).
+//  * line kernels (Tridiag, Smooth, ResSmooth): the tridiagonal system of each
+//    column is solved by two lanes of one wavefront.  Lane l < 32 eliminates
+//    upwards from the bottom layer, lane l + 32 downwards from the top layer;
+//    they meet in the middle, exchange their last elimination coefficients
+//    with one cross-lane swap, solve the 2x2 interface system and
+//    back-substitute outwards.  This is Gaussian elimination without pivoting
+//    in a twisted order (exact for the diagonally dominant column matrices);
+//    each lane keeps only ceil(nz/2) pairs (c', d') in registers, so the whole
+//    elimination stays on chip and the kernel streams each field once.
+//
+// Workgroup ids are remapped so that each of the 8 XCDs (each with its own L2)
+// works on a contiguous band of tiles: neighbouring tiles share halo rows.
+
+#include "gmg_internal.h"
+
+namespace gmg {
+
+namespace {
+
+constexpr int KSEG = 32;        // layers per thread in stencil kernels
+constexpr int SROWS = 4;        // rows (j) per stencil workgroup, 64 columns wide
+constexpr int LROWS = 4;        // rows (j) per line workgroup, 32 columns wide
+constexpr int NTHREADS = 256;
+
+__device__ __forceinline__ int xcd_remap(int b, int n) {
+  const int x = b & 7, q = n >> 3, r = n & 7;
+  return x * q + min(x, r) + (b >> 3);
+}
+
+template <typename T>
+struct Col {
+  int64_t base;              // index of (i, j, 0)
+  int64_t oe, ow, on, os;    // offsets to the four horizontal neighbours
+  T ce, cw, cn, cs, S;       // face couplings and their sum
+};
+
+template <typename T>
+__device__ __forceinline__ Col<T> load_col(const Lvl<T>& L, int i, int j) {
+  Col<T> c;
+  const int nx = L.nx, ny = L.ny;
+  const int ie = (i + 1 == nx) ? 0 : i + 1;
+  const int iw = (i == 0) ? nx - 1 : i - 1;
+  const int jn = (j + 1 == ny) ? 0 : j + 1;
+  const int js = (j == 0) ? ny - 1 : j - 1;
+  const int64_t row = (int64_t)j * nx;
+  c.ce = L.cx[row + i];
+  c.cw = L.cx[row + iw];
+  c.cn = L.cy[row + i];
+  c.cs = L.cy[(int64_t)js * nx + i];
+  c.S = c.ce + c.cw + c.cn + c.cs;
+  const int64_t jstride = (int64_t)L.nz * L.ldx;
+  c.base = (int64_t)j * jstride + i;
+  c.oe = ie - i;
+  c.ow = iw - i;
+  c.on = (int64_t)(jn - j) * jstride;
+  c.os = (int64_t)(js - j) * jstride;
+  return c;
+}
+
+template <typename T>
+__device__ __forceinline__ T hsum(const Col<T>& c, const T* __restrict__ x, int64_t o) {
+  return c.ce * x[o + c.oe] + c.cw * x[o + c.ow] + c.cn * x[o + c.on] + c.cs * x[o + c.os];
+}
+
+// Sum NC per-thread values over the workgroup; thread 0 stores them to
+// partials[blockIdx.x*NC + c].  Fixed order, so results are reproducible.
+template <int NC>
+__device__ __forceinline__ void block_partials(double (&v)[NC], double* __restrict__ partials) {
+  __shared__ double sm[NC][NTHREADS / 64];
+#pragma unroll
+  for (int c = 0; c < NC; ++c)
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v[c] += __shfl_xor(v[c], off);
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0)
+#pragma unroll
+    for (int c = 0; c < NC; ++c) sm[c][w] = v[c];
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const int nw = blockDim.x >> 6;
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      double s = 0.0;
+      for (int q = 0; q < nw; ++q) s += sm[c][q];
+      partials[(int64_t)blockIdx.x * NC + c] = s;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Stencil kernels: SpMV (y = Ax) and Residual (r = f - Ax, optional ||r||^2
+// and an FP32 copy of r for the mixed-precision refinement).
+// ---------------------------------------------------------------------------
+template <typename T, int MODE>
+__global__ __launch_bounds__(NTHREADS) void k_stencil(Lvl<T> L, const T* __restrict__ x,
+                                                      const T* __restrict__ f,
+                                                      T* __restrict__ y,
+                                                      float* __restrict__ ydown,
+                                                      double* __restrict__ partials, int nti,
+                                                      int ntj) {
+  const int b = xcd_remap(blockIdx.x, gridDim.x);
+  const int ti = b % nti;
+  const int r1 = b / nti;
+  const int tj = r1 % ntj;
+  const int kb = r1 / ntj;
+  const int i = ti * 64 + (threadIdx.x & 63);
+  const int j = tj * SROWS + (threadIdx.x >> 6);
+  double nrm[1] = {0.0};
+  if (i < L.nx && j < L.ny) {
+    const Col<T> c = load_col(L, i, j);
+    const int nz = L.nz;
+    const int k0 = kb * KSEG;
+    const int k1 = min(nz, k0 + KSEG);
+    const int64_t ldx = L.ldx;
+    int64_t o = c.base + (int64_t)k0 * ldx;
+    T um = (k0 > 0) ? x[o - ldx] : T(0);
+    T uc = x[o];
+#pragma unroll 4
+    for (int k = k0; k < k1; ++k, o += ldx) {
+      const T up = (k + 1 < nz) ? x[o + ldx] : T(0);
+      const T h = hsum(c, x, o);
+      const T dzk = L.dz[k];
+      const T au = (L.dg[k] + dzk * c.S) * uc - dzk * h + L.sub[k] * um + L.sup[k] * up;
+      if constexpr (MODE == (int)Stencil::SPMV) {
+        y[o] = au;
+      } else {
+        const T rr = f[o] - au;
+        y[o] = rr;
+        if constexpr (MODE >= (int)Stencil::RESIDUAL_NORM) nrm[0] += (double)rr * (double)rr;
+        if constexpr (MODE == (int)Stencil::RESIDUAL_NORM_DOWN) ydown[o] = (float)rr;
+      }
+      um = uc;
+      uc = up;
+    }
+  }
+  if constexpr (MODE >= (int)Stencil::RESIDUAL_NORM) block_partials<1>(nrm, partials);
+}
+
+// ---------------------------------------------------------------------------
+// Line kernels
+// ---------------------------------------------------------------------------
+enum LineMode { LINE_SOLVE = 0, LINE_SMOOTH = 1, LINE_RESTRICT_SMOOTH = 2, LINE_CG = 3 };
+
+template <typename T>
+struct LineArgs {
+  const T* a;         // SOLVE: r; SMOOTH: u_in; RESTRICT_SMOOTH: fine r; CG: q
+  const T* b;         // SMOOTH: f
+  T* rw;              // CG: r (updated in place)
+  T* o0;              // SOLVE: z; SMOOTH: u_out; RESTRICT_SMOOTH: coarse u; CG: z
+  T* o1;              // RESTRICT_SMOOTH: coarse f
+  T rho;
+  Lvl<T> F;           // RESTRICT_SMOOTH: the fine level
+  const CgState* st;  // CG
+  int init;           // CG: initial step (alpha = 0)
+  double* partials;   // CG: <r,r>, <r,z> per workgroup
+};
+
+template <typename T>
+struct Vec2;
+template <>
+struct Vec2<double> { using type = double2; };
+template <>
+struct Vec2<float> { using type = float2; };
+
+template <typename T, int HALF, int MODE>
+__global__ __launch_bounds__(NTHREADS) void k_line(Lvl<T> L, LineArgs<T> a, int nti, int ntj) {
+  if constexpr (MODE == LINE_CG) {
+    if (a.st->done) return;  // uniform: the solve has already stopped
+  }
+  const int b = xcd_remap(blockIdx.x, gridDim.x);
+  const int ti = b % nti;
+  const int tj = b / nti;
+  const int lane = threadIdx.x & 63;
+  const int half = lane >> 5;
+  const int i = ti * 32 + (lane & 31);
+  const int j = tj * LROWS + (threadIdx.x >> 6);
+  const bool active = (i < L.nx) && (j < L.ny);
+  // inactive lanes compute on a valid column and store nothing; they still
+  // take part in the cross-lane exchange
+  const Col<T> c = load_col(L, min(i, L.nx - 1), min(j, L.ny - 1));
+  const int nz = L.nz;
+  const int m = nz >> 1;
+  const int nown = half ? nz - m : m;
+  const int k0 = half ? nz - 1 : 0;
+  const int dir = half ? -1 : 1;
+  const int64_t ldx = L.ldx;
+  const int64_t sdir = half ? -ldx : ldx;
+
+  T alpha = T(0);
+  if constexpr (MODE == LINE_CG) alpha = a.init ? T(0) : (T)a.st->alpha;
+  double acc_rr = 0.0, acc_rz = 0.0;
+
+  // fine-level addressing for the restriction (coarse column (i,j) owns fine
+  // columns 2i, 2i+1 in rows 2j, 2j+1)
+  int64_t fbase = 0, fjs = 0;
+  if constexpr (MODE == LINE_RESTRICT_SMOOTH) {
+    const int ii = min(i, L.nx - 1), jj = min(j, L.ny - 1);
+    fjs = (int64_t)a.F.nz * a.F.ldx;
+    fbase = (int64_t)(2 * jj) * fjs + 2 * ii;
+  }
+
+  T cp[HALF], dp[HALF];
+  T cprev = T(0), dprev = T(0);
+  T uprv = T(0), ucur = T(0);
+  if constexpr (MODE == LINE_SMOOTH) ucur = a.a[c.base + (int64_t)k0 * ldx];
+
+#pragma unroll
+  for (int s = 0; s < HALF; ++s) {
+    if (s < nown) {
+      const int k = k0 + dir * s;
+      const int64_t o = c.base + (int64_t)k * ldx;
+      const T sub = L.sub[k], sup = L.sup[k], dzk = L.dz[k];
+      const T cpv = half ? sup : sub;  // coupling to the previously eliminated row
+      const T cnx = half ? sub : sup;  // coupling to the next row in this lane's order
+      const T diag = L.dg[k] + dzk * c.S;
+      T rhs;
+      if constexpr (MODE == LINE_SOLVE) {
+        rhs = a.a[o];
+      } else if constexpr (MODE == LINE_SMOOTH) {
+        const T unxt = a.a[o + sdir];
+        const T au = diag * ucur - dzk * hsum(c, a.a, o) + cpv * uprv + cnx * unxt;
+        rhs = a.b[o] - au;
+        uprv = ucur;
+        ucur = unxt;
+      } else if constexpr (MODE == LINE_RESTRICT_SMOOTH) {
+        using V2 = typename Vec2<T>::type;
+        const int64_t fo = fbase + (int64_t)k * a.F.ldx;
+        const V2 lo = *reinterpret_cast<const V2*>(a.a + fo);
+        const V2 hi = *reinterpret_cast<const V2*>(a.a + fo + fjs);
+        rhs = lo.x + lo.y + hi.x + hi.y;
+        if (active) a.o1[o] = rhs;
+      } else {  // LINE_CG
+        rhs = a.rw[o] - alpha * a.a[o];
+        if (active) {
+          a.rw[o] = rhs;
+          acc_rr += (double)rhs * (double)rhs;
+        }
+      }
+      const T piv = diag - cpv * cprev;
+      const T inv = T(1) / piv;
+      cprev = cnx * inv;
+      dprev = (rhs - cpv * dprev) * inv;
+      cp[s] = cprev;
+      dp[s] = dprev;
+    }
+  }
+
+  // interface between the two halves: lane's last row x_a = d_a - c_a x_b,
+  // partner's last row x_b = d_b - c_b x_a
+  const T cq = __shfl_xor(cprev, 32);
+  const T dq = __shfl_xor(dprev, 32);
+  T x = (dprev - cprev * dq) / (T(1) - cprev * cq);
+
+#pragma unroll
+  for (int s = HALF - 1; s >= 0; --s) {
+    if (s < nown) {
+      if (s < nown - 1) x = dp[s] - cp[s] * x;
+      const int k = k0 + dir * s;
+      const int64_t o = c.base + (int64_t)k * ldx;
+      if (active) {
+        if constexpr (MODE == LINE_SOLVE) {
+          a.o0[o] = x;
+        } else if constexpr (MODE == LINE_SMOOTH) {
+          a.o0[o] = a.a[o] + a.rho * x;
+        } else if constexpr (MODE == LINE_RESTRICT_SMOOTH) {
+          a.o0[o] = a.rho * x;
+        } else {
+          a.o0[o] = x;
+          acc_rz += (double)a.rw[o] * (double)x;
+        }
+      }
+    }
+  }
+  if constexpr (MODE == LINE_CG) {
+    double v[2] = {acc_rr, acc_rz};
+    block_partials<2>(v, a.partials);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Prolongate: uf += P uc (cell-centred bilinear, 9/3/3/1 over 16, periodic)
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(NTHREADS) void k_prolongate(Lvl<T> C, Lvl<T> F,
+                                                         const T* __restrict__ uc,
+                                                         T* __restrict__ uf, int nti, int ntj) {
+  const int b = xcd_remap(blockIdx.x, gridDim.x);
+  const int ti = b % nti;
+  const int r1 = b / nti;
+  const int tj = r1 % ntj;
+  const int kb = r1 / ntj;
+  const int i = ti * 64 + (threadIdx.x & 63);
+  const int j = tj * SROWS + (threadIdx.x >> 6);
+  if (i >= F.nx || j >= F.ny) return;
+  const int I = i >> 1, J = j >> 1;
+  int I2 = I + ((i & 1) ? 1 : -1);
+  int J2 = J + ((j & 1) ? 1 : -1);
+  I2 = (I2 < 0) ? C.nx - 1 : (I2 == C.nx ? 0 : I2);
+  J2 = (J2 < 0) ? C.ny - 1 : (J2 == C.ny ? 0 : J2);
+  const int64_t cjs = (int64_t)C.nz * C.ldx;
+  const int64_t c00 = (int64_t)J * cjs + I, c10 = (int64_t)J * cjs + I2;
+  const int64_t c01 = (int64_t)J2 * cjs + I, c11 = (int64_t)J2 * cjs + I2;
+  const int64_t fb = (int64_t)j * F.nz * F.ldx + i;
+  const int k0 = kb * KSEG, k1 = min(F.nz, k0 + KSEG);
+#pragma unroll 4
+  for (int k = k0; k < k1; ++k) {
+    const int64_t kc = (int64_t)k * C.ldx;
+    const T v = T(9) * uc[c00 + kc] + T(3) * uc[c10 + kc] + T(3) * uc[c01 + kc] + uc[c11 + kc];
+    uf[fb + (int64_t)k * F.ldx] += v * T(0.0625);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// CG, first fused kernel ("SpMV" of Sec. 3.1):
+//   u += alpha p;  p = z + beta p;  q = A z + beta q;  partial <p, q>
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(NTHREADS) void k_cg_p1(Lvl<double> L, double* __restrict__ u,
+                                                    double* __restrict__ p,
+                                                    const double* __restrict__ z,
+                                                    double* __restrict__ q,
+                                                    const CgState* __restrict__ st,
+                                                    double* __restrict__ partials, int nti,
+                                                    int ntj) {
+  if (st->done) return;
+  const double alpha = st->alpha, beta = st->beta;
+  const int b = xcd_remap(blockIdx.x, gridDim.x);
+  const int ti = b % nti;
+  const int r1 = b / nti;
+  const int tj = r1 % ntj;
+  const int kb = r1 / ntj;
+  const int i = ti * 64 + (threadIdx.x & 63);
+  const int j = tj * SROWS + (threadIdx.x >> 6);
+  double pq[1] = {0.0};
+  if (i < L.nx && j < L.ny) {
+    const Col<double> c = load_col(L, i, j);
+    const int nz = L.nz;
+    const int k0 = kb * KSEG;
+    const int k1 = min(nz, k0 + KSEG);
+    const int64_t ldx = L.ldx;
+    int64_t o = c.base + (int64_t)k0 * ldx;
+    double zm = (k0 > 0) ? z[o - ldx] : 0.0;
+    double zc = z[o];
+#pragma unroll 4
+    for (int k = k0; k < k1; ++k, o += ldx) {
+      const double zp = (k + 1 < nz) ? z[o + ldx] : 0.0;
+      const double dzk = L.dz[k];
+      const double az = (L.dg[k] + dzk * c.S) * zc - dzk * hsum(c, z, o) + L.sub[k] * zm +
+                        L.sup[k] * zp;
+      const double pold = p[o];
+      u[o] += alpha * pold;
+      const double pn = zc + beta * pold;
+      const double qn = az + beta * q[o];
+      p[o] = pn;
+      q[o] = qn;
+      pq[0] += pn * qn;
+      zm = zc;
+      zc = zp;
+    }
+  }
+  block_partials<1>(pq, partials);
+}
+
+// ---------------------------------------------------------------------------
+// Reductions and scalar updates (single workgroup, fixed summation order)
+// ---------------------------------------------------------------------------
+template <int NC>
+__device__ __forceinline__ void reduce_fixed(const double* __restrict__ partials, int64_t n,
+                                             double (&out)[NC]) {
+  __shared__ double sm[NC][NTHREADS];
+  double s[NC];
+#pragma unroll
+  for (int c = 0; c < NC; ++c) s[c] = 0.0;
+  for (int64_t q = threadIdx.x; q < n; q += NTHREADS)
+#pragma unroll
+    for (int c = 0; c < NC; ++c) s[c] += partials[q * NC + c];
+#pragma unroll
+  for (int c = 0; c < NC; ++c) sm[c][threadIdx.x] = s[c];
+  __syncthreads();
+  for (int w = NTHREADS / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w)
+#pragma unroll
+      for (int c = 0; c < NC; ++c) sm[c][threadIdx.x] += sm[c][threadIdx.x + w];
+    __syncthreads();
+  }
+#pragma unroll
+  for (int c = 0; c < NC; ++c) out[c] = sm[c][0];
+}
+
+__global__ __launch_bounds__(NTHREADS) void k_reduce(const double* __restrict__ partials,
+                                                     int64_t n, int ncomp,
+                                                     double* __restrict__ out) {
+  if (ncomp == 1) {
+    double r[1];
+    reduce_fixed<1>(partials, n, r);
+    if (threadIdx.x == 0) out[0] = r[0];
+  } else {
+    double r[2];
+    reduce_fixed<2>(partials, n, r);
+    if (threadIdx.x == 0) {
+      out[0] = r[0];
+      out[1] = r[1];
+    }
+  }
+}
+
+__global__ __launch_bounds__(NTHREADS) void k_cg_fin1(CgState* st,
+                                                      const double* __restrict__ partials,
+                                                      int64_t n) {
+  if (st->done) return;
+  double r[1];
+  reduce_fixed<1>(partials, n, r);
+  if (threadIdx.x == 0) {
+    const double sigma = r[0];
+    st->sigma = sigma;
+    if (!(sigma > 0.0) || !isfinite(sigma)) {
+      st->status = 3;  // breakdown before the step: keep the previous iterate
+      st->done = 1;
+    } else {
+      st->alpha = st->kappa / sigma;
+    }
+  }
+}
+
+__global__ __launch_bounds__(NTHREADS) void k_cg_fin2(CgState* st,
+                                                      const double* __restrict__ partials,
+                                                      int64_t n, int init,
+                                                      double* __restrict__ hist) {
+  if (st->done) return;
+  double r[2];
+  reduce_fixed<2>(partials, n, r);
+  if (threadIdx.x == 0) {
+    const double rr = r[0], rz = r[1];
+    st->rr = rr;
+    if (init) {
+      st->rr0 = rr;
+      st->thresh2 *= rr;
+      st->kappa = rz;
+      st->iter = 0;
+      st->alpha = 0.0;
+      st->beta = 0.0;
+      hist[0] = 1.0;
+      if (rr == 0.0) st->done = 1;
+      else if (!isfinite(rr) || !isfinite(rz)) { st->status = 2; st->done = 1; }
+      return;
+    }
+    const int it = st->iter + 1;
+    st->iter = it;
+    hist[it] = sqrt(rr / st->rr0);
+    if (!isfinite(rr) || !isfinite(rz)) {
+      st->status = 2;
+      st->done = 1;
+    } else if (rr < st->thresh2) {
+      st->done = 1;
+    } else if (it >= st->maxit) {
+      st->status = 1;
+      st->done = 1;
+    } else {
+      st->beta = rz / st->kappa;
+      st->kappa = rz;
+    }
+  }
+}
+
+__global__ __launch_bounds__(NTHREADS) void k_cg_final_update(Lvl<double> L,
+                                                              double* __restrict__ u,
+                                                              const double* __restrict__ p,
+                                                              const CgState* __restrict__ st) {
+  if (st->status == 3 || st->iter == 0) return;
+  const double alpha = st->alpha;
+  const int64_t n = (int64_t)L.ny * L.nz * L.ldx;
+  for (int64_t g = (int64_t)blockIdx.x * NTHREADS + threadIdx.x; g < n;
+       g += (int64_t)gridDim.x * NTHREADS)
+    u[g] += alpha * p[g];
+}
+
+template <typename T>
+__global__ __launch_bounds__(NTHREADS) void k_fill(T* __restrict__ p, int64_t n, T v) {
+  for (int64_t g = (int64_t)blockIdx.x * NTHREADS + threadIdx.x; g < n;
+       g += (int64_t)gridDim.x * NTHREADS)
+    p[g] = v;
+}
+
+__global__ __launch_bounds__(NTHREADS) void k_add_f32_to_f64(double* __restrict__ u,
+                                                             const float* __restrict__ e,
+                                                             int64_t n) {
+  for (int64_t g = (int64_t)blockIdx.x * NTHREADS + threadIdx.x; g < n;
+       g += (int64_t)gridDim.x * NTHREADS)
+    u[g] += (double)e[g];
+}
+
+inline int cdiv(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
+
+inline int grid_stride_blocks(int64_t n) {
+  int64_t b = (n + NTHREADS - 1) / NTHREADS;
+  return (int)(b < 8192 ? (b > 0 ? b : 1) : 8192);
+}
+
+template <typename T, int MODE>
+hipError_t line_dispatch(const Lvl<T>& L, const LineArgs<T>& a, hipStream_t s) {
+  const int nti = cdiv(L.nx, 32), ntj = cdiv(L.ny, LROWS);
+  const dim3 grid(nti * ntj), block(NTHREADS);
+  const int half = (L.nz + 1) / 2;
+  if (half <= 4)
+    hipLaunchKernelGGL((k_line<T, 4, MODE>), grid, block, 0, s, L, a, nti, ntj);
+  else if (half <= 8)
+    hipLaunchKernelGGL((k_line<T, 8, MODE>), grid, block, 0, s, L, a, nti, ntj);
+  else if (half <= 16)
+    hipLaunchKernelGGL((k_line<T, 16, MODE>), grid, block, 0, s, L, a, nti, ntj);
+  else if (half <= 32)
+    hipLaunchKernelGGL((k_line<T, 32, MODE>), grid, block, 0, s, L, a, nti, ntj);
+  else if (half <= 64)
+    hipLaunchKernelGGL((k_line<T, 64, MODE>), grid, block, 0, s, L, a, nti, ntj);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+}  // namespace
+
+int64_t stencil_blocks(int nx, int ny, int nz) {
+  return (int64_t)cdiv(nx, 64) * cdiv(ny, SROWS) * cdiv(nz, KSEG);
+}
+
+int64_t line_blocks(int nx, int ny) { return (int64_t)cdiv(nx, 32) * cdiv(ny, LROWS); }
+
+template <typename T>
+hipError_t launch_stencil(const Lvl<T>& L, Stencil mode, const T* x, const T* f, T* y,
+                          float* ydown, double* partials, int64_t* nblocks, hipStream_t s) {
+  const int nti = cdiv(L.nx, 64), ntj = cdiv(L.ny, SROWS), nkb = cdiv(L.nz, KSEG);
+  const dim3 grid(nti * ntj * nkb), block(NTHREADS);
+  if (nblocks) *nblocks = (int64_t)nti * ntj * nkb;
+  switch (mode) {
+    case Stencil::SPMV:
+      hipLaunchKernelGGL((k_stencil<T, 0>), grid, block, 0, s, L, x, f, y, ydown, partials,
+                         nti, ntj);
+      break;
+    case Stencil::RESIDUAL:
+      hipLaunchKernelGGL((k_stencil<T, 1>), grid, block, 0, s, L, x, f, y, ydown, partials,
+                         nti, ntj);
+      break;
+    case Stencil::RESIDUAL_NORM:
+      hipLaunchKernelGGL((k_stencil<T, 2>), grid, block, 0, s, L, x, f, y, ydown, partials,
+                         nti, ntj);
+      break;
+    case Stencil::RESIDUAL_NORM_DOWN:
+      hipLaunchKernelGGL((k_stencil<T, 3>), grid, block, 0, s, L, x, f, y, ydown, partials,
+                         nti, ntj);
+      break;
+  }
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_line_solve(const Lvl<T>& L, const T* r, T* z, hipStream_t s) {
+  LineArgs<T> a{};
+  a.a = r;
+  a.o0 = z;
+  return line_dispatch<T, LINE_SOLVE>(L, a, s);
+}
+
+template <typename T>
+hipError_t launch_smooth(const Lvl<T>& L, const T* f, const T* uin, T* uout, T rho,
+                         hipStream_t s) {
+  LineArgs<T> a{};
+  a.a = uin;
+  a.b = f;
+  a.o0 = uout;
+  a.rho = rho;
+  return line_dispatch<T, LINE_SMOOTH>(L, a, s);
+}
+
+template <typename T>
+hipError_t launch_restrict_smooth(const Lvl<T>& C, const Lvl<T>& F, const T* rf, T* fc, T* uc,
+                                  T rho, hipStream_t s) {
+  LineArgs<T> a{};
+  a.a = rf;
+  a.o0 = uc;
+  a.o1 = fc;
+  a.rho = rho;
+  a.F = F;
+  return line_dispatch<T, LINE_RESTRICT_SMOOTH>(C, a, s);
+}
+
+template <typename T>
+hipError_t launch_prolongate(const Lvl<T>& C, const Lvl<T>& F, const T* uc, T* uf,
+                             hipStream_t s) {
+  const int nti = cdiv(F.nx, 64), ntj = cdiv(F.ny, SROWS), nkb = cdiv(F.nz, KSEG);
+  hipLaunchKernelGGL((k_prolongate<T>), dim3(nti * ntj * nkb), dim3(NTHREADS), 0, s, C, F, uc,
+                     uf, nti, ntj);
+  return hipGetLastError();
+}
+
+hipError_t launch_cg_p1(const Lvl<double>& L, double* u, double* p, const double* z, double* q,
+                        const CgState* st, double* partials, int64_t* nblocks, hipStream_t s) {
+  const int nti = cdiv(L.nx, 64), ntj = cdiv(L.ny, SROWS), nkb = cdiv(L.nz, KSEG);
+  *nblocks = (int64_t)nti * ntj * nkb;
+  hipLaunchKernelGGL(k_cg_p1, dim3(nti * ntj * nkb), dim3(NTHREADS), 0, s, L, u, p, z, q, st,
+                     partials, nti, ntj);
+  return hipGetLastError();
+}
+
+hipError_t launch_cg_p2(const Lvl<double>& L, double* r, const double* q, double* z,
+                        const CgState* st, int init, double* partials, int64_t* nblocks,
+                        hipStream_t s) {
+  LineArgs<double> a{};
+  a.a = q;
+  a.rw = r;
+  a.o0 = z;
+  a.st = st;
+  a.init = init;
+  a.partials = partials;
+  *nblocks = line_blocks(L.nx, L.ny);
+  return line_dispatch<double, LINE_CG>(L, a, s);
+}
+
+hipError_t launch_cg_fin1(CgState* st, const double* partials, int64_t nblocks, hipStream_t s) {
+  hipLaunchKernelGGL(k_cg_fin1, dim3(1), dim3(NTHREADS), 0, s, st, partials, nblocks);
+  return hipGetLastError();
+}
+
+hipError_t launch_cg_fin2(CgState* st, const double* partials, int64_t nblocks, int init,
+                          double* hist, hipStream_t s) {
+  hipLaunchKernelGGL(k_cg_fin2, dim3(1), dim3(NTHREADS), 0, s, st, partials, nblocks, init,
+                     hist);
+  return hipGetLastError();
+}
+
+hipError_t launch_cg_final_update(const Lvl<double>& L, double* u, const double* p,
+                                  const CgState* st, hipStream_t s) {
+  const int64_t n = (int64_t)L.ny * L.nz * L.ldx;
+  hipLaunchKernelGGL(k_cg_final_update, dim3(grid_stride_blocks(n)), dim3(NTHREADS), 0, s, L, u,
+                     p, st);
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce(const double* partials, int64_t nblocks, int ncomp, double* out,
+                         hipStream_t s) {
+  hipLaunchKernelGGL(k_reduce, dim3(1), dim3(NTHREADS), 0, s, partials, nblocks, ncomp, out);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_fill(T* p, int64_t n, T v, hipStream_t s) {
+  hipLaunchKernelGGL((k_fill<T>), dim3(grid_stride_blocks(n)), dim3(NTHREADS), 0, s, p, n, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_add_f32_to_f64(double* u, const float* e, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(k_add_f32_to_f64, dim3(grid_stride_blocks(n)), dim3(NTHREADS), 0, s, u, e,
+                     n);
+  return hipGetLastError();
+}
+
+#define GMG_INSTANTIATE(T)                                                                    \
+  template hipError_t launch_stencil<T>(const Lvl<T>&, Stencil, const T*, const T*, T*,       \
+                                        float*, double*, int64_t*, hipStream_t);              \
+  template hipError_t launch_line_solve<T>(const Lvl<T>&, const T*, T*, hipStream_t);         \
+  template hipError_t launch_smooth<T>(const Lvl<T>&, const T*, const T*, T*, T, hipStream_t); \
+  template hipError_t launch_restrict_smooth<T>(const Lvl<T>&, const Lvl<T>&, const T*, T*,   \
+                                                T*, T, hipStream_t);                          \
+  template hipError_t launch_prolongate<T>(const Lvl<T>&, const Lvl<T>&, const T*, T*,        \
+                                           hipStream_t);                                      \
+  template hipError_t launch_fill<T>(T*, int64_t, T, hipStream_t);
+
+GMG_INSTANTIATE(double)
+GMG_INSTANTIATE(float)
+
+}  // namespace gmg

@@ -1,0 +1,51 @@
+"""Shared helpers of the GPU parity tests: problem construction for both the
+HIP library and the CPU oracle from the same seeded inputs, and comparison
+bars.  Imports torch lazily so CPU-only collection works."""
+
+from __future__ import annotations
+
+import numpy as np
+
+import oracle
+import workloads as W
+
+
+def problem(nx, ny, nz, nlevels=1, kv=1e3, seed=3, kh_model="uniform", bc_v=0, ncoarse=2,
+            prec_precond=0, matfree=False):
+    """(library context, oracle problem, kh) for one operator."""
+    import paper_1402_3545_amd as G
+    if kh_model == "uniform":
+        kh = W.kh_uniform(seed, nx, ny)
+    elif kh_model == "lognormal":
+        kh = W.kh_lognormal(seed, nx, ny)
+    else:
+        kh = W.kh_constant(nx, ny)
+    zf = W.quadratic_faces(nz)
+    ctx = G.GmgContext(nx, ny, nz, nlevels, kv=kv, sigma=1.0, zfaces=zf, kh=kh, bc_v=bc_v,
+                       ncoarse=ncoarse, prec_precond=prec_precond)
+    orc = oracle.OracleProblem(nx, ny, nz, nlevels, kv=kv, sigma=1.0, zfaces=zf, kh=kh,
+                               bc_v=bc_v, ncoarse=ncoarse, matfree=matfree)
+    return ctx, orc, kh
+
+
+def abs_matvec(orc, x, depth=0):
+    """|A| |x| (row-wise bound of the terms summed in A x)."""
+    A = orc.scipy(depth)
+    A.data = np.abs(A.data)
+    return A @ np.abs(x)
+
+
+def device_index(ctx, rows, level=0):
+    """Library-layout indices of canonical rows (j*nx+i)*nz+k."""
+    nx, ny, nz = ctx.shape(level)
+    ldx, _ = ctx.layout(level)
+    rows = np.asarray(rows, dtype=np.int64)
+    k = rows % nz
+    col = rows // nz
+    i = col % nx
+    j = col // nx
+    return (j * nz + k) * ldx + i
+
+
+def max_rel(got, ref, scale):
+    return float(np.max(np.abs(got - ref) / scale))

@@ -1,0 +1,102 @@
+"""Full-size parity: the 1024 x 1024 x 128 grid of one GPU's share (K_T ~
+U[0.5,2], K_v = 1e4, 6 levels), in the same launch configuration the benchmark
+times.  The oracle cannot assemble this operator in a test, so it checks the
+GPU outputs at sampled columns (all layers) with its row-wise forms, and the
+solver result through the FP64 residual norm over all rows."""
+
+import numpy as np
+import pytest
+
+import workloads as W
+from tests.gpu_util import device_index, max_rel, problem
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+NCOLS = 512
+
+
+@pytest.fixture(scope="module")
+def share():
+    if not torch.cuda.is_available():
+        pytest.skip("needs a GPU")
+    w = W.SHARE
+    ctx, orc, kh = problem(w.nx, w.ny, w.nz, nlevels=w.nlevels, kv=w.kv, seed=w.seed,
+                           kh_model=w.kh_model, matfree=True)
+    rng = np.random.default_rng(1234)
+    cols = np.unique(np.concatenate([
+        rng.integers(0, w.nx * w.ny, NCOLS),
+        [0, w.nx - 1, w.nx * (w.ny - 1), w.nx * w.ny - 1]]))      # wrap-around corners
+    return w, ctx, orc, cols
+
+
+def _gather(ctx, t, rows, level=0):
+    idx = torch.from_numpy(device_index(ctx, rows, level)).cuda()
+    return t.index_select(0, idx).double().cpu().numpy()
+
+
+def test_fullsize_kernels_at_sampled_columns(share):
+    import paper_1402_3545_amd as G
+    w, ctx, orc, cols = share
+    n = w.unknowns
+    x = W.uniform_pm1(77, 1, n)
+    f = w.rhs()
+    rows = orc.column_rows(cols)
+    xd, fd, yd = ctx.to_device(x), ctx.to_device(f), ctx.empty()
+    # SpMV
+    G.spmv(ctx, 0, xd, yd)
+    ref = orc.apply_rows(rows, x)
+    scale = np.abs(ref).max()
+    assert max_rel(_gather(ctx, yd, rows), ref, scale) < 1e-12
+    # residual
+    G.gmg_residual(ctx, 0, fd, xd, yd)
+    rref = f[rows] - ref
+    assert max_rel(_gather(ctx, yd, rows), rref, np.abs(rref).max()) < 1e-12
+    # line solve
+    G.line_solve(ctx, 0, fd, yd)
+    zref = orc.line_solve_columns(cols, f)[rows]
+    assert max_rel(_gather(ctx, yd, rows), zref, np.abs(zref).max()) < 1e-12
+    # smooth: u + rho M^-1 (f - A u) on the sampled columns
+    ud = xd.clone()
+    G.line_smooth(ctx, 0, fd, ud)
+    r_full = np.zeros(n)
+    r_full[rows] = f[rows] - ref
+    sref = x[rows] + ctx.rho * orc.line_solve_columns(cols, r_full)[rows]
+    assert max_rel(_gather(ctx, ud, rows), sref, np.abs(sref).max()) < 1e-12
+
+
+def test_fullsize_transfers_at_sampled_columns(share):
+    import paper_1402_3545_amd as G
+    w, ctx, orc, cols = share
+    n = w.unknowns
+    rf = W.uniform_pm1(78, 1, n)
+    nc = orc.size(1)
+    rfd = ctx.to_device(rf)
+    fcd, ucd = ctx.empty(1), ctx.empty(1)
+    G.gmg_restrict_smooth(ctx, 1, rfd, fcd, ucd)
+    fc_ref = orc.restrict(rf, 0)
+    ccols = np.unique(cols % nc)
+    crow = orc.column_rows(ccols)
+    assert max_rel(_gather(ctx, fcd, crow, 1), fc_ref[crow], np.abs(fc_ref).max()) < 1e-12
+    uc_ref = ctx.rho * orc.line_solve_columns(ccols, fc_ref, depth=1)[crow]
+    assert max_rel(_gather(ctx, ucd, crow, 1), uc_ref, np.abs(uc_ref).max()) < 1e-12
+    uc = W.uniform_pm1(79, 1, nc)
+    ufd = ctx.to_device(rf)
+    G.gmg_prolongate(ctx, 1, ctx.to_device(uc, 1), ufd)
+    pref = orc.prolongate_add(uc, rf, 1)
+    rows = orc.column_rows(cols)
+    assert max_rel(_gather(ctx, ufd, rows), pref[rows], np.abs(pref).max()) < 1e-12
+
+
+def test_fullsize_mg_solve_true_residual(share):
+    import paper_1402_3545_amd as G
+    w, ctx, orc, _ = share
+    f = w.rhs()
+    fd, ud = ctx.to_device(f), ctx.empty()
+    it, rel, hist, st = G.gmg_solve(ctx, fd, ud, rtol=w.rtol, maxit=60)
+    assert st == 0 and 5 < it < 40
+    assert (np.diff(hist) < 0).all()
+    u = ctx.from_device(ud)
+    true_rel = orc.residual_norm2_rows(f, u) ** 0.5 / np.linalg.norm(f)
+    assert true_rel < w.rtol
+    assert true_rel == pytest.approx(rel, rel=1e-6)

@@ -1,0 +1,149 @@
+"""Parity of the V-cycle and of the MG / CG / mixed-precision solvers with the
+CPU oracle on seeded synthetic inputs.
+
+Bars: the V-cycle is a fixed linear map; FP64 cycles agree with the oracle to
+1e-11 of max|u| (a few kernels' worth of 1e-15-level differences).  FP64 MG
+takes exactly the oracle's number of cycles with residual histories within
+1e-10 relative; FP64 CG ends within one iteration of the oracle and meets the
+tolerance in the true residual.  Mixed precision (FP32 cycles inside FP64
+refinement) is judged by the true FP64 relative residual, computed by the
+oracle from the returned solution; its error against the oracle's FP64
+solution is recorded, not gated beyond that."""
+
+import numpy as np
+import pytest
+
+import workloads as W
+from tests.gpu_util import max_rel, problem
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(autouse=True, scope="module")
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("needs a GPU")
+
+
+VC = [((4, 4, 8), 1, 2), ((8, 8, 4), 2, 2), ((8, 8, 3), 3, 3), ((64, 64, 64), 4, 2),
+      ((40, 24, 37), 3, 2), ((32, 64, 128), 5, 2)]
+
+
+@pytest.mark.parametrize("shape,L,nc", VC)
+def test_vcycle_f64(shape, L, nc):
+    import paper_1402_3545_amd as G
+    nx, ny, nz = shape
+    ctx, orc, _ = problem(nx, ny, nz, nlevels=L, ncoarse=nc, seed=10)
+    n = nx * ny * nz
+    f = W.uniform_pm1(10, 1, n)
+    u = W.uniform_pm1(10, 2, n)
+    fd, ud = ctx.to_device(f), ctx.to_device(u)
+    G.gmg_vcycle(ctx, fd, ud)
+    ref = orc.vcycle(f, u)
+    assert max_rel(ctx.from_device(ud), ref, np.abs(ref).max()) < 1e-11
+
+
+@pytest.mark.parametrize("shape,L,nc", VC)
+def test_vcycle_f32(shape, L, nc):
+    import paper_1402_3545_amd as G
+    nx, ny, nz = shape
+    ctx, orc, _ = problem(nx, ny, nz, nlevels=L, ncoarse=nc, seed=10, prec_precond=1)
+    n = nx * ny * nz
+    f = W.uniform_pm1(10, 1, n).astype(np.float32).astype(np.float64)
+    u = W.uniform_pm1(10, 2, n).astype(np.float32).astype(np.float64)
+    fd, ud = ctx.to_device(f, dtype=torch.float32), ctx.to_device(u, dtype=torch.float32)
+    G.gmg_vcycle(ctx, fd, ud)
+    ref = orc.vcycle(f, u)
+    assert max_rel(ctx.from_device(ud), ref, np.abs(ref).max()) < 1e-4
+
+
+def _small():
+    w = W.SMALL
+    ctx, orc, _ = problem(w.nx, w.ny, w.nz, nlevels=w.nlevels, kv=w.kv, seed=w.seed,
+                          kh_model=w.kh_model)
+    return w, ctx, orc
+
+
+def test_mg_solve_matches_oracle_history():
+    import paper_1402_3545_amd as G
+    w, ctx, orc = _small()
+    f = w.rhs()
+    fd, ud = ctx.to_device(f), ctx.empty()
+    it, rel, hist, st = G.gmg_solve(ctx, fd, ud, rtol=w.rtol, maxit=50)
+    u_ref, it_ref, hist_ref, st_ref = orc.mg_solve(f, rtol=w.rtol, maxit=50)
+    assert st == 0 and st_ref == 0
+    assert it == it_ref
+    assert np.allclose(hist, hist_ref, rtol=1e-10, atol=0)
+    u = ctx.from_device(ud)
+    assert max_rel(u, u_ref, np.abs(u_ref).max()) < 1e-10
+    assert orc.residual_norm2_rows(f, u) ** 0.5 / np.linalg.norm(f) < w.rtol
+
+
+def test_mg_solve_tight_tolerance():
+    import paper_1402_3545_amd as G
+    w, ctx, orc = _small()
+    f = w.rhs()
+    fd, ud = ctx.to_device(f), ctx.empty()
+    it, rel, hist, st = G.gmg_solve(ctx, fd, ud, rtol=1e-10, maxit=100)
+    _, it_ref, _, _ = orc.mg_solve(f, rtol=1e-10, maxit=100)
+    assert st == 0 and it == it_ref
+    assert (np.diff(hist) < 0).all()
+    u = ctx.from_device(ud)
+    true_rel = orc.residual_norm2_rows(f, u) ** 0.5 / np.linalg.norm(f)
+    assert true_rel < 1e-10 and true_rel == pytest.approx(rel, rel=1e-6)
+
+
+def test_pcg_line_matches_oracle():
+    import paper_1402_3545_amd as G
+    w, ctx, orc = _small()
+    f = w.rhs()
+    for rtol in (w.rtol, 1e-8):
+        fd, ud = ctx.to_device(f), ctx.empty()
+        it, rel, hist, st = G.pcg_solve(ctx, fd, ud, rtol=rtol, maxit=500)
+        u_ref, it_ref, hist_ref, rt_ref, st_ref = orc.pcg_solve(f, rtol=rtol, maxit=500)
+        assert st == 0 and st_ref == 0
+        assert abs(it - it_ref) <= 1
+        m = min(it, it_ref) + 1
+        assert np.allclose(hist[:m], hist_ref[:m], rtol=1e-6, atol=0)
+        u = ctx.from_device(ud)
+        true_rel = orc.residual_norm2_rows(f, u) ** 0.5 / np.linalg.norm(f)
+        assert true_rel < rtol * 1.01
+        assert true_rel == pytest.approx(rel, rel=1e-6)
+
+
+def test_mixed_precision_refinement_reaches_fp64_tolerance():
+    import paper_1402_3545_amd as G
+    w = W.SMALL
+    ctx, orc, _ = problem(w.nx, w.ny, w.nz, nlevels=w.nlevels, kv=w.kv, seed=w.seed,
+                          kh_model=w.kh_model, prec_precond=1)
+    f = w.rhs()
+    fd, ud = ctx.to_device(f), ctx.empty()
+    it, rel, hist, st = G.gmg_solve(ctx, fd, ud, rtol=1e-8, maxit=60)
+    _, it64, _, _ = orc.mg_solve(f, rtol=1e-8, maxit=60)
+    assert st == 0
+    u = ctx.from_device(ud)
+    true_rel = orc.residual_norm2_rows(f, u) ** 0.5 / np.linalg.norm(f)
+    assert true_rel < 1e-8
+    assert it <= it64 + 2          # FP32 cycles cost at most a couple of extra cycles
+    u_ref, _, _, _ = orc.mg_solve(f, rtol=1e-12, maxit=100)
+    err = np.linalg.norm(u - u_ref) / np.linalg.norm(u_ref)
+    assert err < 1e-6, err
+
+
+def test_solvers_degenerate_cases():
+    import paper_1402_3545_amd as G
+    ctx, orc, _ = problem(8, 8, 4, nlevels=2)
+    fd, ud = ctx.empty(), ctx.empty()
+    it, rel, hist, st = G.gmg_solve(ctx, fd, ud, rtol=1e-8, maxit=10)   # f = 0
+    assert st == 0 and it == 0 and rel == 0.0
+    it, rel, hist, st = G.pcg_solve(ctx, fd, ud, rtol=1e-8, maxit=10)
+    assert st == 0 and it == 0
+    f = W.uniform_pm1(1, 1, 8 * 8 * 4)
+    fd = ctx.to_device(f)
+    it, rel, hist, st = G.gmg_solve(ctx, fd, ud, rtol=1e-8, maxit=0, check=False)
+    assert st == G.GMG_ENOCONV and it == 0
+    it, rel, hist, st = G.pcg_solve(ctx, fd, ctx.empty(), rtol=1e-30, maxit=3, check=False)
+    assert st == G.GMG_ENOCONV and it == 3
+    with pytest.raises(G.GmgError):
+        G.gmg_solve(ctx, fd, ud, rtol=0.0)

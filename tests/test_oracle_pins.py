@@ -466,6 +466,27 @@ def test_small_workload_iteration_counts():
     assert rt < w.rtol * 1.01
 
 
+def test_rowwise_forms_equal_csr_forms():
+    nx, ny, nz = 8, 6, 7
+    kh = W.kh_uniform(8, nx, ny)
+    p = oracle.OracleProblem(nx, ny, nz, 2, kv=300.0, sigma=1.0, kh=kh)
+    q = oracle.OracleProblem(nx, ny, nz, 2, kv=300.0, sigma=1.0, kh=kh, matfree=True)
+    x = W.uniform_pm1(8, 1, nx * ny * nz)
+    f = W.uniform_pm1(8, 2, nx * ny * nz)
+    rows = np.arange(nx * ny * nz)
+    assert np.array_equal(q.apply_rows(rows, x), p.spmv(x))
+    r = p.residual(f, x)
+    assert q.residual_norm2_rows(f, x) == pytest.approx(r @ r, rel=1e-13)
+    cols = np.array([0, 5, nx * ny - 1])
+    z = q.line_solve_columns(cols, f)
+    ref = p.line_solve(f)
+    sel = q.column_rows(cols)
+    assert np.array_equal(z[sel], ref[sel])
+    assert np.isnan(np.delete(z, sel)).all()
+    with pytest.raises(RuntimeError):
+        q.spmv(x)
+
+
 def test_invalid_inputs_raise():
     with pytest.raises(ValueError):
         oracle.OracleProblem(6, 6, 4, 3)      # 6 not divisible by 4

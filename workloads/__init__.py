@@ -33,8 +33,12 @@ import math
 import numpy as np
 
 GAMMA = 0x9E3779B97F4A7C15
-_M1 = np.uint64(0xBF58476D1CE4E5B9)
-_M2 = np.uint64(0x94D049BB133111EB)
+# one-element arrays, not numpy scalars: scalar uint64 operands take a slow
+# overflow-checked path
+_M1 = np.array([0xBF58476D1CE4E5B9], dtype=np.uint64)
+_M2 = np.array([0x94D049BB133111EB], dtype=np.uint64)
+_G = np.array([GAMMA], dtype=np.uint64)
+_S30, _S27, _S31, _S11 = (np.array([v], dtype=np.uint64) for v in (30, 27, 31, 11))
 _MASK64 = (1 << 64) - 1
 _CHUNK = 1 << 22
 
@@ -47,29 +51,61 @@ def stream_state(seed: int, stream: int) -> int:
     return (int(seed) + int(stream) * (1 << 32)) & _MASK64
 
 
+def _chunks(seed: int, stream: int, start: int, count: int, emit) -> None:
+    """Run SplitMix64 over outputs start..start+count-1 in reused chunk buffers,
+    handing each uint64 chunk to emit(c0, c1, chunk)."""
+    s0 = np.array([stream_state(seed, stream)], dtype=np.uint64)
+    m = max(1, min(count, _CHUNK))
+    z = np.empty(m, dtype=np.uint64)
+    t = np.empty(m, dtype=np.uint64)
+    for c0 in range(0, count, _CHUNK):
+        c1 = min(count, c0 + _CHUNK)
+        w = c1 - c0
+        zz, tt = z[:w], t[:w]
+        zz.view(np.int64)[:] = np.arange(start + c0 + 1, start + c1 + 1, dtype=np.int64)
+        np.multiply(zz, _G, out=zz)
+        np.add(zz, s0, out=zz)
+        for shift, mul in ((_S30, _M1), (_S27, _M2)):
+            np.right_shift(zz, shift, out=tt)
+            np.bitwise_xor(zz, tt, out=zz)
+            np.multiply(zz, mul, out=zz)
+        np.right_shift(zz, _S31, out=tt)
+        np.bitwise_xor(zz, tt, out=zz)
+        emit(c0, c1, zz)
+
+
 def splitmix64(seed: int, stream: int, start: int, count: int) -> np.ndarray:
     """Outputs start .. start+count-1 of the stream, as uint64."""
-    s0 = np.uint64(stream_state(seed, stream))
     out = np.empty(count, dtype=np.uint64)
-    g = np.uint64(GAMMA)
-    with np.errstate(over="ignore"):
-        for c0 in range(0, count, _CHUNK):
-            c1 = min(count, c0 + _CHUNK)
-            n = np.arange(start + c0 + 1, start + c1 + 1, dtype=np.uint64)
-            z = s0 + n * g
-            z = (z ^ (z >> np.uint64(30))) * _M1
-            z = (z ^ (z >> np.uint64(27))) * _M2
-            out[c0:c1] = z ^ (z >> np.uint64(31))
+
+    def emit(c0, c1, zz):
+        out[c0:c1] = zz
+
+    _chunks(seed, stream, start, count, emit)
     return out
 
 
-def uniform01(seed: int, stream: int, count: int, start: int = 0) -> np.ndarray:
-    x = splitmix64(seed, stream, start, count)
-    return (x >> np.uint64(11)).astype(np.float64) * (2.0 ** -53)
+def uniform01(seed: int, stream: int, count: int, start: int = 0, lo: float = 0.0,
+              hi: float = 1.0) -> np.ndarray:
+    """lo + (hi - lo) * U with U = (x >> 11) * 2**-53 (exact in float64)."""
+    out = np.empty(count, dtype=np.float64)
+
+    def emit(c0, c1, zz):
+        np.right_shift(zz, _S11, out=zz)
+        o = out[c0:c1]
+        o[:] = zz.view(np.int64)
+        o *= 2.0 ** -53
+        if lo != 0.0 or hi != 1.0:
+            o *= hi - lo
+            o += lo
+
+    _chunks(seed, stream, start, count, emit)
+    return out
 
 
 def uniform_pm1(seed: int, stream: int, count: int) -> np.ndarray:
-    return 2.0 * uniform01(seed, stream, count) - 1.0
+    """2U - 1 (the scaling by 2 and shift by 1 are exact)."""
+    return uniform01(seed, stream, count, lo=-1.0, hi=1.0)
 
 
 def normal(seed: int, stream: int, count: int) -> np.ndarray:
@@ -110,23 +146,6 @@ def quadratic_faces(nz: int) -> np.ndarray:
 
 def uniform_faces(nz: int) -> np.ndarray:
     return np.arange(nz + 1, dtype=np.float64) / nz
-
-
-# ---------------------------------------------------------------------------
-# Layout helpers (pure data movement)
-# ---------------------------------------------------------------------------
-
-def canonical_to_xcontig(a: np.ndarray, nx: int, ny: int, nz: int, ldx: int) -> np.ndarray:
-    """(j*nx+i)*nz+k order -> x-contiguous (j*nz+k)*ldx+i order, padding zeroed."""
-    v = np.asarray(a).reshape(ny, nx, nz).transpose(0, 2, 1)
-    out = np.zeros((ny, nz, ldx), dtype=np.asarray(a).dtype)
-    out[:, :, :nx] = v
-    return out.reshape(-1)
-
-
-def xcontig_to_canonical(a: np.ndarray, nx: int, ny: int, nz: int, ldx: int) -> np.ndarray:
-    v = np.asarray(a).reshape(ny, nz, ldx)[:, :, :nx]
-    return np.ascontiguousarray(v.transpose(0, 2, 1)).reshape(-1)
 
 
 # ---------------------------------------------------------------------------
