@@ -9,8 +9,9 @@ One step = the whole hot path once on the resident input, every solve from
 u = 0 to a relative residual of 1e-8:
   1. FP64 multigrid, V(1,1) cycles (Algorithm 1);
   2. FP64 CG with the vertical line preconditioner (fused kernels);
-  3. mixed precision: FP32 V-cycles inside FP64 iterative refinement.
-value = sum over the three solves of (unknowns x iterations) / step time.
+  3. mixed precision: FP32 V-cycles inside FP64 iterative refinement;
+  4. mixed precision: flexible CG (FP64) preconditioned by one FP32 V-cycle.
+value = sum over the four solves of (unknowns x iterations) / step time.
 
 The dominant kernel's roofline comes from the library's own per-kernel HIP
 event timing over the timed region (gmg_timing_*), on the stream the kernels
@@ -128,7 +129,9 @@ def main():
         out = {}
         for name, fn in (("mg_f64", lambda: G.gmg_solve(ctx64, fd, ud, w.rtol, 100)),
                          ("pcg_f64", lambda: G.pcg_solve(ctx64, fd, ud, w.rtol, 2000)),
-                         ("mg_mixed", lambda: G.gmg_solve(ctx32, fd, ud, w.rtol, 100))):
+                         ("mg_mixed", lambda: G.gmg_solve(ctx32, fd, ud, w.rtol, 100)),
+                         ("fcg_mixed", lambda: G.pcg_solve(ctx32, fd, ud, w.rtol, 100,
+                                                           precond=1))):
             ud.zero_()
             a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             a.record()
@@ -202,11 +205,14 @@ def main():
             "workload": w.name,
             "nx": w.nx, "ny": w.ny, "nz": w.nz, "levels": w.nlevels, "kv": w.kv,
             "kh": "U[0.5,2] seed 2", "rtol": w.rtol,
-            "step": "FP64 MG + FP64 line-CG + FP32-cycle MG in FP64 refinement, each from u=0",
+            "step": ("FP64 MG + FP64 line-CG + FP32-cycle MG in FP64 refinement + FP64 "
+                     "flexible CG with FP32 V-cycle, each from u=0"),
         },
         "solves": {n: {"iters": v["iters"], "ms": round(v["ms"], 3),
                        "relres": v["relres"]} for n, v in last.items()},
         "mixed_vs_fp64_mg_speedup": mg["ms"] / mx["ms"] if mx["ms"] > 0 else None,
+        "fcg_mixed_vs_fp64_mg_speedup": (mg["ms"] / last["fcg_mixed"]["ms"]
+                                         if last["fcg_mixed"]["ms"] > 0 else None),
         "roofline": {
             "bound": "hbm",
             "kernel": f"{dom[0]} level {dom[1]} {dom[2]}",

@@ -474,6 +474,89 @@ int residual_norm2(gmg_ctx* c, const T* f, const T* u, T* r, float* rdown, doubl
   return GMG_OK;
 }
 
+int ensure_hist(gmg_ctx* c, int maxit) {
+  if (c->dhist_len < maxit + 1) {
+    dfree(c->dhist);
+    c->dhist_len = 0;
+    HIP_TRY(dmalloc(&c->dhist, (size_t)maxit + 1));
+    c->dhist_len = maxit + 1;
+  }
+  return GMG_OK;
+}
+
+// Flexible CG preconditioned by one V-cycle of precision TZ per iteration
+// (TZ = float: the FP32 cycle runs on an FP32 copy of the FP64 residual and
+// its FP32 correction enters the FP64 recurrences directly).
+template <typename TZ>
+int fcg_impl(gmg_ctx* c, const double* f, double* u, double rtol, int maxit, int* iters,
+             double* relres, double* history, hipStream_t s) {
+  const bool mixed = sizeof(TZ) == 4;
+  const Lvl<double> V = gmg::view<double>(c, 0);
+  const int64_t n0 = c->lev[0].elems;
+  int st;
+  if ((st = ensure_hist(c, maxit))) return st;
+  double rr0 = 0.0;
+  if ((st = residual_norm2<double>(c, f, u, c->vr, mixed ? c->er32 : nullptr, &rr0, s))) return st;
+  if (iters) *iters = 0;
+  if (relres) *relres = rr0 > 0.0 ? 1.0 : 0.0;
+  if (history) history[0] = 1.0;
+  if (!isfinite(rr0)) return fail(GMG_ENOCONV, "initial residual is not finite");
+  if (rr0 == 0.0) return GMG_OK;
+  CgState init{};
+  init.maxit = maxit;
+  init.rr0 = rr0;
+  init.rr = rr0;
+  init.thresh2 = rtol * rtol * rr0;
+  init.sigma = 1.0;
+  const double one = 1.0;
+  HIP_TRY(hipMemcpyAsync(c->state, &init, sizeof(CgState), hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(c->dhist, &one, sizeof(double), hipMemcpyHostToDevice, s));
+  HIP_TRY(timed(c, GMG_K_AUX, 0, GMG_F64, s,
+                [&] { return gmg::launch_fill<double>(c->vp, n0, 0.0, s); }));
+  HIP_TRY(timed(c, GMG_K_AUX, 0, GMG_F64, s,
+                [&] { return gmg::launch_fill<double>(c->vq, n0, 0.0, s); }));
+  TZ* z = mixed ? reinterpret_cast<TZ*>(c->eu32) : reinterpret_cast<TZ*>(c->vz);
+  const TZ* rin = mixed ? reinterpret_cast<const TZ*>(c->er32) : reinterpret_cast<const TZ*>(c->vr);
+  const int P = mixed ? GMG_F32 : GMG_F64;
+  for (int it = 1; it <= maxit; ++it) {
+    HIP_TRY(timed(c, GMG_K_AUX, 0, P, s, [&] { return gmg::launch_fill<TZ>(z, n0, TZ(0), s); }));
+    if ((st = vcycle_impl<TZ>(c, rin, z, s))) return st;
+    int64_t nb = 0;
+    HIP_TRY(timed(c, GMG_K_AUX, 0, GMG_F64, s,
+                  [&] { return gmg::launch_fcg_zq<TZ>(V, z, c->vq, c->partials, &nb, s); }));
+    HIP_TRY(timed(c, GMG_K_REDUCE, 0, GMG_F64, s,
+                  [&] { return gmg::launch_fcg_fin(0, c->state, c->partials, nb, nullptr, s); }));
+    HIP_TRY(timed(c, GMG_K_CG_SPMV, 0, GMG_F64, s, [&] {
+      return gmg::launch_fcg_dir<TZ>(V, z, c->vp, c->vq, c->vr, c->state, c->partials, &nb, s);
+    }));
+    HIP_TRY(timed(c, GMG_K_REDUCE, 0, GMG_F64, s,
+                  [&] { return gmg::launch_fcg_fin(1, c->state, c->partials, nb, nullptr, s); }));
+    HIP_TRY(timed(c, GMG_K_AUX, 0, GMG_F64, s, [&] {
+      return gmg::launch_fcg_update(V, u, c->vr, c->vp, c->vq, mixed ? c->er32 : nullptr,
+                                    c->state, c->partials, &nb, s);
+    }));
+    HIP_TRY(timed(c, GMG_K_REDUCE, 0, GMG_F64, s,
+                  [&] { return gmg::launch_fcg_fin(2, c->state, c->partials, nb, c->dhist, s); }));
+    HIP_TRY(hipMemcpyAsync(c->hstate, c->state, sizeof(CgState), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (c->hstate->done) break;
+  }
+  const CgState hs = *c->hstate;
+  if (history)
+    HIP_TRY(hipMemcpyAsync(history, c->dhist, (size_t)(hs.iter + 1) * sizeof(double),
+                           hipMemcpyDeviceToHost, s));
+  double rr = 0.0;
+  if ((st = residual_norm2<double>(c, f, u, c->vt, nullptr, &rr, s))) return st;
+  if (iters) *iters = hs.iter;
+  if (relres) *relres = sqrt(rr / rr0);
+  if (hs.status == 1 || !hs.done)
+    return fail(GMG_ENOCONV, "no convergence to %g in %d iterations", rtol, maxit);
+  if (hs.status >= 2)
+    return fail(GMG_ENOCONV, "flexible CG breakdown or non-finite value at iteration %d",
+                hs.iter);
+  return GMG_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -704,17 +787,16 @@ int pcg_solve(gmg_ctx* c, const double* f, double* u, double rtol, int maxit, in
   if (!(rtol > 0.0)) return fail(GMG_EINVAL, "rtol must be > 0");
   if (maxit < 0) return fail(GMG_EINVAL, "maxit must be >= 0");
   if (f == u) return fail(GMG_EINVAL, "f and u must not overlap");
-  if (precond != 0)
-    return fail(GMG_EUNSUPPORTED, "pcg_solve: precond=%d not implemented", precond);
+  if (precond != 0 && precond != 1) return fail(GMG_EINVAL, "precond must be 0 or 1");
   hipStream_t s = as_stream(stream);
+  if (precond == 1) {
+    if (c->p.prec_precond == GMG_F32)
+      return fcg_impl<float>(c, f, u, rtol, maxit, iters, relres, history, s);
+    return fcg_impl<double>(c, f, u, rtol, maxit, iters, relres, history, s);
+  }
   const Lvl<double> V = gmg::view<double>(c, 0);
   const int64_t n0 = c->lev[0].elems;
-  if (c->dhist_len < maxit + 1) {
-    dfree(c->dhist);
-    c->dhist_len = 0;
-    HIP_TRY(dmalloc(&c->dhist, (size_t)maxit + 1));
-    c->dhist_len = maxit + 1;
-  }
+  if ((st = ensure_hist(c, maxit))) return st;
   // initial state: r = f - A u, z = M^-1 r, kappa = <r,z>, p = q = 0
   CgState init{};
   init.maxit = maxit;

@@ -129,6 +129,20 @@ hipError_t launch_cg_final_update(const Lvl<double>& L, double* u, const double*
                                   const CgState* st, hipStream_t s);
 hipError_t launch_reduce(const double* partials, int64_t nblocks, int ncomp, double* out,
                          hipStream_t s);
+// flexible CG (variable preconditioner)
+template <typename TZ>
+hipError_t launch_fcg_zq(const Lvl<double>& L, const TZ* z, const double* q, double* partials,
+                         int64_t* nblocks, hipStream_t s);
+template <typename TZ>
+hipError_t launch_fcg_dir(const Lvl<double>& L, const TZ* z, double* p, double* q,
+                          const double* r, const CgState* st, double* partials, int64_t* nblocks,
+                          hipStream_t s);
+hipError_t launch_fcg_update(const Lvl<double>& L, double* u, double* r, const double* p,
+                             const double* q, float* rdown, const CgState* st, double* partials,
+                             int64_t* nblocks, hipStream_t s);
+// which: 0 beta, 1 alpha, 2 residual / convergence
+hipError_t launch_fcg_fin(int which, CgState* st, const double* partials, int64_t nblocks,
+                          double* hist, hipStream_t s);
 
 template <typename T>
 hipError_t launch_fill(T* p, int64_t n, T v, hipStream_t s);

@@ -373,6 +373,114 @@ __global__ __launch_bounds__(NTHREADS) void k_cg_p1(Lvl<double> L, double* __res
 }
 
 // ---------------------------------------------------------------------------
+// Flexible CG with a variable (multigrid) preconditioner z = B(r)
+// (Notay, "Flexible conjugate gradients", SIAM J. Sci. Comput. 22, 2000; one
+// direction kept):  beta = -<z, q_old>/<p_old, q_old>,  p = z + beta p,
+// q = A z + beta q  (= A p),  alpha = <p, r>/<p, q>,  u += alpha p,
+// r -= alpha q.  z may be FP32 (mixed precision); everything else is FP64.
+// ---------------------------------------------------------------------------
+template <typename TZ>
+__global__ __launch_bounds__(NTHREADS) void k_fcg_zq(Lvl<double> L, const TZ* __restrict__ z,
+                                                     const double* __restrict__ q,
+                                                     double* __restrict__ partials, int nti,
+                                                     int ntj) {
+  const int b = xcd_remap(blockIdx.x, gridDim.x);
+  const int ti = b % nti;
+  const int r1 = b / nti;
+  const int tj = r1 % ntj;
+  const int kb = r1 / ntj;
+  const int i = ti * 64 + (threadIdx.x & 63);
+  const int j = tj * SROWS + (threadIdx.x >> 6);
+  double acc[1] = {0.0};
+  if (i < L.nx && j < L.ny) {
+    const int64_t base = (int64_t)j * L.nz * L.ldx + i;
+    const int k0 = kb * KSEG, k1 = min(L.nz, k0 + KSEG);
+    for (int k = k0; k < k1; ++k) {
+      const int64_t o = base + (int64_t)k * L.ldx;
+      acc[0] += (double)z[o] * q[o];
+    }
+  }
+  block_partials<1>(acc, partials);
+}
+
+template <typename TZ>
+__global__ __launch_bounds__(NTHREADS) void k_fcg_dir(Lvl<double> L, const TZ* __restrict__ z,
+                                                      double* __restrict__ p,
+                                                      double* __restrict__ q,
+                                                      const double* __restrict__ r,
+                                                      const CgState* __restrict__ st,
+                                                      double* __restrict__ partials, int nti,
+                                                      int ntj) {
+  const double beta = st->beta;
+  const int b = xcd_remap(blockIdx.x, gridDim.x);
+  const int ti = b % nti;
+  const int r1 = b / nti;
+  const int tj = r1 % ntj;
+  const int kb = r1 / ntj;
+  const int i = ti * 64 + (threadIdx.x & 63);
+  const int j = tj * SROWS + (threadIdx.x >> 6);
+  double acc[2] = {0.0, 0.0};
+  if (i < L.nx && j < L.ny) {
+    const Col<double> c = load_col(L, i, j);
+    const int nz = L.nz;
+    const int k0 = kb * KSEG;
+    const int k1 = min(nz, k0 + KSEG);
+    const int64_t ldx = L.ldx;
+    int64_t o = c.base + (int64_t)k0 * ldx;
+    double zm = (k0 > 0) ? (double)z[o - ldx] : 0.0;
+    double zc = (double)z[o];
+    for (int k = k0; k < k1; ++k, o += ldx) {
+      const double zp = (k + 1 < nz) ? (double)z[o + ldx] : 0.0;
+      const double h = c.ce * (double)z[o + c.oe] + c.cw * (double)z[o + c.ow] +
+                       c.cn * (double)z[o + c.on] + c.cs * (double)z[o + c.os];
+      const double dzk = L.dz[k];
+      const double az = (L.dg[k] + dzk * c.S) * zc - dzk * h + L.sub[k] * zm + L.sup[k] * zp;
+      const double pn = zc + beta * p[o];
+      const double qn = az + beta * q[o];
+      p[o] = pn;
+      q[o] = qn;
+      acc[0] += pn * qn;
+      acc[1] += pn * r[o];
+      zm = zc;
+      zc = zp;
+    }
+  }
+  block_partials<2>(acc, partials);
+}
+
+__global__ __launch_bounds__(NTHREADS) void k_fcg_update(Lvl<double> L, double* __restrict__ u,
+                                                         double* __restrict__ r,
+                                                         const double* __restrict__ p,
+                                                         const double* __restrict__ q,
+                                                         float* __restrict__ rdown,
+                                                         const CgState* __restrict__ st,
+                                                         double* __restrict__ partials, int nti,
+                                                         int ntj) {
+  const double alpha = st->alpha;
+  const int b = xcd_remap(blockIdx.x, gridDim.x);
+  const int ti = b % nti;
+  const int r1 = b / nti;
+  const int tj = r1 % ntj;
+  const int kb = r1 / ntj;
+  const int i = ti * 64 + (threadIdx.x & 63);
+  const int j = tj * SROWS + (threadIdx.x >> 6);
+  double acc[1] = {0.0};
+  if (i < L.nx && j < L.ny) {
+    const int64_t base = (int64_t)j * L.nz * L.ldx + i;
+    const int k0 = kb * KSEG, k1 = min(L.nz, k0 + KSEG);
+    for (int k = k0; k < k1; ++k) {
+      const int64_t o = base + (int64_t)k * L.ldx;
+      u[o] += alpha * p[o];
+      const double rn = r[o] - alpha * q[o];
+      r[o] = rn;
+      if (rdown) rdown[o] = (float)rn;
+      acc[0] += rn * rn;
+    }
+  }
+  block_partials<1>(acc, partials);
+}
+
+// ---------------------------------------------------------------------------
 // Reductions and scalar updates (single workgroup, fixed summation order)
 // ---------------------------------------------------------------------------
 template <int NC>
@@ -469,6 +577,57 @@ __global__ __launch_bounds__(NTHREADS) void k_cg_fin2(CgState* st,
     } else {
       st->beta = rz / st->kappa;
       st->kappa = rz;
+    }
+  }
+}
+
+// beta = -<z, q_old> / sigma_old  (0 on the first iteration: q_old = 0)
+__global__ __launch_bounds__(NTHREADS) void k_fcg_fin_beta(CgState* st,
+                                                           const double* __restrict__ partials,
+                                                           int64_t n) {
+  double r[1];
+  reduce_fixed<1>(partials, n, r);
+  if (threadIdx.x == 0) st->beta = st->iter == 0 ? 0.0 : -r[0] / st->sigma;
+}
+
+// sigma = <p, q>, alpha = <p, r> / sigma
+__global__ __launch_bounds__(NTHREADS) void k_fcg_fin_alpha(CgState* st,
+                                                            const double* __restrict__ partials,
+                                                            int64_t n) {
+  double r[2];
+  reduce_fixed<2>(partials, n, r);
+  if (threadIdx.x == 0) {
+    st->sigma = r[0];
+    if (!(r[0] > 0.0) || !isfinite(r[0])) {
+      st->status = 3;
+      st->done = 1;
+      st->alpha = 0.0;
+    } else {
+      st->alpha = r[1] / r[0];
+    }
+  }
+}
+
+// ||r||^2 after the update: history, convergence, iteration count
+__global__ __launch_bounds__(NTHREADS) void k_fcg_fin_res(CgState* st,
+                                                          const double* __restrict__ partials,
+                                                          int64_t n, double* __restrict__ hist) {
+  double r[1];
+  reduce_fixed<1>(partials, n, r);
+  if (threadIdx.x == 0) {
+    const double rr = r[0];
+    st->rr = rr;
+    const int it = st->iter + 1;
+    st->iter = it;
+    hist[it] = sqrt(rr / st->rr0);
+    if (!isfinite(rr)) {
+      st->status = 2;
+      st->done = 1;
+    } else if (rr < st->thresh2) {
+      st->done = 1;
+    } else if (it >= st->maxit) {
+      st->status = 1;
+      st->done = 1;
     }
   }
 }
@@ -624,6 +783,60 @@ hipError_t launch_cg_p2(const Lvl<double>& L, double* r, const double* q, double
   *nblocks = line_blocks(L.nx, L.ny);
   return line_dispatch<double, LINE_CG>(L, a, s);
 }
+
+template <typename TZ>
+hipError_t launch_fcg_zq(const Lvl<double>& L, const TZ* z, const double* q, double* partials,
+                         int64_t* nblocks, hipStream_t s) {
+  const int nti = cdiv(L.nx, 64), ntj = cdiv(L.ny, SROWS), nkb = cdiv(L.nz, KSEG);
+  *nblocks = (int64_t)nti * ntj * nkb;
+  hipLaunchKernelGGL((k_fcg_zq<TZ>), dim3(nti * ntj * nkb), dim3(NTHREADS), 0, s, L, z, q,
+                     partials, nti, ntj);
+  return hipGetLastError();
+}
+
+template <typename TZ>
+hipError_t launch_fcg_dir(const Lvl<double>& L, const TZ* z, double* p, double* q,
+                          const double* r, const CgState* st, double* partials, int64_t* nblocks,
+                          hipStream_t s) {
+  const int nti = cdiv(L.nx, 64), ntj = cdiv(L.ny, SROWS), nkb = cdiv(L.nz, KSEG);
+  *nblocks = (int64_t)nti * ntj * nkb;
+  hipLaunchKernelGGL((k_fcg_dir<TZ>), dim3(nti * ntj * nkb), dim3(NTHREADS), 0, s, L, z, p, q,
+                     r, st, partials, nti, ntj);
+  return hipGetLastError();
+}
+
+hipError_t launch_fcg_update(const Lvl<double>& L, double* u, double* r, const double* p,
+                             const double* q, float* rdown, const CgState* st, double* partials,
+                             int64_t* nblocks, hipStream_t s) {
+  const int nti = cdiv(L.nx, 64), ntj = cdiv(L.ny, SROWS), nkb = cdiv(L.nz, KSEG);
+  *nblocks = (int64_t)nti * ntj * nkb;
+  hipLaunchKernelGGL(k_fcg_update, dim3(nti * ntj * nkb), dim3(NTHREADS), 0, s, L, u, r, p, q,
+                     rdown, st, partials, nti, ntj);
+  return hipGetLastError();
+}
+
+hipError_t launch_fcg_fin(int which, CgState* st, const double* partials, int64_t nblocks,
+                          double* hist, hipStream_t s) {
+  if (which == 0)
+    hipLaunchKernelGGL(k_fcg_fin_beta, dim3(1), dim3(NTHREADS), 0, s, st, partials, nblocks);
+  else if (which == 1)
+    hipLaunchKernelGGL(k_fcg_fin_alpha, dim3(1), dim3(NTHREADS), 0, s, st, partials, nblocks);
+  else
+    hipLaunchKernelGGL(k_fcg_fin_res, dim3(1), dim3(NTHREADS), 0, s, st, partials, nblocks,
+                       hist);
+  return hipGetLastError();
+}
+
+template hipError_t launch_fcg_zq<double>(const Lvl<double>&, const double*, const double*,
+                                          double*, int64_t*, hipStream_t);
+template hipError_t launch_fcg_zq<float>(const Lvl<double>&, const float*, const double*,
+                                         double*, int64_t*, hipStream_t);
+template hipError_t launch_fcg_dir<double>(const Lvl<double>&, const double*, double*, double*,
+                                           const double*, const CgState*, double*, int64_t*,
+                                           hipStream_t);
+template hipError_t launch_fcg_dir<float>(const Lvl<double>&, const float*, double*, double*,
+                                          const double*, const CgState*, double*, int64_t*,
+                                          hipStream_t);
 
 hipError_t launch_cg_fin1(CgState* st, const double* partials, int64_t nblocks, hipStream_t s) {
   hipLaunchKernelGGL(k_cg_fin1, dim3(1), dim3(NTHREADS), 0, s, st, partials, nblocks);

@@ -147,3 +147,27 @@ def test_solvers_degenerate_cases():
     assert st == G.GMG_ENOCONV and it == 3
     with pytest.raises(G.GmgError):
         G.gmg_solve(ctx, fd, ud, rtol=0.0)
+
+
+@pytest.mark.parametrize("prec_precond", [0, 1])
+def test_flexible_cg_with_multigrid_preconditioner(prec_precond):
+    """Flexible CG with one V-cycle (FP64 or FP32) per iteration.  The oracle has
+    no flexible CG; the result is judged by the FP64 true residual the oracle
+    computes from the returned solution and by its distance to the oracle's
+    tightly converged FP64 multigrid solution."""
+    import paper_1402_3545_amd as G
+    w = W.SMALL
+    ctx, orc, _ = problem(w.nx, w.ny, w.nz, nlevels=w.nlevels, kv=w.kv, seed=w.seed,
+                          kh_model=w.kh_model, prec_precond=prec_precond)
+    f = w.rhs()
+    fd, ud = ctx.to_device(f), ctx.empty()
+    it, rel, hist, st = G.pcg_solve(ctx, fd, ud, rtol=1e-8, maxit=60, precond=1)
+    _, it_mg, _, _ = orc.mg_solve(f, rtol=1e-8, maxit=60)
+    assert st == 0
+    assert it <= it_mg                 # a Krylov wrapper never needs more cycles than plain MG
+    u = ctx.from_device(ud)
+    true_rel = orc.residual_norm2_rows(f, u) ** 0.5 / np.linalg.norm(f)
+    assert true_rel < 1e-8
+    assert true_rel == pytest.approx(rel, rel=1e-6)
+    u_ref, _, _, _ = orc.mg_solve(f, rtol=1e-12, maxit=100)
+    assert np.linalg.norm(u - u_ref) / np.linalg.norm(u_ref) < 1e-6
