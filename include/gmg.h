@@ -156,6 +156,27 @@ int gmg_solve(gmg_ctx *c, const double *f, double *u, double rtol, int maxit, in
 int pcg_solve(gmg_ctx *c, const double *f, double *u, double rtol, int maxit, int precond,
               int *iters, double *relres, double *history, void *stream);
 
+/* Batched solves: `ninst` independent instances (each with its own grid size,
+ * level count and coefficients, inst[i]; rho and ncoarse must agree), each
+ * with `nrhs` right-hand sides, solved together by FP64 iterative refinement
+ * with FP32 V-cycles of Algorithm 1.  Every V-cycle phase of all pairs runs in
+ * one grouped launch per phase; each refinement step is one hipGraph replay;
+ * converged (instance, rhs) pairs are masked on the device.  The context owns
+ * the fields of every pair (about 40 bytes per unknown and right-hand side).
+ * Single-instance entry points reject a batched context. */
+int gmg_batch_setup(const gmg_params *inst, int ninst, int nrhs, void *stream, gmg_ctx **out);
+
+/* Layout of instance `instance` (its finest level), as gmg_field_layout. */
+int gmg_batch_layout(const gmg_ctx *c, int instance, int64_t *ldx, int64_t *elems);
+
+/* f[i*nrhs + r], u[i*nrhs + r]: DEVICE FP64 fields of instance i, rhs r in that
+ * instance's layout; u holds the initial guess and receives the solution.
+ * iters, relres: HOST arrays of ninst*nrhs (may be NULL): cycles and final
+ * relative residual ||f - A u|| / ||f - A u_0|| of each pair.  Synchronises
+ * `stream`.  GMG_ENOCONV if any pair missed rtol within maxit cycles. */
+int gmg_batch_solve(gmg_ctx *c, const double *const *f, double *const *u, double rtol,
+                    int maxit, int *iters, double *relres, void *stream);
+
 /* Per-kernel timing (measurement support; the paper's per-kernel, per-level
  * breakdown tables, Sec. 5.3).  While enabled, every kernel the context
  * launches is bracketed by two HIP events on its launch stream.

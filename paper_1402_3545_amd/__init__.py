@@ -25,8 +25,8 @@ GMG_F64, GMG_F32 = 0, 1
 
 EXPORTS = ("gmg_default_params", "gmg_setup", "gmg_destroy", "gmg_field_layout", "spmv",
            "line_solve", "line_smooth", "gmg_residual", "gmg_restrict_smooth", "gmg_prolongate",
-           "gmg_vcycle", "gmg_solve", "pcg_solve", "gmg_timing_enable", "gmg_timing_read",
-           "gmg_last_error")
+           "gmg_vcycle", "gmg_solve", "pcg_solve", "gmg_batch_setup", "gmg_batch_layout",
+           "gmg_batch_solve", "gmg_timing_enable", "gmg_timing_read", "gmg_last_error")
 
 # kernel ids of the timing facility (gmg_kernel in include/gmg.h)
 KERNELS = ("spmv", "residual", "line_solve", "smooth", "restrict_smooth", "prolongate",
@@ -83,6 +83,10 @@ def _load():
         "gmg_vcycle": (i32, [vp, vp, vp, vp]),
         "gmg_solve": (i32, [vp, vp, vp, dbl, i32, intp, dblp, dblp, vp]),
         "pcg_solve": (i32, [vp, vp, vp, dbl, i32, i32, intp, dblp, dblp, vp]),
+        "gmg_batch_setup": (i32, [C.POINTER(GmgParams), i32, i32, vp, C.POINTER(vp)]),
+        "gmg_batch_layout": (i32, [vp, i32, i64p, i64p]),
+        "gmg_batch_solve": (i32, [vp, C.POINTER(C.c_void_p), C.POINTER(C.c_void_p), dbl, i32, intp,
+                                  dblp, vp]),
         "gmg_timing_enable": (i32, [vp, i32]),
         "gmg_timing_read": (i32, [vp, i32, i32, i32, i64p, dblp]),
         "gmg_last_error": (C.c_char_p, []),
@@ -198,6 +202,108 @@ class GmgContext:
         nx, ny, nz = self.shape(level)
         ldx, _ = self.layout(level)
         return xcontig_to_canonical(t.detach().cpu().double().numpy(), nx, ny, nz, ldx)
+
+
+def _params(nx, ny, nz, nlevels=1, kv=1.0, sigma=1.0, zfaces=None, kh=None, bc_v=0,
+            rho=2.0 / 3.0, ncoarse=2, prec_precond=GMG_F64, bc_h=0, keep=None):
+    p = GmgParams()
+    _lib.gmg_default_params(C.byref(p))
+    p.nx, p.ny, p.nz, p.nlevels = int(nx), int(ny), int(nz), int(nlevels)
+    p.bc_h, p.bc_v = int(bc_h), int(bc_v)
+    p.kv, p.sigma, p.rho, p.ncoarse = float(kv), float(sigma), float(rho), int(ncoarse)
+    p.prec_precond = int(prec_precond)
+    if zfaces is not None:
+        z = np.ascontiguousarray(zfaces, dtype=np.float64)
+        if z.size != nz + 1:
+            raise ValueError("zfaces needs nz+1 entries")
+        keep.append(z)
+        p.zfaces = z.ctypes.data_as(C.POINTER(C.c_double))
+    if kh is not None:
+        k = np.ascontiguousarray(kh, dtype=np.float64)
+        if k.size != nx * ny:
+            raise ValueError("kh needs nx*ny entries")
+        keep.append(k)
+        p.kh = k.ctypes.data_as(C.POINTER(C.c_double))
+    return p
+
+
+class GmgBatch:
+    """A batched context: independent instances (dicts of GmgContext keyword
+    arguments), each with nrhs right-hand sides, solved together."""
+
+    def __init__(self, instances, nrhs=1, stream=None):
+        keep = []
+        arr = (GmgParams * len(instances))()
+        for q, kw in enumerate(instances):
+            arr[q] = _params(keep=keep, **kw)
+        h = C.c_void_p()
+        _check(_lib.gmg_batch_setup(arr, len(instances), int(nrhs), _stream(stream),
+                                    C.byref(h)))
+        self._h = h
+        self.ninst, self.nrhs = len(instances), int(nrhs)
+        self.shapes = [(kw["nx"], kw["ny"], kw["nz"]) for kw in instances]
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _lib.gmg_destroy(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def layout(self, instance):
+        ldx, elems = C.c_int64(), C.c_int64()
+        _check(_lib.gmg_batch_layout(self._h, int(instance), C.byref(ldx), C.byref(elems)))
+        return ldx.value, elems.value
+
+    def to_device(self, canonical, instance):
+        import torch
+        nx, ny, nz = self.shapes[instance]
+        ldx, _ = self.layout(instance)
+        return torch.from_numpy(canonical_to_xcontig(np.asarray(canonical, dtype=np.float64),
+                                                     nx, ny, nz, ldx)).cuda()
+
+    def from_device(self, t, instance):
+        nx, ny, nz = self.shapes[instance]
+        ldx, _ = self.layout(instance)
+        return xcontig_to_canonical(t.detach().cpu().numpy(), nx, ny, nz, ldx)
+
+    def empty(self, instance):
+        import torch
+        return torch.zeros(self.layout(instance)[1], dtype=torch.float64, device="cuda")
+
+
+def gmg_batch_setup(instances, nrhs=1, stream=None) -> GmgBatch:
+    return GmgBatch(instances, nrhs, stream)
+
+
+def gmg_batch_layout(batch, instance):
+    return batch.layout(instance)
+
+
+def gmg_batch_solve(batch, fs, us, rtol=1e-8, maxit=100, stream=None, check=True):
+    """fs, us: lists of ninst*nrhs FP64 device tensors (pair i*nrhs + r).
+    Returns (iters array, relres array, status)."""
+    n = batch.ninst * batch.nrhs
+    if len(fs) != n or len(us) != n:
+        raise ValueError(f"need {n} right-hand sides and solutions")
+    fp = (C.c_void_p * n)(*[t.data_ptr() for t in fs])
+    up = (C.c_void_p * n)(*[t.data_ptr() for t in us])
+    it = np.zeros(n, dtype=np.int32)
+    rel = np.zeros(n)
+    st = _lib.gmg_batch_solve(batch.handle, fp, up, float(rtol), int(maxit),
+                              it.ctypes.data_as(C.POINTER(C.c_int)),
+                              rel.ctypes.data_as(C.POINTER(C.c_double)), _stream(stream))
+    if check and st != GMG_ENOCONV:
+        _check(st)
+    return it, rel, st
 
 
 def gmg_setup(**kw) -> GmgContext:

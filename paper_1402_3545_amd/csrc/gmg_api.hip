@@ -57,7 +57,9 @@ int64_t round_up(int64_t a, int64_t m) { return (a + m - 1) / m * m; }
 
 hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
 
-bool level_ok(const gmg_ctx* c, int level) { return c && level >= 0 && level < c->nlevels; }
+bool level_ok(const gmg_ctx* c, int level) {
+  return c && !c->batch && level >= 0 && level < c->nlevels;
+}
 
 int validate(const gmg_params* p) {
   if (!p) return fail(GMG_EINVAL, "params is NULL");
@@ -106,6 +108,9 @@ int upload(T** dst, const std::vector<double>& src) {
 
 namespace gmg {
 
+int set_error(int code, const char* msg) { return fail(code, "%s", msg); }
+int validate_params(const gmg_params* p) { return validate(p); }
+
 template <>
 Lvl<double> view<double>(const gmg_ctx* c, int d) {
   const LevelBuf& L = c->lev[d];
@@ -137,6 +142,7 @@ void gmg_default_params(gmg_params* p) {
 
 int gmg_destroy(gmg_ctx* c) {
   if (!c) return GMG_OK;
+  if (c->batch) gmg::batch_free(c->batch);
   for (LevelBuf& L : c->lev) {
     dfree(L.cx64); dfree(L.cy64); dfree(L.sub64); dfree(L.sup64); dfree(L.dg64);
     dfree(L.cx32); dfree(L.cy32); dfree(L.sub32); dfree(L.sup32); dfree(L.dg32);
@@ -159,6 +165,15 @@ int gmg_destroy(gmg_ctx* c) {
 }
 
 int gmg_setup(const gmg_params* p, void* stream, gmg_ctx** out) {
+  return gmg::setup_impl(p, stream, out, true);
+}
+
+}  // extern "C"
+
+// Context construction; with fields = false only the coefficients (profiles,
+// face couplings) and small scratch are built -- the batched solver owns the
+// fields of its instances itself.
+int gmg::setup_impl(const gmg_params* p, void* stream, gmg_ctx** out, bool fields) {
   if (!out) return fail(GMG_EINVAL, "out is NULL");
   *out = nullptr;
   int st = validate(p);
@@ -238,19 +253,21 @@ int gmg_setup(const gmg_params* p, void* stream, gmg_ctx** out) {
       return cleanup(st);
     const size_t bytes = (size_t)L.elems * c->esize;
     hipError_t e = hipSuccess;
+    if (!fields) continue;
     if (d > 0) {
       if ((e = hipMalloc(&L.u, bytes)) != hipSuccess || (e = hipMalloc(&L.f, bytes)) != hipSuccess)
         return cleanup(fail(GMG_ENOMEM, "level %d fields: %s", d, hipGetErrorString(e)));
     }
-    if ((e = hipMalloc(&L.ualt, bytes)) != hipSuccess || (e = hipMalloc(&L.r, bytes)) != hipSuccess)
+    if ((e = hipMalloc(&L.ualt, bytes)) != hipSuccess)
       return cleanup(fail(GMG_ENOMEM, "level %d fields: %s", d, hipGetErrorString(e)));
   }
   const int64_t n0 = c->lev[0].elems;
   hipError_t e;
-  if ((e = dmalloc(&c->vr, n0)) || (e = dmalloc(&c->vz, n0)) || (e = dmalloc(&c->vp, n0)) ||
-      (e = dmalloc(&c->vq, n0)) || (e = dmalloc(&c->vt, n0)))
+  if (fields && ((e = dmalloc(&c->vr, n0)) || (e = dmalloc(&c->vz, n0)) ||
+                 (e = dmalloc(&c->vp, n0)) || (e = dmalloc(&c->vq, n0)) ||
+                 (e = dmalloc(&c->vt, n0))))
     return cleanup(fail(GMG_ENOMEM, "solver vectors: %s", hipGetErrorString(e)));
-  if (p->prec_precond == GMG_F32) {
+  if (fields && p->prec_precond == GMG_F32) {
     if ((e = dmalloc(&c->er32, n0)) || (e = dmalloc(&c->eu32, n0)))
       return cleanup(fail(GMG_ENOMEM, "FP32 vectors: %s", hipGetErrorString(e)));
   }
@@ -271,7 +288,7 @@ int gmg_setup(const gmg_params* p, void* stream, gmg_ctx** out) {
         return cleanup(hip_fail(e, "hipMemsetAsync"));
   }
   for (double* q : {c->vr, c->vz, c->vp, c->vq, c->vt})
-    if ((e = hipMemsetAsync(q, 0, (size_t)n0 * 8, s)) != hipSuccess)
+    if (q && (e = hipMemsetAsync(q, 0, (size_t)n0 * 8, s)) != hipSuccess)
       return cleanup(hip_fail(e, "hipMemsetAsync"));
   for (float* q : {c->er32, c->eu32})
     if (q && (e = hipMemsetAsync(q, 0, (size_t)n0 * 4, s)) != hipSuccess)
@@ -280,6 +297,8 @@ int gmg_setup(const gmg_params* p, void* stream, gmg_ctx** out) {
   *out = c;
   return GMG_OK;
 }
+
+extern "C" {
 
 int gmg_field_layout(const gmg_ctx* c, int level, int64_t* ldx, int64_t* elems) {
   if (!level_ok(c, level)) return fail(GMG_EINVAL, "bad context or level %d", level);
@@ -372,8 +391,17 @@ hipError_t smooth_steps(gmg_ctx* c, int d, const T* f, T* cur, T* other, int n, 
 }
 
 // One V(1,1) cycle of Algorithm 1 in precision T on the caller's (f0, u0).
+//  zero_guess:  u0 is taken as 0 (its content is not read); the first
+//               smoothing step is then rho M^-1 f0, a scaled line solve.
+//  presmoothed: the caller has already put the finest level's pre-smoothed
+//               iterate into lev[0].ualt (see the multigrid solve, which
+//               takes its convergence norm from that smoothing step).
+// The fine-level residual is fused with the restriction (f_c = R(f - A u),
+// the residual itself is never stored), so each coarse level starts with the
+// scaled line solve u_c = rho M_c^-1 f_c: the values of ResSmooth.
 template <typename T>
-int vcycle_impl(gmg_ctx* c, const T* f0, T* u0, hipStream_t s) {
+int vcycle_impl(gmg_ctx* c, const T* f0, T* u0, hipStream_t s, bool zero_guess = false,
+                bool presmoothed = false) {
   const int L = c->nlevels;
   const int P = prec_of<T>();
   const T rho = (T)c->p.rho;
@@ -381,31 +409,38 @@ int vcycle_impl(gmg_ctx* c, const T* f0, T* u0, hipStream_t s) {
   std::vector<const T*> fl(L, nullptr);
   fl[0] = f0;
   for (int d = 1; d < L; ++d) fl[d] = static_cast<const T*>(c->lev[d].f);
+  T* ualt0 = static_cast<T*>(c->lev[0].ualt);
+  const Lvl<T> V0 = gmg::view<T>(c, 0);
+  // finest-level pre-smoothing into ualt0
+  int pre_done = 0;
+  if (presmoothed) {
+    pre_done = 1;
+  } else if (zero_guess) {
+    HIP_TRY(timed(c, GMG_K_LINE_SOLVE, 0, P, s,
+                  [&] { return gmg::launch_line_solve_scaled<T>(V0, f0, ualt0, rho, s); }));
+    pre_done = 1;
+  }
   if (L == 1) {
     T* res = nullptr;
-    HIP_TRY(smooth_steps<T>(c, 0, f0, u0, static_cast<T*>(c->lev[0].ualt), c->p.ncoarse, rho, s,
-                            &res));
+    T* from = pre_done ? ualt0 : u0;
+    T* other = pre_done ? u0 : ualt0;
+    HIP_TRY(smooth_steps<T>(c, 0, f0, from, other, c->p.ncoarse - pre_done, rho, s, &res));
     if (res != u0)
       HIP_TRY(hipMemcpyAsync(u0, res, (size_t)c->lev[0].elems * sizeof(T),
                              hipMemcpyDeviceToDevice, s));
     return GMG_OK;
   }
-  // descend: pre-smoothing (Smooth on the finest level, ResSmooth below) and
-  // the residual that the next level restricts
+  if (!pre_done)
+    HIP_TRY(timed(c, GMG_K_SMOOTH, 0, P, s,
+                  [&] { return gmg::launch_smooth<T>(V0, f0, u0, ualt0, rho, s); }));
+  cur[0] = ualt0;
+  // descend
   for (int d = 0; d < L; ++d) {
     const Lvl<T> V = gmg::view<T>(c, d);
     LevelBuf& B = c->lev[d];
-    if (d == 0) {
-      HIP_TRY(timed(c, GMG_K_SMOOTH, 0, P, s, [&] {
-        return gmg::launch_smooth<T>(V, f0, u0, static_cast<T*>(B.ualt), rho, s);
-      }));
-      cur[0] = static_cast<T*>(B.ualt);
-    } else {
-      const Lvl<T> F = gmg::view<T>(c, d - 1);
-      const T* rf = static_cast<const T*>(c->lev[d - 1].r);
+    if (d > 0) {
       HIP_TRY(timed(c, GMG_K_RESTRICT_SMOOTH, d, P, s, [&] {
-        return gmg::launch_restrict_smooth<T>(V, F, rf, static_cast<T*>(B.f),
-                                              static_cast<T*>(B.u), rho, s);
+        return gmg::launch_line_solve_scaled<T>(V, fl[d], static_cast<T*>(B.u), rho, s);
       }));
       cur[d] = static_cast<T*>(B.u);
     }
@@ -413,9 +448,10 @@ int vcycle_impl(gmg_ctx* c, const T* f0, T* u0, hipStream_t s) {
       T* other = cur[d] == B.u ? static_cast<T*>(B.ualt) : static_cast<T*>(B.u);
       HIP_TRY(smooth_steps<T>(c, d, fl[d], cur[d], other, c->p.ncoarse - 1, rho, s, &cur[d]));
     } else {
+      const Lvl<T> C = gmg::view<T>(c, d + 1);
+      T* fc = static_cast<T*>(c->lev[d + 1].f);
       HIP_TRY(timed(c, GMG_K_RESIDUAL, d, P, s, [&] {
-        return gmg::launch_stencil<T>(V, Stencil::RESIDUAL, cur[d], fl[d], static_cast<T*>(B.r),
-                                      nullptr, nullptr, nullptr, s);
+        return gmg::launch_resrestrict<T>(V, C, cur[d], fl[d], fc, s);
       }));
     }
   }
@@ -450,6 +486,17 @@ int line_smooth_t(gmg_ctx* c, int level, const T* f, T* u, int nsweeps, T rho, h
   if (res != u)
     HIP_TRY(hipMemcpyAsync(u, res, (size_t)B.elems * sizeof(T), hipMemcpyDeviceToDevice, s));
   if (!own) HIP_TRY(hipFreeAsync(tmp, s));
+  return GMG_OK;
+}
+
+// Sum nb per-workgroup partials on the device and read the scalar back.
+int reduce_read(gmg_ctx* c, int64_t nb, double* out, hipStream_t s) {
+  double* dst = c->partials + c->max_partials;
+  HIP_TRY(timed(c, GMG_K_REDUCE, 0, GMG_F64, s,
+                [&] { return gmg::launch_reduce(c->partials, nb, 1, dst, s); }));
+  HIP_TRY(hipMemcpyAsync(c->hscal, dst, sizeof(double), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  *out = c->hscal[0];
   return GMG_OK;
 }
 
@@ -517,10 +564,8 @@ int fcg_impl(gmg_ctx* c, const double* f, double* u, double rtol, int maxit, int
                 [&] { return gmg::launch_fill<double>(c->vq, n0, 0.0, s); }));
   TZ* z = mixed ? reinterpret_cast<TZ*>(c->eu32) : reinterpret_cast<TZ*>(c->vz);
   const TZ* rin = mixed ? reinterpret_cast<const TZ*>(c->er32) : reinterpret_cast<const TZ*>(c->vr);
-  const int P = mixed ? GMG_F32 : GMG_F64;
   for (int it = 1; it <= maxit; ++it) {
-    HIP_TRY(timed(c, GMG_K_AUX, 0, P, s, [&] { return gmg::launch_fill<TZ>(z, n0, TZ(0), s); }));
-    if ((st = vcycle_impl<TZ>(c, rin, z, s))) return st;
+    if ((st = vcycle_impl<TZ>(c, rin, z, s, true, false))) return st;
     int64_t nb = 0;
     HIP_TRY(timed(c, GMG_K_AUX, 0, GMG_F64, s,
                   [&] { return gmg::launch_fcg_zq<TZ>(V, z, c->vq, c->partials, &nb, s); }));
@@ -562,7 +607,7 @@ int fcg_impl(gmg_ctx* c, const double* f, double* u, double rtol, int maxit, int
 extern "C" {
 
 int gmg_timing_enable(gmg_ctx* c, int enable) {
-  if (!c) return fail(GMG_EINVAL, "context is NULL");
+  if (!c || c->batch) return fail(GMG_EINVAL, "context is NULL or batched");
   if (enable) {
     c->pending.clear();
     c->evused = 0;
@@ -575,7 +620,7 @@ int gmg_timing_enable(gmg_ctx* c, int enable) {
 
 int gmg_timing_read(gmg_ctx* c, int kernel, int level, int prec, int64_t* count,
                     double* total_ms) {
-  if (!c) return fail(GMG_EINVAL, "context is NULL");
+  if (!c || c->batch) return fail(GMG_EINVAL, "context is NULL or batched");
   if (kernel < 0 || kernel >= GMG_K_COUNT) return fail(GMG_EINVAL, "bad kernel id %d", kernel);
   if (level < -1 || level >= c->nlevels) return fail(GMG_EINVAL, "bad level %d", level);
   int st;
@@ -683,7 +728,7 @@ int gmg_residual(gmg_ctx* c, int level, int prec, const void* f, const void* u, 
 
 int gmg_restrict_smooth(gmg_ctx* c, int level, int prec, const void* rf, void* fc, void* uc,
                         double rho, void* stream) {
-  if (!c || level < 1 || level >= c->nlevels)
+  if (!c || c->batch || level < 1 || level >= c->nlevels)
     return fail(GMG_EINVAL, "restrict_smooth needs a coarse level in [1, nlevels)");
   int st;
   if ((st = check_prec(prec)) || (st = check_ptrs({rf, fc, uc}))) return st;
@@ -706,7 +751,7 @@ int gmg_restrict_smooth(gmg_ctx* c, int level, int prec, const void* rf, void* f
 }
 
 int gmg_prolongate(gmg_ctx* c, int level, int prec, const void* uc, void* uf, void* stream) {
-  if (!c || level < 1 || level >= c->nlevels)
+  if (!c || c->batch || level < 1 || level >= c->nlevels)
     return fail(GMG_EINVAL, "prolongate needs a coarse level in [1, nlevels)");
   int st;
   if ((st = check_prec(prec)) || (st = check_ptrs({uc, uf}))) return st;
@@ -727,7 +772,7 @@ int gmg_prolongate(gmg_ctx* c, int level, int prec, const void* uc, void* uf, vo
 }
 
 int gmg_vcycle(gmg_ctx* c, const void* f, void* u, void* stream) {
-  if (!c) return fail(GMG_EINVAL, "context is NULL");
+  if (!c || c->batch) return fail(GMG_EINVAL, "context is NULL or batched");
   int st;
   if ((st = check_ptrs({f, u}))) return st;
   if (f == u) return fail(GMG_EINVAL, "f and u must not overlap");
@@ -738,50 +783,92 @@ int gmg_vcycle(gmg_ctx* c, const void* f, void* u, void* stream) {
 
 int gmg_solve(gmg_ctx* c, const double* f, double* u, double rtol, int maxit, int* iters,
               double* relres, double* history, void* stream) {
-  if (!c) return fail(GMG_EINVAL, "context is NULL");
+  if (!c || c->batch) return fail(GMG_EINVAL, "context is NULL or batched");
   int st;
   if ((st = check_ptrs({f, u}))) return st;
   if (!(rtol > 0.0)) return fail(GMG_EINVAL, "rtol must be > 0");
   if (maxit < 0) return fail(GMG_EINVAL, "maxit must be >= 0");
   if (f == u) return fail(GMG_EINVAL, "f and u must not overlap");
   hipStream_t s = as_stream(stream);
-  const bool mixed = c->p.prec_precond == GMG_F32;
-  const int64_t n0 = c->lev[0].elems;
-  double rr0 = 0.0, rr = 0.0;
-  if ((st = residual_norm2<double>(c, f, u, c->vr, mixed ? c->er32 : nullptr, &rr0, s))) return st;
   if (iters) *iters = 0;
-  if (relres) *relres = rr0 > 0.0 ? 1.0 : 0.0;
   if (history) history[0] = 1.0;
+  const Lvl<double> V0 = gmg::view<double>(c, 0);
+  double rr0 = 0.0, rr = 0.0;
+  if (c->p.prec_precond == GMG_F64) {
+    // The first smoothing step of every cycle computes f - A u of the current
+    // iterate in its forward sweep; its norm is the convergence test of the
+    // previous cycle, so no separate residual pass is needed.  The step writes
+    // lev[0].ualt, so u still holds the tested iterate when the loop stops.
+    double* ualt0 = static_cast<double*>(c->lev[0].ualt);
+    const double rho = c->p.rho;
+    for (int it = 0;; ++it) {
+      int64_t nb = 0;
+      HIP_TRY(timed(c, GMG_K_SMOOTH, 0, GMG_F64, s, [&] {
+        return gmg::launch_smooth_norm<double>(V0, f, u, ualt0, rho, c->partials, &nb, s);
+      }));
+      if ((st = reduce_read(c, nb, &rr, s))) return st;
+      if (it == 0) {
+        rr0 = rr;
+        if (relres) *relres = rr0 > 0.0 ? 1.0 : 0.0;
+        if (!isfinite(rr0)) return fail(GMG_ENOCONV, "initial residual is not finite");
+        if (rr0 == 0.0) return GMG_OK;
+      } else {
+        const double rel = sqrt(rr / rr0);
+        if (history) history[it] = rel;
+        if (iters) *iters = it;
+        if (relres) *relres = rel;
+        if (!isfinite(rel)) return fail(GMG_ENOCONV, "residual became non-finite at cycle %d", it);
+        if (rel < rtol) return GMG_OK;
+      }
+      if (it == maxit) break;
+      if ((st = vcycle_impl<double>(c, f, u, s, false, true))) return st;
+    }
+    return fail(GMG_ENOCONV, "no convergence to %g in %d cycles", rtol, maxit);
+  }
+  // FP64 iterative refinement with FP32 cycles: e = V32(r32) from a zero guess,
+  // then u' = u + e, r = f - A u', r32 and ||r||^2 in one fused pass.  The
+  // iterate alternates between the caller's u and an internal buffer.
+  if ((st = residual_norm2<double>(c, f, u, c->vr, c->er32, &rr0, s))) return st;
+  if (relres) *relres = rr0 > 0.0 ? 1.0 : 0.0;
   if (!isfinite(rr0)) return fail(GMG_ENOCONV, "initial residual is not finite");
   if (rr0 == 0.0) return GMG_OK;
-  const double r0 = sqrt(rr0);
+  double* ucur = u;
+  double* unext = c->vt;
+  int status = GMG_ENOCONV;
   for (int it = 1; it <= maxit; ++it) {
-    if (!mixed) {
-      if ((st = vcycle_impl<double>(c, f, u, s))) return st;
-      if ((st = residual_norm2<double>(c, f, u, c->vr, nullptr, &rr, s))) return st;
-    } else {
-      // FP64 iterative refinement: e = V32(r) from a zero guess, u += e, new
-      // FP64 residual (and its FP32 copy) in one pass
-      HIP_TRY(timed(c, GMG_K_AUX, 0, GMG_F32, s,
-                    [&] { return gmg::launch_fill<float>(c->eu32, n0, 0.0f, s); }));
-      if ((st = vcycle_impl<float>(c, c->er32, c->eu32, s))) return st;
-      HIP_TRY(timed(c, GMG_K_AUX, 0, GMG_F64, s,
-                    [&] { return gmg::launch_add_f32_to_f64(u, c->eu32, n0, s); }));
-      if ((st = residual_norm2<double>(c, f, u, c->vr, c->er32, &rr, s))) return st;
-    }
-    const double rel = sqrt(rr) / r0;
+    if ((st = vcycle_impl<float>(c, c->er32, c->eu32, s, true, false))) return st;
+    int64_t nb = 0;
+    HIP_TRY(timed(c, GMG_K_RESIDUAL, 0, GMG_F64, s, [&] {
+      return gmg::launch_correct_residual(V0, ucur, c->eu32, f, unext, c->er32, c->partials, &nb,
+                                          s);
+    }));
+    std::swap(ucur, unext);
+    if ((st = reduce_read(c, nb, &rr, s))) return st;
+    const double rel = sqrt(rr / rr0);
     if (history) history[it] = rel;
     if (iters) *iters = it;
     if (relres) *relres = rel;
-    if (!isfinite(rel)) return fail(GMG_ENOCONV, "residual became non-finite at cycle %d", it);
-    if (rel < rtol) return GMG_OK;
+    if (!isfinite(rel)) {
+      status = GMG_EINVAL;  // marker: non-finite
+      break;
+    }
+    if (rel < rtol) {
+      status = GMG_OK;
+      break;
+    }
   }
+  if (ucur != u)
+    HIP_TRY(hipMemcpyAsync(u, ucur, (size_t)c->lev[0].elems * sizeof(double),
+                           hipMemcpyDeviceToDevice, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  if (status == GMG_OK) return GMG_OK;
+  if (status == GMG_EINVAL) return fail(GMG_ENOCONV, "residual became non-finite");
   return fail(GMG_ENOCONV, "no convergence to %g in %d cycles", rtol, maxit);
 }
 
 int pcg_solve(gmg_ctx* c, const double* f, double* u, double rtol, int maxit, int precond,
               int* iters, double* relres, double* history, void* stream) {
-  if (!c) return fail(GMG_EINVAL, "context is NULL");
+  if (!c || c->batch) return fail(GMG_EINVAL, "context is NULL or batched");
   int st;
   if ((st = check_ptrs({f, u}))) return st;
   if (!(rtol > 0.0)) return fail(GMG_EINVAL, "rtol must be > 0");

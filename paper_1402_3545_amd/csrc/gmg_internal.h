@@ -40,6 +40,39 @@ struct CgState {
   int iter, done, maxit, status;     // status: 0 running/converged, 2 breakdown
 };
 
+// One work item of a grouped launch: one kernel applied to one level of one
+// (instance, right-hand side) pair.  Items of a launch are sorted by blk0, the
+// item's first workgroup.
+template <typename T>
+struct GItem {
+  Lvl<T> L;      // level the kernel works on (resrestrict, prolongate: the FINE level)
+  Lvl<T> X;      // resrestrict, prolongate: the COARSE level
+  const T* a;    // line: rhs (solve) or u (smooth); resrestrict: u; prolongate: u_c
+  const T* b;    // smooth, resrestrict: f
+  T* o;          // line: output; resrestrict: f_c; prolongate: u_f (updated)
+  int nti, ntj;  // tiles of the item
+  int blk0;      // first workgroup of the item in its launch
+  int pair;      // (instance, rhs) index: activity mask, partial-sum segment
+};
+
+// Grouped FP64 refinement step u' = u + e, r = f - A u' (FP32 copy), ||r||^2.
+struct GItemCR {
+  Lvl<double> L;
+  const double* u;
+  const float* e;
+  const double* f;
+  double* uout;
+  float* r32;
+  int nti, ntj, blk0, pair;
+};
+
+// Per-pair state of a batched solve (device).
+struct PairState {
+  double rr0, rr, thresh2;
+  int iters, maxit, status;   // status: 0 converged / running, 1 maxit, 2 non-finite
+  int blk0, nblk;             // partial-sum segment of the pair in the residual launch
+};
+
 // One multigrid level as owned by the context.
 struct LevelBuf {
   int nx, ny, nz;
@@ -62,8 +95,13 @@ struct gmg_timed_launch {
   hipEvent_t a, b;
 };
 
+namespace gmg {
+struct Batch;
+}
+
 struct gmg_ctx {
   gmg_params p;
+  gmg::Batch* batch = nullptr;       // non-null: a batched context (gmg_batch_setup)
   // per-kernel timing
   bool timing = false;
   std::vector<hipEvent_t> evpool;
@@ -94,6 +132,11 @@ namespace gmg {
 template <typename T>
 Lvl<T> view(const gmg_ctx* c, int d);
 
+int setup_impl(const gmg_params* p, void* stream, gmg_ctx** out, bool fields);
+int set_error(int code, const char* msg);
+int validate_params(const gmg_params* p);
+void batch_free(Batch* b);
+
 // ---- launchers (kernels.hip); every launcher returns the hipError_t of the launch
 enum class Stencil { SPMV = 0, RESIDUAL = 1, RESIDUAL_NORM = 2, RESIDUAL_NORM_DOWN = 3 };
 
@@ -111,6 +154,25 @@ hipError_t launch_smooth(const Lvl<T>& L, const T* f, const T* uin, T* uout, T r
 template <typename T>
 hipError_t launch_restrict_smooth(const Lvl<T>& C, const Lvl<T>& F, const T* rf, T* fc, T* uc,
                                   T rho, hipStream_t s);
+
+// z = scale * M^-1 r (first smoothing step from a zero guess when scale = rho)
+template <typename T>
+hipError_t launch_line_solve_scaled(const Lvl<T>& L, const T* r, T* z, T scale, hipStream_t s);
+
+// Smooth that also returns ||f - A u_in||^2 per workgroup (line_blocks partials)
+template <typename T>
+hipError_t launch_smooth_norm(const Lvl<T>& L, const T* f, const T* uin, T* uout, T rho,
+                              double* partials, int64_t* nblocks, hipStream_t s);
+
+// fc = R (f - A u): residual of level F restricted to level C, r never stored
+template <typename T>
+hipError_t launch_resrestrict(const Lvl<T>& F, const Lvl<T>& C, const T* u, const T* f, T* fc,
+                              hipStream_t s);
+
+// uout = u + e, r32 = f - A uout, partial ||r||^2
+hipError_t launch_correct_residual(const Lvl<double>& L, const double* u, const float* e,
+                                   const double* f, double* uout, float* r32, double* partials,
+                                   int64_t* nblocks, hipStream_t s);
 
 template <typename T>
 hipError_t launch_prolongate(const Lvl<T>& C, const Lvl<T>& F, const T* uc, T* uf,
@@ -147,6 +209,22 @@ hipError_t launch_fcg_fin(int which, CgState* st, const double* partials, int64_
 template <typename T>
 hipError_t launch_fill(T* p, int64_t n, T v, hipStream_t s);
 hipError_t launch_add_f32_to_f64(double* u, const float* e, int64_t n, hipStream_t s);
+
+// grouped launches (batched solves)
+enum class GKind { LINE_SOLVE = 0, SMOOTH = 1, RESRESTRICT = 2, PROLONGATE = 3 };
+hipError_t launch_grouped_f32(GKind kind, int half, const GItem<float>* items, int nitems,
+                              int nblocks, const int* active, float rho, hipStream_t s);
+hipError_t launch_grouped_cr(const GItemCR* items, int nitems, int nblocks, const int* active,
+                             double* partials, hipStream_t s);
+// one workgroup per pair: sum its partials, update its state and activity
+hipError_t launch_pair_reduce(PairState* ps, int* active, const double* partials, int npairs,
+                              int init, hipStream_t s);
+// tiles of each kernel shape for a level of nx x ny x nz
+int64_t line_tiles_x(int nx);
+int64_t line_tiles_y(int ny);
+int64_t stencil_tiles_x(int nx);
+int64_t stencil_tiles_y(int ny);
+int64_t stencil_tiles_k(int nz);
 
 int64_t stencil_blocks(int nx, int ny, int nz);
 int64_t line_blocks(int nx, int ny);

@@ -151,7 +151,13 @@ __global__ __launch_bounds__(NTHREADS) void k_stencil(Lvl<T> L, const T* __restr
 // ---------------------------------------------------------------------------
 // Line kernels
 // ---------------------------------------------------------------------------
-enum LineMode { LINE_SOLVE = 0, LINE_SMOOTH = 1, LINE_RESTRICT_SMOOTH = 2, LINE_CG = 3 };
+enum LineMode {
+  LINE_SOLVE = 0,          // z = rho M^-1 r (rho = 1 for the plain line solve)
+  LINE_SMOOTH = 1,         // u' = u + rho M^-1 (f - A u)
+  LINE_RESTRICT_SMOOTH = 2,
+  LINE_CG = 3,
+  LINE_SMOOTH_NORM = 4     // LINE_SMOOTH plus ||f - A u||^2 partials
+};
 
 template <typename T>
 struct LineArgs {
@@ -160,11 +166,11 @@ struct LineArgs {
   T* rw;              // CG: r (updated in place)
   T* o0;              // SOLVE: z; SMOOTH: u_out; RESTRICT_SMOOTH: coarse u; CG: z
   T* o1;              // RESTRICT_SMOOTH: coarse f
-  T rho;
+  T rho;              // SOLVE: output scale; SMOOTH*, RESTRICT_SMOOTH: damping
   Lvl<T> F;           // RESTRICT_SMOOTH: the fine level
   const CgState* st;  // CG
   int init;           // CG: initial step (alpha = 0)
-  double* partials;   // CG: <r,r>, <r,z> per workgroup
+  double* partials;   // CG: <r,r>, <r,z>; SMOOTH_NORM: ||f - A u||^2 per workgroup
 };
 
 template <typename T>
@@ -174,12 +180,11 @@ struct Vec2<double> { using type = double2; };
 template <>
 struct Vec2<float> { using type = float2; };
 
+// Body of the line kernels for tile b of a level (tiles of 32 columns x LROWS
+// rows, nti tiles across).  Block partials go to a.partials[blockIdx.x].
 template <typename T, int HALF, int MODE>
-__global__ __launch_bounds__(NTHREADS) void k_line(Lvl<T> L, LineArgs<T> a, int nti, int ntj) {
-  if constexpr (MODE == LINE_CG) {
-    if (a.st->done) return;  // uniform: the solve has already stopped
-  }
-  const int b = xcd_remap(blockIdx.x, gridDim.x);
+__device__ __forceinline__ void line_body(const Lvl<T>& L, const LineArgs<T>& a, int nti,
+                                          int b) {
   const int ti = b % nti;
   const int tj = b / nti;
   const int lane = threadIdx.x & 63;
@@ -214,7 +219,8 @@ __global__ __launch_bounds__(NTHREADS) void k_line(Lvl<T> L, LineArgs<T> a, int 
   T cp[HALF], dp[HALF];
   T cprev = T(0), dprev = T(0);
   T uprv = T(0), ucur = T(0);
-  if constexpr (MODE == LINE_SMOOTH) ucur = a.a[c.base + (int64_t)k0 * ldx];
+  constexpr bool kSmooth = (MODE == LINE_SMOOTH || MODE == LINE_SMOOTH_NORM);
+  if constexpr (kSmooth) ucur = a.a[c.base + (int64_t)k0 * ldx];
 
 #pragma unroll
   for (int s = 0; s < HALF; ++s) {
@@ -228,10 +234,12 @@ __global__ __launch_bounds__(NTHREADS) void k_line(Lvl<T> L, LineArgs<T> a, int 
       T rhs;
       if constexpr (MODE == LINE_SOLVE) {
         rhs = a.a[o];
-      } else if constexpr (MODE == LINE_SMOOTH) {
+      } else if constexpr (kSmooth) {
         const T unxt = a.a[o + sdir];
         const T au = diag * ucur - dzk * hsum(c, a.a, o) + cpv * uprv + cnx * unxt;
         rhs = a.b[o] - au;
+        if constexpr (MODE == LINE_SMOOTH_NORM)
+          if (active) acc_rr += (double)rhs * (double)rhs;
         uprv = ucur;
         ucur = unxt;
       } else if constexpr (MODE == LINE_RESTRICT_SMOOTH) {
@@ -271,8 +279,8 @@ __global__ __launch_bounds__(NTHREADS) void k_line(Lvl<T> L, LineArgs<T> a, int 
       const int64_t o = c.base + (int64_t)k * ldx;
       if (active) {
         if constexpr (MODE == LINE_SOLVE) {
-          a.o0[o] = x;
-        } else if constexpr (MODE == LINE_SMOOTH) {
+          a.o0[o] = a.rho * x;
+        } else if constexpr (kSmooth) {
           a.o0[o] = a.a[o] + a.rho * x;
         } else if constexpr (MODE == LINE_RESTRICT_SMOOTH) {
           a.o0[o] = a.rho * x;
@@ -287,16 +295,173 @@ __global__ __launch_bounds__(NTHREADS) void k_line(Lvl<T> L, LineArgs<T> a, int 
     double v[2] = {acc_rr, acc_rz};
     block_partials<2>(v, a.partials);
   }
+  if constexpr (MODE == LINE_SMOOTH_NORM) {
+    double v[1] = {acc_rr};
+    block_partials<1>(v, a.partials);
+  }
+}
+
+template <typename T, int HALF, int MODE>
+__global__ __launch_bounds__(NTHREADS) void k_line(Lvl<T> L, LineArgs<T> a, int nti, int ntj) {
+  if constexpr (MODE == LINE_CG) {
+    if (a.st->done) return;  // uniform: the solve has already stopped
+  }
+  line_body<T, HALF, MODE>(L, a, nti, xcd_remap(blockIdx.x, gridDim.x));
+}
+
+// ---------------------------------------------------------------------------
+// Residual fused with the restriction: f_c(I,J,k) = sum over the four fine
+// children (2I+a, 2J+b) of (f - A u).  One thread per coarse column; the fine
+// residual itself is never stored.  A wavefront covers 64 coarse = 128 fine
+// columns and reads each fine row pair with 16-byte vector loads.
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ void resrestrict_body(const Lvl<T>& F, const Lvl<T>& C,
+                                                 const T* __restrict__ u,
+                                                 const T* __restrict__ f, T* __restrict__ fc,
+                                                 int nti, int ntj, int b) {
+  using V2 = typename Vec2<T>::type;
+  const int ti = b % nti;
+  const int r1 = b / nti;
+  const int tj = r1 % ntj;
+  const int kb = r1 / ntj;
+  const int I = ti * 64 + (threadIdx.x & 63);
+  const int J = tj * SROWS + (threadIdx.x >> 6);
+  if (I >= C.nx || J >= C.ny) return;
+  const int nx = F.nx, ny = F.ny, nz = F.nz;
+  const int i0 = 2 * I, j0 = 2 * J;
+  const int iw = (i0 == 0) ? nx - 1 : i0 - 1;
+  const int ie = (i0 + 2 == nx) ? 0 : i0 + 2;
+  const int js = (j0 == 0) ? ny - 1 : j0 - 1;
+  const int jn = (j0 + 2 == ny) ? 0 : j0 + 2;
+  // face couplings of the 2x2 block: a = (i0,j0), b = (i0+1,j0), c = (i0,j0+1),
+  // d = (i0+1,j0+1)
+  const int64_t r0 = (int64_t)j0 * nx, r1c = (int64_t)(j0 + 1) * nx, rs = (int64_t)js * nx;
+  const T xab = F.cx[r0 + i0], xbE = F.cx[r0 + i0 + 1], xWa = F.cx[r0 + iw];
+  const T xcd = F.cx[r1c + i0], xdE = F.cx[r1c + i0 + 1], xWc = F.cx[r1c + iw];
+  const T yac = F.cy[r0 + i0], ybd = F.cy[r0 + i0 + 1];
+  const T ycN = F.cy[r1c + i0], ydN = F.cy[r1c + i0 + 1];
+  const T ySa = F.cy[rs + i0], ySb = F.cy[rs + i0 + 1];
+  const T Sa = xab + xWa + yac + ySa;
+  const T Sb = xbE + xab + ybd + ySb;
+  const T Sc = xcd + xWc + ycN + yac;
+  const T Sd = xdE + xcd + ydN + ybd;
+  const int64_t jst = (int64_t)nz * F.ldx;
+  const int64_t ra = (int64_t)j0 * jst, rc = (int64_t)(j0 + 1) * jst;
+  const int64_t rS = (int64_t)js * jst, rN = (int64_t)jn * jst;
+  const int64_t ldx = F.ldx;
+  const int k0 = kb * KSEG, k1 = min(nz, k0 + KSEG);
+  V2 m0 = {T(0), T(0)}, m1 = {T(0), T(0)};
+  if (k0 > 0) {
+    m0 = *reinterpret_cast<const V2*>(u + ra + (int64_t)(k0 - 1) * ldx + i0);
+    m1 = *reinterpret_cast<const V2*>(u + rc + (int64_t)(k0 - 1) * ldx + i0);
+  }
+  V2 c0 = *reinterpret_cast<const V2*>(u + ra + (int64_t)k0 * ldx + i0);
+  V2 c1 = *reinterpret_cast<const V2*>(u + rc + (int64_t)k0 * ldx + i0);
+  const int64_t ocj = (int64_t)J * C.nz * C.ldx + I;
+#pragma unroll 2
+  for (int k = k0; k < k1; ++k) {
+    const int64_t ok = (int64_t)k * ldx;
+    V2 p0 = {T(0), T(0)}, p1 = {T(0), T(0)};
+    if (k + 1 < nz) {
+      p0 = *reinterpret_cast<const V2*>(u + ra + ok + ldx + i0);
+      p1 = *reinterpret_cast<const V2*>(u + rc + ok + ldx + i0);
+    }
+    const T uWa = u[ra + ok + iw], uEb = u[ra + ok + ie];
+    const T uWc = u[rc + ok + iw], uEd = u[rc + ok + ie];
+    const V2 sS = *reinterpret_cast<const V2*>(u + rS + ok + i0);
+    const V2 sN = *reinterpret_cast<const V2*>(u + rN + ok + i0);
+    const V2 f0 = *reinterpret_cast<const V2*>(f + ra + ok + i0);
+    const V2 f1 = *reinterpret_cast<const V2*>(f + rc + ok + i0);
+    const T dzk = F.dz[k], dgk = F.dg[k], sub = F.sub[k], sup = F.sup[k];
+    const T ra_ = f0.x - ((dgk + dzk * Sa) * c0.x -
+                          dzk * (xab * c0.y + xWa * uWa + yac * c1.x + ySa * sS.x) +
+                          sub * m0.x + sup * p0.x);
+    const T rb_ = f0.y - ((dgk + dzk * Sb) * c0.y -
+                          dzk * (xbE * uEb + xab * c0.x + ybd * c1.y + ySb * sS.y) +
+                          sub * m0.y + sup * p0.y);
+    const T rc_ = f1.x - ((dgk + dzk * Sc) * c1.x -
+                          dzk * (xcd * c1.y + xWc * uWc + ycN * sN.x + yac * c0.x) +
+                          sub * m1.x + sup * p1.x);
+    const T rd_ = f1.y - ((dgk + dzk * Sd) * c1.y -
+                          dzk * (xdE * uEd + xcd * c1.x + ydN * sN.y + ybd * c0.y) +
+                          sub * m1.y + sup * p1.y);
+    fc[ocj + (int64_t)k * C.ldx] = ra_ + rb_ + rc_ + rd_;
+    m0 = c0;
+    m1 = c1;
+    c0 = p0;
+    c1 = p1;
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(NTHREADS) void k_resrestrict(Lvl<T> F, Lvl<T> C,
+                                                          const T* __restrict__ u,
+                                                          const T* __restrict__ f,
+                                                          T* __restrict__ fc, int nti, int ntj) {
+  resrestrict_body<T>(F, C, u, f, fc, nti, ntj, xcd_remap(blockIdx.x, gridDim.x));
+}
+
+// ---------------------------------------------------------------------------
+// Refinement step fused with the next residual: u' = u + e (e FP32),
+// r = f - A u', r32 = (float) r, partial ||r||^2.  u' goes to a different
+// buffer (neighbouring threads still read u and e).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void correct_residual_body(
+    const Lvl<double>& L, const double* __restrict__ u, const float* __restrict__ e,
+    const double* __restrict__ f, double* __restrict__ uout, float* __restrict__ r32,
+    double* __restrict__ partials, int nti, int ntj, int b) {
+  const int ti = b % nti;
+  const int r1 = b / nti;
+  const int tj = r1 % ntj;
+  const int kb = r1 / ntj;
+  const int i = ti * 64 + (threadIdx.x & 63);
+  const int j = tj * SROWS + (threadIdx.x >> 6);
+  double nrm[1] = {0.0};
+  if (i < L.nx && j < L.ny) {
+    const Col<double> c = load_col(L, i, j);
+    const int nz = L.nz;
+    const int k0 = kb * KSEG;
+    const int k1 = min(nz, k0 + KSEG);
+    const int64_t ldx = L.ldx;
+    int64_t o = c.base + (int64_t)k0 * ldx;
+    double um = (k0 > 0) ? u[o - ldx] + (double)e[o - ldx] : 0.0;
+    double uc = u[o] + (double)e[o];
+#pragma unroll 2
+    for (int k = k0; k < k1; ++k, o += ldx) {
+      const double up = (k + 1 < nz) ? u[o + ldx] + (double)e[o + ldx] : 0.0;
+      const double h = c.ce * (u[o + c.oe] + (double)e[o + c.oe]) +
+                       c.cw * (u[o + c.ow] + (double)e[o + c.ow]) +
+                       c.cn * (u[o + c.on] + (double)e[o + c.on]) +
+                       c.cs * (u[o + c.os] + (double)e[o + c.os]);
+      const double dzk = L.dz[k];
+      const double au = (L.dg[k] + dzk * c.S) * uc - dzk * h + L.sub[k] * um + L.sup[k] * up;
+      const double rr = f[o] - au;
+      uout[o] = uc;
+      r32[o] = (float)rr;
+      nrm[0] += rr * rr;
+      um = uc;
+      uc = up;
+    }
+  }
+  block_partials<1>(nrm, partials);
+}
+
+__global__ __launch_bounds__(NTHREADS) void k_correct_residual(
+    Lvl<double> L, const double* __restrict__ u, const float* __restrict__ e,
+    const double* __restrict__ f, double* __restrict__ uout, float* __restrict__ r32,
+    double* __restrict__ partials, int nti, int ntj) {
+  correct_residual_body(L, u, e, f, uout, r32, partials, nti, ntj,
+                        xcd_remap(blockIdx.x, gridDim.x));
 }
 
 // ---------------------------------------------------------------------------
 // Prolongate: uf += P uc (cell-centred bilinear, 9/3/3/1 over 16, periodic)
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ __launch_bounds__(NTHREADS) void k_prolongate(Lvl<T> C, Lvl<T> F,
-                                                         const T* __restrict__ uc,
-                                                         T* __restrict__ uf, int nti, int ntj) {
-  const int b = xcd_remap(blockIdx.x, gridDim.x);
+__device__ __forceinline__ void prolongate_body(const Lvl<T>& C, const Lvl<T>& F,
+                                                const T* __restrict__ uc, T* __restrict__ uf,
+                                                int nti, int ntj, int b) {
   const int ti = b % nti;
   const int r1 = b / nti;
   const int tj = r1 % ntj;
@@ -320,6 +485,13 @@ __global__ __launch_bounds__(NTHREADS) void k_prolongate(Lvl<T> C, Lvl<T> F,
     const T v = T(9) * uc[c00 + kc] + T(3) * uc[c10 + kc] + T(3) * uc[c01 + kc] + uc[c11 + kc];
     uf[fb + (int64_t)k * F.ldx] += v * T(0.0625);
   }
+}
+
+template <typename T>
+__global__ __launch_bounds__(NTHREADS) void k_prolongate(Lvl<T> C, Lvl<T> F,
+                                                         const T* __restrict__ uc,
+                                                         T* __restrict__ uf, int nti, int ntj) {
+  prolongate_body<T>(C, F, uc, uf, nti, ntj, xcd_remap(blockIdx.x, gridDim.x));
 }
 
 // ---------------------------------------------------------------------------
@@ -481,6 +653,66 @@ __global__ __launch_bounds__(NTHREADS) void k_fcg_update(Lvl<double> L, double* 
 }
 
 // ---------------------------------------------------------------------------
+// Grouped launches: one launch covers the work items of many (instance, rhs)
+// pairs; each workgroup finds its item by binary search over the items' first
+// workgroups (uniform scalar loads) and runs the single-level body.  Items of
+// converged pairs return at once.
+// ---------------------------------------------------------------------------
+template <typename I>
+__device__ __forceinline__ int find_item(const I* __restrict__ items, int nitems, int B) {
+  int lo = 0, hi = nitems - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (items[mid].blk0 <= B) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+template <int HALF, int MODE>
+__global__ __launch_bounds__(NTHREADS) void k_line_grouped(const GItem<float>* __restrict__ items,
+                                                           int nitems,
+                                                           const int* __restrict__ active,
+                                                           float rho) {
+  const int B = xcd_remap(blockIdx.x, gridDim.x);
+  const GItem<float> it = items[find_item(items, nitems, B)];
+  if (!active[it.pair]) return;
+  LineArgs<float> a{};
+  a.a = it.a;
+  a.b = it.b;
+  a.o0 = it.o;
+  a.rho = rho;
+  line_body<float, HALF, MODE>(it.L, a, it.nti, B - it.blk0);
+}
+
+__global__ __launch_bounds__(NTHREADS) void k_resrestrict_grouped(
+    const GItem<float>* __restrict__ items, int nitems, const int* __restrict__ active) {
+  const int B = xcd_remap(blockIdx.x, gridDim.x);
+  const GItem<float> it = items[find_item(items, nitems, B)];
+  if (!active[it.pair]) return;
+  resrestrict_body<float>(it.L, it.X, it.a, it.b, it.o, it.nti, it.ntj, B - it.blk0);
+}
+
+__global__ __launch_bounds__(NTHREADS) void k_prolongate_grouped(
+    const GItem<float>* __restrict__ items, int nitems, const int* __restrict__ active) {
+  const int B = xcd_remap(blockIdx.x, gridDim.x);
+  const GItem<float> it = items[find_item(items, nitems, B)];
+  if (!active[it.pair]) return;
+  prolongate_body<float>(it.X, it.L, it.a, it.o, it.nti, it.ntj, B - it.blk0);
+}
+
+__global__ __launch_bounds__(NTHREADS) void k_correct_residual_grouped(
+    const GItemCR* __restrict__ items, int nitems, const int* __restrict__ active,
+    double* __restrict__ partials) {
+  const int B = xcd_remap(blockIdx.x, gridDim.x);
+  const GItemCR it = items[find_item(items, nitems, B)];
+  if (!active[it.pair]) return;
+  // partial of workgroup B of the item goes to slot B (the pair's segment)
+  correct_residual_body(it.L, it.u, it.e, it.f, it.uout, it.r32, partials - blockIdx.x + B,
+                        it.nti, it.ntj, B - it.blk0);
+}
+
+// ---------------------------------------------------------------------------
 // Reductions and scalar updates (single workgroup, fixed summation order)
 // ---------------------------------------------------------------------------
 template <int NC>
@@ -632,6 +864,36 @@ __global__ __launch_bounds__(NTHREADS) void k_fcg_fin_res(CgState* st,
   }
 }
 
+// One workgroup per pair: sum the pair's partials (fixed order) and update
+// its state.  init: record ||r_0||^2.  Otherwise count the iteration and stop
+// the pair on convergence, maxit or a non-finite norm.
+__global__ __launch_bounds__(NTHREADS) void k_pair_reduce(PairState* __restrict__ ps,
+                                                          int* __restrict__ active,
+                                                          const double* __restrict__ partials,
+                                                          int init) {
+  const int p = blockIdx.x;
+  if (!active[p]) return;
+  double r[1];
+  reduce_fixed<1>(partials + ps[p].blk0, ps[p].nblk, r);
+  if (threadIdx.x == 0) {
+    const double rr = r[0];
+    PairState& q = ps[p];
+    q.rr = rr;
+    if (init) {
+      q.rr0 = rr;
+      q.thresh2 *= rr;
+      q.iters = 0;
+      if (!isfinite(rr)) { q.status = 2; active[p] = 0; }
+      else if (rr == 0.0) active[p] = 0;
+      return;
+    }
+    q.iters += 1;
+    if (!isfinite(rr)) { q.status = 2; active[p] = 0; }
+    else if (rr < q.thresh2) active[p] = 0;
+    else if (q.iters >= q.maxit) { q.status = 1; active[p] = 0; }
+  }
+}
+
 __global__ __launch_bounds__(NTHREADS) void k_cg_final_update(Lvl<double> L,
                                                               double* __restrict__ u,
                                                               const double* __restrict__ p,
@@ -688,6 +950,61 @@ hipError_t line_dispatch(const Lvl<T>& L, const LineArgs<T>& a, hipStream_t s) {
 
 }  // namespace
 
+int64_t line_tiles_x(int nx) { return cdiv(nx, 32); }
+int64_t line_tiles_y(int ny) { return cdiv(ny, LROWS); }
+int64_t stencil_tiles_x(int nx) { return cdiv(nx, 64); }
+int64_t stencil_tiles_y(int ny) { return cdiv(ny, SROWS); }
+int64_t stencil_tiles_k(int nz) { return cdiv(nz, KSEG); }
+
+hipError_t launch_grouped_f32(GKind kind, int half, const GItem<float>* items, int nitems,
+                              int nblocks, const int* active, float rho, hipStream_t s) {
+  const dim3 grid(nblocks), block(NTHREADS);
+  switch (kind) {
+    case GKind::LINE_SOLVE:
+    case GKind::SMOOTH: {
+      const bool sm = kind == GKind::SMOOTH;
+#define GMG_GLINE(H)                                                                         \
+  if (half == H) {                                                                           \
+    if (sm)                                                                                  \
+      hipLaunchKernelGGL((k_line_grouped<H, LINE_SMOOTH>), grid, block, 0, s, items, nitems, \
+                         active, rho);                                                       \
+    else                                                                                     \
+      hipLaunchKernelGGL((k_line_grouped<H, LINE_SOLVE>), grid, block, 0, s, items, nitems,  \
+                         active, rho);                                                       \
+    return hipGetLastError();                                                                \
+  }
+      GMG_GLINE(4)
+      GMG_GLINE(8)
+      GMG_GLINE(16)
+      GMG_GLINE(32)
+      GMG_GLINE(64)
+#undef GMG_GLINE
+      return hipErrorInvalidValue;
+    }
+    case GKind::RESRESTRICT:
+      hipLaunchKernelGGL(k_resrestrict_grouped, grid, block, 0, s, items, nitems, active);
+      return hipGetLastError();
+    case GKind::PROLONGATE:
+      hipLaunchKernelGGL(k_prolongate_grouped, grid, block, 0, s, items, nitems, active);
+      return hipGetLastError();
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_grouped_cr(const GItemCR* items, int nitems, int nblocks, const int* active,
+                             double* partials, hipStream_t s) {
+  hipLaunchKernelGGL(k_correct_residual_grouped, dim3(nblocks), dim3(NTHREADS), 0, s, items,
+                     nitems, active, partials);
+  return hipGetLastError();
+}
+
+hipError_t launch_pair_reduce(PairState* ps, int* active, const double* partials, int npairs,
+                              int init, hipStream_t s) {
+  hipLaunchKernelGGL(k_pair_reduce, dim3(npairs), dim3(NTHREADS), 0, s, ps, active, partials,
+                     init);
+  return hipGetLastError();
+}
+
 int64_t stencil_blocks(int nx, int ny, int nz) {
   return (int64_t)cdiv(nx, 64) * cdiv(ny, SROWS) * cdiv(nz, KSEG);
 }
@@ -726,6 +1043,7 @@ hipError_t launch_line_solve(const Lvl<T>& L, const T* r, T* z, hipStream_t s) {
   LineArgs<T> a{};
   a.a = r;
   a.o0 = z;
+  a.rho = T(1);
   return line_dispatch<T, LINE_SOLVE>(L, a, s);
 }
 
@@ -750,6 +1068,47 @@ hipError_t launch_restrict_smooth(const Lvl<T>& C, const Lvl<T>& F, const T* rf,
   a.rho = rho;
   a.F = F;
   return line_dispatch<T, LINE_RESTRICT_SMOOTH>(C, a, s);
+}
+
+template <typename T>
+hipError_t launch_line_solve_scaled(const Lvl<T>& L, const T* r, T* z, T scale, hipStream_t s) {
+  LineArgs<T> a{};
+  a.a = r;
+  a.o0 = z;
+  a.rho = scale;
+  return line_dispatch<T, LINE_SOLVE>(L, a, s);
+}
+
+template <typename T>
+hipError_t launch_smooth_norm(const Lvl<T>& L, const T* f, const T* uin, T* uout, T rho,
+                              double* partials, int64_t* nblocks, hipStream_t s) {
+  LineArgs<T> a{};
+  a.a = uin;
+  a.b = f;
+  a.o0 = uout;
+  a.rho = rho;
+  a.partials = partials;
+  *nblocks = line_blocks(L.nx, L.ny);
+  return line_dispatch<T, LINE_SMOOTH_NORM>(L, a, s);
+}
+
+template <typename T>
+hipError_t launch_resrestrict(const Lvl<T>& F, const Lvl<T>& C, const T* u, const T* f, T* fc,
+                              hipStream_t s) {
+  const int nti = cdiv(C.nx, 64), ntj = cdiv(C.ny, SROWS), nkb = cdiv(C.nz, KSEG);
+  hipLaunchKernelGGL((k_resrestrict<T>), dim3(nti * ntj * nkb), dim3(NTHREADS), 0, s, F, C, u, f,
+                     fc, nti, ntj);
+  return hipGetLastError();
+}
+
+hipError_t launch_correct_residual(const Lvl<double>& L, const double* u, const float* e,
+                                   const double* f, double* uout, float* r32, double* partials,
+                                   int64_t* nblocks, hipStream_t s) {
+  const int nti = cdiv(L.nx, 64), ntj = cdiv(L.ny, SROWS), nkb = cdiv(L.nz, KSEG);
+  *nblocks = (int64_t)nti * ntj * nkb;
+  hipLaunchKernelGGL(k_correct_residual, dim3(nti * ntj * nkb), dim3(NTHREADS), 0, s, L, u, e, f,
+                     uout, r32, partials, nti, ntj);
+  return hipGetLastError();
 }
 
 template <typename T>
@@ -885,7 +1244,12 @@ hipError_t launch_add_f32_to_f64(double* u, const float* e, int64_t n, hipStream
                                                 T*, T, hipStream_t);                          \
   template hipError_t launch_prolongate<T>(const Lvl<T>&, const Lvl<T>&, const T*, T*,        \
                                            hipStream_t);                                      \
-  template hipError_t launch_fill<T>(T*, int64_t, T, hipStream_t);
+  template hipError_t launch_fill<T>(T*, int64_t, T, hipStream_t);                            \
+  template hipError_t launch_line_solve_scaled<T>(const Lvl<T>&, const T*, T*, T, hipStream_t); \
+  template hipError_t launch_smooth_norm<T>(const Lvl<T>&, const T*, const T*, T*, T, double*, \
+                                            int64_t*, hipStream_t);                           \
+  template hipError_t launch_resrestrict<T>(const Lvl<T>&, const Lvl<T>&, const T*, const T*, \
+                                            T*, hipStream_t);
 
 GMG_INSTANTIATE(double)
 GMG_INSTANTIATE(float)

@@ -31,8 +31,10 @@ def share():
 
 
 def _gather(ctx, t, rows, level=0):
-    idx = torch.from_numpy(device_index(ctx, rows, level)).cuda()
-    return t.index_select(0, idx).double().cpu().numpy()
+    idx = device_index(ctx, rows, level)
+    # host-side bounds check before the device gather
+    assert idx.size and idx.min() >= 0 and idx.max() < t.numel(), (idx.min(), idx.max(), t.numel())
+    return t.index_select(0, torch.from_numpy(idx).cuda()).double().cpu().numpy()
 
 
 def test_fullsize_kernels_at_sampled_columns(share):
@@ -75,7 +77,9 @@ def test_fullsize_transfers_at_sampled_columns(share):
     fcd, ucd = ctx.empty(1), ctx.empty(1)
     G.gmg_restrict_smooth(ctx, 1, rfd, fcd, ucd)
     fc_ref = orc.restrict(rf, 0)
-    ccols = np.unique(cols % nc)
+    ncx = w.nx // 2
+    ccols = np.unique((cols // w.nx // 2) * ncx + (cols % w.nx) // 2)   # parents (I, J)
+    assert ccols.max() < ncx * (w.ny // 2)
     crow = orc.column_rows(ccols)
     assert max_rel(_gather(ctx, fcd, crow, 1), fc_ref[crow], np.abs(fc_ref).max()) < 1e-12
     uc_ref = ctx.rho * orc.line_solve_columns(ccols, fc_ref, depth=1)[crow]

@@ -7,9 +7,12 @@ cancellation cannot fake a failure; for the line kernels against max|z|
 eliminations agree to ~1e-15).
 
 FP32 bars: inputs are rounded to FP32 before both sides see them; the
-oracle computes in FP64.  Coefficients rounded to FP32 (relative 6e-8), a
-7-term sum and a Thomas forward error of ~30 unit roundoffs give the bars
-2e-6 (stencils, scaled as above) and 2e-5 (line kernels).
+oracle computes in FP64.  Stencils: coefficients rounded to FP32 (relative
+6e-8) and a 7-term sum give 2e-6, scaled as above.  Line kernels: the error of
+an FP32 elimination grows with the column height (a textbook FP32 Thomas sweep
+on the FP32-rounded columns of these operators is off by 2.3e-5 of max|z| at
+n_z = 128 and 4e-6 at n_z = 64), so the bar is 4e-7 n_z (about seven FP32
+unit roundoffs per layer), at least 2e-6.
 """
 
 import numpy as np
@@ -31,7 +34,10 @@ SHAPES = [
 ]
 F64 = 1e-12
 F32_STENCIL = 2e-6
-F32_LINE = 2e-5
+
+
+def f32_line_bar(nz):
+    return max(2e-6, 4e-7 * nz)
 
 
 @pytest.fixture(autouse=True, scope="module")
@@ -100,7 +106,7 @@ def test_line_solve(shape, prec):
     G.line_solve(ctx, 0, rd, zd)
     got = ctx.from_device(zd)
     ref = orc.line_solve(r)
-    bar = F64 if prec == 0 else F32_LINE
+    bar = F64 if prec == 0 else f32_line_bar(nz)
     assert max_rel(got, ref, np.abs(ref).max()) < bar
     # in place (r and z the same buffer) gives the same result
     G.line_solve(ctx, 0, rd, rd)
@@ -121,7 +127,7 @@ def test_line_smooth(shape, prec, nsweeps):
     ref = u.copy()
     for _ in range(nsweeps):
         ref = orc.smooth(f, ref)
-    bar = F64 if prec == 0 else F32_LINE
+    bar = F64 if prec == 0 else f32_line_bar(nz)
     assert max_rel(got, ref, np.abs(ref).max()) < bar * nsweeps
 
 
@@ -140,7 +146,7 @@ def test_restrict_smooth(shape, L, prec):
         fcd, ucd = ctx.empty(lvl, dtype=_dtype(prec)), ctx.empty(lvl, dtype=_dtype(prec))
         G.gmg_restrict_smooth(ctx, lvl, rfd, fcd, ucd)
         fc_ref, uc_ref = orc.restrict_smooth(rf, lvl)
-        bar = F64 if prec == 0 else F32_LINE
+        bar = F64 if prec == 0 else f32_line_bar(nz)
         assert max_rel(ctx.from_device(fcd, lvl), fc_ref, np.abs(fc_ref).max()) < bar
         assert max_rel(ctx.from_device(ucd, lvl), uc_ref, np.abs(uc_ref).max()) < bar
 
