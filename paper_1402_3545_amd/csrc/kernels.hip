@@ -180,89 +180,224 @@ struct Vec2<double> { using type = double2; };
 template <>
 struct Vec2<float> { using type = float2; };
 
+// Reciprocal: hardware estimate refined by Newton-Raphson steps
+// r <- r (2 - p r), written as e = 1 - p r, r <- r + r e (two steps in FP64,
+// one in FP32 bring the estimate to the last bit or so).  Pivots here are
+// positive and well scaled, so no special cases arise.
+__device__ __forceinline__ double rcp_nr(double p) {
+  double r = __builtin_amdgcn_rcp(p);
+  double e = fma(-p, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-p, r, 1.0);
+  return fma(r, e, r);
+}
+__device__ __forceinline__ float rcp_nr(float p) {
+  const float r = __builtin_amdgcn_rcpf(p);
+  const float e = fmaf(-p, r, 1.0f);
+  return fmaf(r, e, r);
+}
+
+// One elimination step: pivot, its reciprocal and the new c' of this row.
+template <typename T>
+__device__ __forceinline__ void elim_step(T diag, T cpv, T cnx, T cprev, T& piv, T& inv, T& c) {
+  piv = diag - cpv * cprev;
+  inv = rcp_nr(piv);
+  c = cnx * inv;
+}
+
+// Values one elimination step reads from memory (loaded a chunk ahead).
+template <typename T, int MODE>
+struct StepIn;
+template <typename T>
+struct StepIn<T, LINE_SOLVE> { T r; };
+template <typename T>
+struct StepIn<T, LINE_SMOOTH> { T un, ue, uw, unn, us, f; };
+template <typename T>
+struct StepIn<T, LINE_SMOOTH_NORM> { T un, ue, uw, unn, us, f; };
+template <typename T>
+struct StepIn<T, LINE_RESTRICT_SMOOTH> { typename Vec2<T>::type lo, hi; };
+template <typename T>
+struct StepIn<T, LINE_CG> { T r, q; };
+
+// Load/store through a wave-uniform row base (SGPRs) and a 32-bit per-lane
+// byte offset: the compiler then emits the saddr form of global memory
+// instructions, one VGPR per address.
+template <typename T>
+__device__ __forceinline__ T ldo(const char* base, uint32_t off) {
+  return *reinterpret_cast<const T*>(base + off);
+}
+template <typename T>
+__device__ __forceinline__ void sto(char* base, uint32_t off, T v) {
+  *reinterpret_cast<T*>(base + off) = v;
+}
+
 // Body of the line kernels for tile b of a level (tiles of 32 columns x LROWS
-// rows, nti tiles across).  Block partials go to a.partials[blockIdx.x].
+// rows, nti tiles across; wavefront w of the workgroup owns grid row
+// tj*LROWS + w).  Block partials go to a.partials[blockIdx.x].
+//
+// Every column is treated as 2*HALF rows: rows k >= nz are identity rows
+// (diagonal 1, no coupling, zero right-hand side) that do not touch the real
+// nz x nz block (its last row has no super-diagonal), so one branch-free,
+// fully unrolled sweep serves every nz <= 2*HALF.  Addresses of virtual rows
+// are clamped to a real row and their results are not stored.  The vertical
+// profiles (padded the same way) are staged in LDS once per workgroup.
+//
+// Registers: the forward sweep keeps d' of its HALF rows and a c' checkpoint
+// every G rows; the loads of each chunk of CH steps are issued one chunk
+// ahead (double buffer) so that memory latency overlaps the elimination.  The
+// back sweep recomputes c' (and the pivots) of each G-row segment from its
+// checkpoint and substitutes backwards.
 template <typename T, int HALF, int MODE>
 __device__ __forceinline__ void line_body(const Lvl<T>& L, const LineArgs<T>& a, int nti,
                                           int b) {
+  constexpr int NR = 2 * HALF;
+  constexpr bool kSmooth = (MODE == LINE_SMOOTH || MODE == LINE_SMOOTH_NORM);
+  constexpr int G = HALF < 8 ? HALF : 8;                       // back-sweep segment
+  constexpr int NG = HALF / G;
+  // prefetch chunk: bounded by the registers the buffered loads take
+  constexpr int CHW = (MODE == LINE_SOLVE || sizeof(T) == 4) && MODE != LINE_RESTRICT_SMOOTH
+                          ? (kSmooth ? 4 : 8)
+                          : 4;
+  constexpr int CH = HALF < CHW ? HALF : CHW;
+  constexpr int NCH = HALF / CH;
+  constexpr uint32_t ES = sizeof(T);
+  using V2 = typename Vec2<T>::type;
+  __shared__ T s_sub[NR], s_sup[NR], s_dg[NR], s_dz[NR];
+  const int nz = L.nz;
+  for (int k = threadIdx.x; k < NR; k += blockDim.x) {
+    const bool real = k < nz;
+    s_sub[k] = real ? L.sub[k] : T(0);
+    s_sup[k] = real ? L.sup[k] : T(0);
+    s_dg[k] = real ? L.dg[k] : T(1);
+    s_dz[k] = real ? L.dz[k] : T(0);
+  }
+  __syncthreads();
   const int ti = b % nti;
   const int tj = b / nti;
   const int lane = threadIdx.x & 63;
   const int half = lane >> 5;
   const int i = ti * 32 + (lane & 31);
-  const int j = tj * LROWS + (threadIdx.x >> 6);
+  // the row of the wavefront, made visibly uniform so that row bases live in
+  // SGPRs
+  const int j = tj * LROWS + __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   const bool active = (i < L.nx) && (j < L.ny);
   // inactive lanes compute on a valid column and store nothing; they still
   // take part in the cross-lane exchange
-  const Col<T> c = load_col(L, min(i, L.nx - 1), min(j, L.ny - 1));
-  const int nz = L.nz;
-  const int m = nz >> 1;
-  const int nown = half ? nz - m : m;
-  const int k0 = half ? nz - 1 : 0;
+  const int ic = min(i, L.nx - 1), jc = min(j, L.ny - 1);
+  const Col<T> c = load_col(L, ic, jc);
+  const int jn = (jc + 1 == L.ny) ? 0 : jc + 1;
+  const int js = (jc == 0) ? L.ny - 1 : jc - 1;
+  const int ie = (ic + 1 == L.nx) ? 0 : ic + 1;
+  const int iw = (ic == 0) ? L.nx - 1 : ic - 1;
+  const int64_t jstride = (int64_t)nz * L.ldx;
+  const uint32_t kbytes = (uint32_t)L.ldx * ES;   // one layer
+  const int k0 = half ? NR - 1 : 0;
   const int dir = half ? -1 : 1;
-  const int64_t ldx = L.ldx;
-  const int64_t sdir = half ? -ldx : ldx;
+
+  // wave-uniform row bases
+  const char* rA = reinterpret_cast<const char*>(a.a + (int64_t)jc * jstride);
+  const char* rAn = reinterpret_cast<const char*>(a.a + (int64_t)jn * jstride);
+  const char* rAs = reinterpret_cast<const char*>(a.a + (int64_t)js * jstride);
+  const char* rB = reinterpret_cast<const char*>(a.b + (int64_t)jc * jstride);
+  char* rW = reinterpret_cast<char*>(a.rw + (int64_t)jc * jstride);
+  char* rO0 = reinterpret_cast<char*>(a.o0 + (int64_t)jc * jstride);
+  char* rO1 = reinterpret_cast<char*>(a.o1 + (int64_t)jc * jstride);
+  const char* rF0 = nullptr;
+  const char* rF1 = nullptr;
+  uint32_t fkbytes = 0;
+  if constexpr (MODE == LINE_RESTRICT_SMOOTH) {
+    const int64_t fjs = (int64_t)a.F.nz * a.F.ldx;
+    rF0 = reinterpret_cast<const char*>(a.a + (int64_t)(2 * jc) * fjs);
+    rF1 = reinterpret_cast<const char*>(a.a + (int64_t)(2 * jc + 1) * fjs);
+    fkbytes = (uint32_t)a.F.ldx * ES;
+  }
 
   T alpha = T(0);
   if constexpr (MODE == LINE_CG) alpha = a.init ? T(0) : (T)a.st->alpha;
   double acc_rr = 0.0, acc_rz = 0.0;
 
-  // fine-level addressing for the restriction (coarse column (i,j) owns fine
-  // columns 2i, 2i+1 in rows 2j, 2j+1)
-  int64_t fbase = 0, fjs = 0;
-  if constexpr (MODE == LINE_RESTRICT_SMOOTH) {
-    const int ii = min(i, L.nx - 1), jj = min(j, L.ny - 1);
-    fjs = (int64_t)a.F.nz * a.F.ldx;
-    fbase = (int64_t)(2 * jj) * fjs + 2 * ii;
-  }
+  // Row indices advance as running per-lane counters; the empty asm makes each
+  // step's value opaque so the compiler does not precompute (and keep alive)
+  // the rows and addresses of the whole unrolled sweep.
+  auto next_row = [&](int& kk) {
+    asm volatile("" : "+v"(kk));
+    const int k = kk;
+    kk += dir;
+    return k;
+  };
+  auto kcl = [&](int k) { return (uint32_t)min(k, nz - 1); };
+  auto off = [&](int k, int col) { return (uint32_t)col * ES + kcl(k) * kbytes; };
+  auto load_step = [&](int k, StepIn<T, MODE>& v) {
+    const uint32_t o = off(k, ic);
+    if constexpr (MODE == LINE_SOLVE) {
+      v.r = ldo<T>(rA, o);
+    } else if constexpr (kSmooth) {
+      v.un = ldo<T>(rA, (uint32_t)ic * ES + (uint32_t)min(max(k + dir, 0), nz - 1) * kbytes);
+      v.ue = ldo<T>(rA, off(k, ie));
+      v.uw = ldo<T>(rA, off(k, iw));
+      v.unn = ldo<T>(rAn, o);
+      v.us = ldo<T>(rAs, o);
+      v.f = ldo<T>(rB, o);
+    } else if constexpr (MODE == LINE_RESTRICT_SMOOTH) {
+      const uint32_t fo = (uint32_t)(2 * ic) * ES + kcl(k) * fkbytes;
+      v.lo = ldo<V2>(rF0, fo);
+      v.hi = ldo<V2>(rF1, fo);
+    } else {
+      v.r = ldo<T>(rW, o);
+      v.q = ldo<T>(rA, o);
+    }
+  };
 
-  T cp[HALF], dp[HALF];
+  T dp[HALF];
+  T ckpt[NG];
   T cprev = T(0), dprev = T(0);
   T uprv = T(0), ucur = T(0);
-  constexpr bool kSmooth = (MODE == LINE_SMOOTH || MODE == LINE_SMOOTH_NORM);
-  if constexpr (kSmooth) ucur = a.a[c.base + (int64_t)k0 * ldx];
+  if constexpr (kSmooth) ucur = ldo<T>(rA, off(k0, ic));
 
+  StepIn<T, MODE> buf[2][CH];
+  int kl = k0, kf = k0;  // next row to load, next row to eliminate
 #pragma unroll
-  for (int s = 0; s < HALF; ++s) {
-    if (s < nown) {
-      const int k = k0 + dir * s;
-      const int64_t o = c.base + (int64_t)k * ldx;
-      const T sub = L.sub[k], sup = L.sup[k], dzk = L.dz[k];
+  for (int t = 0; t < CH; ++t) load_step(next_row(kl), buf[0][t]);
+#pragma unroll
+  for (int ch = 0; ch < NCH; ++ch) {
+    if (ch + 1 < NCH) {
+#pragma unroll
+      for (int t = 0; t < CH; ++t) load_step(next_row(kl), buf[(ch + 1) & 1][t]);
+    }
+#pragma unroll
+    for (int t = 0; t < CH; ++t) {
+      const int s = ch * CH + t;
+      const StepIn<T, MODE>& v = buf[ch & 1][t];
+      const int k = next_row(kf);
+      const bool real = k < nz;
+      const T sub = s_sub[k], sup = s_sup[k], dzk = s_dz[k];
       const T cpv = half ? sup : sub;  // coupling to the previously eliminated row
       const T cnx = half ? sub : sup;  // coupling to the next row in this lane's order
-      const T diag = L.dg[k] + dzk * c.S;
+      const T diag = s_dg[k] + dzk * c.S;
       T rhs;
       if constexpr (MODE == LINE_SOLVE) {
-        rhs = a.a[o];
+        rhs = real ? v.r : T(0);
       } else if constexpr (kSmooth) {
-        const T unxt = a.a[o + sdir];
-        const T au = diag * ucur - dzk * hsum(c, a.a, o) + cpv * uprv + cnx * unxt;
-        rhs = a.b[o] - au;
-        if constexpr (MODE == LINE_SMOOTH_NORM)
-          if (active) acc_rr += (double)rhs * (double)rhs;
+        const T h = c.ce * v.ue + c.cw * v.uw + c.cn * v.unn + c.cs * v.us;
+        const T au = diag * ucur - dzk * h + cpv * uprv + cnx * v.un;
+        rhs = real ? v.f - au : T(0);
         uprv = ucur;
-        ucur = unxt;
+        ucur = v.un;
       } else if constexpr (MODE == LINE_RESTRICT_SMOOTH) {
-        using V2 = typename Vec2<T>::type;
-        const int64_t fo = fbase + (int64_t)k * a.F.ldx;
-        const V2 lo = *reinterpret_cast<const V2*>(a.a + fo);
-        const V2 hi = *reinterpret_cast<const V2*>(a.a + fo + fjs);
-        rhs = lo.x + lo.y + hi.x + hi.y;
-        if (active) a.o1[o] = rhs;
+        rhs = real ? v.lo.x + v.lo.y + v.hi.x + v.hi.y : T(0);
       } else {  // LINE_CG
-        rhs = a.rw[o] - alpha * a.a[o];
-        if (active) {
-          a.rw[o] = rhs;
-          acc_rr += (double)rhs * (double)rhs;
-        }
+        rhs = real ? v.r - alpha * v.q : T(0);
       }
-      const T piv = diag - cpv * cprev;
-      const T inv = T(1) / piv;
-      cprev = cnx * inv;
+      T piv, inv, cn;
+      elim_step(diag, cpv, cnx, cprev, piv, inv, cn);
       dprev = (rhs - cpv * dprev) * inv;
-      cp[s] = cprev;
+      cprev = cn;
       dp[s] = dprev;
+      if (s % G == G - 1) ckpt[s / G] = cprev;
     }
+    // keep the scheduler from hoisting later chunks' loads and LDS reads
+    // above this point (that would need registers for the whole sweep)
+    __builtin_amdgcn_sched_barrier(0);
   }
 
   // interface between the two halves: lane's last row x_a = d_a - c_a x_b,
@@ -272,24 +407,64 @@ __device__ __forceinline__ void line_body(const Lvl<T>& L, const LineArgs<T>& a,
   T x = (dprev - cprev * dq) / (T(1) - cprev * cq);
 
 #pragma unroll
-  for (int s = HALF - 1; s >= 0; --s) {
-    if (s < nown) {
-      if (s < nown - 1) x = dp[s] - cp[s] * x;
-      const int k = k0 + dir * s;
-      const int64_t o = c.base + (int64_t)k * ldx;
-      if (active) {
+  for (int g = NG - 1; g >= 0; --g) {
+    // rows of this segment: k_t = kseg + dir t
+    int kseg = k0 + dir * (g * G);
+    asm volatile("" : "+v"(kseg));
+    // the smoother adds the correction to u: fetch this segment's u first
+    T useg[kSmooth ? G : 1];
+    if constexpr (kSmooth) {
+#pragma unroll
+      for (int t = 0; t < G; ++t) useg[t] = ldo<T>(rA, off(kseg + dir * t, ic));
+    }
+    // recompute c' (and the pivots) of the segment from its checkpoint
+    T cseg[G], pseg[G];
+    T cc = g == 0 ? T(0) : ckpt[g - 1];
+#pragma unroll
+    for (int t = 0; t < G; ++t) {
+      const int k = kseg + dir * t;
+      const T sub = s_sub[k], sup = s_sup[k];
+      const T cpv = half ? sup : sub, cnx = half ? sub : sup;
+      const T diag = s_dg[k] + s_dz[k] * c.S;
+      T inv;
+      elim_step(diag, cpv, cnx, cc, pseg[t], inv, cseg[t]);
+      cc = cseg[t];
+    }
+#pragma unroll
+    for (int t = G - 1; t >= 0; --t) {
+      const int s = g * G + t;
+      if (s < HALF - 1) x = dp[s] - cseg[t] * x;
+      const int k = kseg + dir * t;
+      const bool st = active && k < nz;
+      // modes that need the right-hand side again rebuild it from the
+      // elimination: rhs_k = d'_k piv_k + (coupling to the previous row) d'_{k-1}
+      // (accurate to a few units of roundoff of the column's largest entry)
+      T rk = T(0);
+      if constexpr (MODE != LINE_SOLVE && MODE != LINE_SMOOTH) {
+        const T cpv = half ? s_sup[k] : s_sub[k];
+        rk = dp[s] * pseg[t] + (s > 0 ? cpv * dp[s > 0 ? s - 1 : 0] : T(0));
+      }
+      if constexpr (MODE == LINE_CG) {
+        acc_rr += st ? (double)rk * (double)rk : 0.0;
+        acc_rz += st ? (double)rk * (double)x : 0.0;
+      }
+      if constexpr (MODE == LINE_SMOOTH_NORM) acc_rr += st ? (double)rk * (double)rk : 0.0;
+      if (st) {
+        const uint32_t o = off(k, ic);
         if constexpr (MODE == LINE_SOLVE) {
-          a.o0[o] = a.rho * x;
-        } else if constexpr (kSmooth) {
-          a.o0[o] = a.a[o] + a.rho * x;
+          sto<T>(rO0, o, a.rho * x);
         } else if constexpr (MODE == LINE_RESTRICT_SMOOTH) {
-          a.o0[o] = a.rho * x;
+          sto<T>(rO1, o, rk);
+          sto<T>(rO0, o, a.rho * x);
+        } else if constexpr (kSmooth) {
+          sto<T>(rO0, o, useg[t] + a.rho * x);
         } else {
-          a.o0[o] = x;
-          acc_rz += (double)a.rw[o] * (double)x;
+          sto<T>(rW, o, rk);
+          sto<T>(rO0, o, x);
         }
       }
     }
+    __builtin_amdgcn_sched_barrier(0);
   }
   if constexpr (MODE == LINE_CG) {
     double v[2] = {acc_rr, acc_rz};
