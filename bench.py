@@ -45,10 +45,24 @@ WORDS_PER_CELL = {
     "line_solve": 2.0,       # read r, write z
     "smooth": 3.0,           # read u, f, write u'
     "restrict_smooth": 6.0,  # per COARSE cell: read 4 fine r, write f_c, u_c
+    # (inside the V-cycle each coarse level starts with a scaled line solve,
+    # timed as line_solve of that level)
     "prolongate": 2.25,      # per FINE cell: read/write u_f, read 1/4 u_c
     "cg_spmv": 7.0,          # read u, p, z, q, write u, p, q
     "cg_tridiag": 4.0,       # read r, q, write r, z
+    "correct": 4.0,          # read u, f (8 B), e (4 B), write u (8 B), r (4 B): 32 B
+    "residual_restrict": 2.25,  # per FINE cell: read u, f, write 1/4 f_c
 }
+
+SOLVES = ("mg_f64", "pcg_f64", "mg_mixed", "fcg_mixed")
+
+# HBM traffic per launch of a kernel, from two rocprofv3 --pmc passes
+# (FETCH_SIZE, then WRITE_SIZE; KiB per dispatch averaged over the kernel's
+# dispatches) scaled by what the same counters read for a plain copy of known
+# size.  Reported only while the kernel source hashes to the recorded value.
+MEASURED_TRAFFIC = {}
+KERNEL_SOURCE = os.path.join(ROOT, "paper_1402_3545_amd", "csrc", "kernels.hip")
+COPY_PROBE_BYTES = 2 << 30   # per direction
 
 
 def log(*a):
@@ -65,6 +79,41 @@ def algorithmic_bytes(kernel, level, prec, w):
     if words is None:
         return None
     return words * cells * esize
+
+
+def source_sha256():
+    import hashlib
+    with open(KERNEL_SOURCE, "rb") as fh:
+        return hashlib.sha256(fh.read()).hexdigest()
+
+
+def measured_traffic(key):
+    rec = MEASURED_TRAFFIC.get(key)
+    if rec is None or rec["source_sha256"] != source_sha256():
+        return None
+    return (rec["fetch_kib"] * 1024.0 * rec["copy_fetch_scale"] +
+            rec["write_kib"] * 1024.0 * rec["copy_write_scale"])
+
+
+def copy_probe(torch, reps=5):
+    """A plain streaming copy of COPY_PROBE_BYTES (2 GiB read + 2 GiB written,
+    far above the caches): the counter calibration for the traffic figures and
+    the achievable-copy ceiling.  Returns GB/s of read + write bytes."""
+    n = COPY_PROBE_BYTES // 8
+    src = torch.ones(n, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    torch.neg(src, out=dst)
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        torch.neg(src, out=dst)
+    b.record()
+    b.synchronize()
+    ms = a.elapsed_time(b) / reps
+    del src, dst
+    torch.cuda.empty_cache()
+    return 2 * COPY_PROBE_BYTES / (ms / 1e3) / 1e9
 
 
 def cpu_baseline(w, f, kh, zf):
@@ -100,7 +149,15 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true",
                     help="skip the oracle timing (for profiler runs)")
+    ap.add_argument("--solves", default=",".join(SOLVES),
+                    help="comma list of solves per step (profiler runs); the reported "
+                         "value is only the whole-path figure with all four")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only run the plain copy used to calibrate traffic counters")
     args = ap.parse_args()
+    solves = [x for x in args.solves.split(",") if x]
+    if any(x not in SOLVES for x in solves) or not solves:
+        ap.error(f"--solves takes a comma list from {SOLVES}")
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the path is "
               "single-GPU by design", file=sys.stderr)
@@ -109,12 +166,18 @@ def main():
     import numpy as np
     import torch
 
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    if args.copy_probe:
+        gbs = copy_probe(torch)
+        print(json.dumps({"copy_probe_bytes_read": COPY_PROBE_BYTES,
+                          "copy_probe_bytes_written": COPY_PROBE_BYTES, "gbs": gbs}), flush=True)
+        return
+
     import paper_1402_3545_amd as G
     import workloads as W
 
     w = W.SHARE
-    dev = torch.device("cuda:0")
-    torch.cuda.set_device(dev)
     log(f"[bench] generating inputs for {w.name}")
     kh, zf, f = w.kh(), w.zfaces(), w.rhs()
     ctx64 = G.GmgContext(w.nx, w.ny, w.nz, w.nlevels, kv=w.kv, sigma=w.sigma, zfaces=zf, kh=kh,
@@ -127,11 +190,12 @@ def main():
 
     def step():
         out = {}
-        for name, fn in (("mg_f64", lambda: G.gmg_solve(ctx64, fd, ud, w.rtol, 100)),
-                         ("pcg_f64", lambda: G.pcg_solve(ctx64, fd, ud, w.rtol, 2000)),
-                         ("mg_mixed", lambda: G.gmg_solve(ctx32, fd, ud, w.rtol, 100)),
-                         ("fcg_mixed", lambda: G.pcg_solve(ctx32, fd, ud, w.rtol, 100,
-                                                           precond=1))):
+        runs = {"mg_f64": lambda: G.gmg_solve(ctx64, fd, ud, w.rtol, 100),
+                "pcg_f64": lambda: G.pcg_solve(ctx64, fd, ud, w.rtol, 2000),
+                "mg_mixed": lambda: G.gmg_solve(ctx32, fd, ud, w.rtol, 100),
+                "fcg_mixed": lambda: G.pcg_solve(ctx32, fd, ud, w.rtol, 100, precond=1)}
+        for name in solves:
+            fn = runs[name]
             ud.zero_()
             a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             a.record()
@@ -181,13 +245,21 @@ def main():
                  for k, (n, ms) in sorted(table.items(), key=lambda kv: -kv[1][1])}
     log("[bench] kernel breakdown (timed region): " + json.dumps(breakdown))
 
+    copy_gbs = copy_probe(torch)
+    log(f"[bench] plain-copy ceiling {copy_gbs:.0f} GB/s")
+    traffic = measured_traffic(dom)
+
     base = None
     if not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle sample")
         base = cpu_baseline(w, f, kh, zf)
         log(f"[bench] oracle: {base['value']:.3e} unknowns*it/s on {base['cores']} threads")
 
-    mg, mx = last["mg_f64"], last["mg_mixed"]
+    def speedup(a, b):
+        if a not in last or b not in last or last[b]["ms"] <= 0:
+            return None
+        return last[a]["ms"] / last[b]["ms"]
+
     line = {
         "metric": METRIC,
         "value": value,
@@ -207,12 +279,12 @@ def main():
             "kh": "U[0.5,2] seed 2", "rtol": w.rtol,
             "step": ("FP64 MG + FP64 line-CG + FP32-cycle MG in FP64 refinement + FP64 "
                      "flexible CG with FP32 V-cycle, each from u=0"),
+            "solves_run": solves,
         },
         "solves": {n: {"iters": v["iters"], "ms": round(v["ms"], 3),
                        "relres": v["relres"]} for n, v in last.items()},
-        "mixed_vs_fp64_mg_speedup": mg["ms"] / mx["ms"] if mx["ms"] > 0 else None,
-        "fcg_mixed_vs_fp64_mg_speedup": (mg["ms"] / last["fcg_mixed"]["ms"]
-                                         if last["fcg_mixed"]["ms"] > 0 else None),
+        "mixed_vs_fp64_mg_speedup": speedup("mg_f64", "mg_mixed"),
+        "fcg_mixed_vs_fp64_mg_speedup": speedup("mg_f64", "fcg_mixed"),
         "roofline": {
             "bound": "hbm",
             "kernel": f"{dom[0]} level {dom[1]} {dom[2]}",
@@ -220,7 +292,8 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": None,
+            "traffic": traffic,
+            "copy_ceiling_gbs": copy_gbs,
             "avg_ms": avg_ms,
             "launches": n_dom,
             "algorithmic_bytes": bytes_dom,

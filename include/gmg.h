@@ -184,11 +184,19 @@ int gmg_batch_solve(gmg_ctx *c, const double *const *f, double *const *u, double
  * gmg_timing_enable(c, 0) stops.  gmg_timing_read() waits for the recorded
  * events and returns, for one kernel kind / level / precision, the number of
  * launches and their summed duration in milliseconds since the last enable.
- * level = -1 sums over all levels. */
+ * level = -1 sums over all levels.  GMG_K_CG_SPMV and GMG_K_CG_TRIDIAG are
+ * the two fused kernels of the line-preconditioned CG; GMG_K_CORRECT is the
+ * fused update + residual of the mixed-precision refinement; GMG_K_FCG the
+ * vector kernels of the flexible CG; GMG_K_RESIDUAL_RESTRICT the V-cycle's
+ * fused fine-level residual + restriction (timed under the fine level; the
+ * residual is not stored); GMG_K_AUX fills and final updates.  Inside the
+ * V-cycle each coarse level starts with a scaled line solve, timed as
+ * GMG_K_LINE_SOLVE of that level. */
 typedef enum {
   GMG_K_SPMV = 0, GMG_K_RESIDUAL = 1, GMG_K_LINE_SOLVE = 2, GMG_K_SMOOTH = 3,
   GMG_K_RESTRICT_SMOOTH = 4, GMG_K_PROLONGATE = 5, GMG_K_CG_SPMV = 6, GMG_K_CG_TRIDIAG = 7,
-  GMG_K_REDUCE = 8, GMG_K_AUX = 9, GMG_K_COUNT = 10
+  GMG_K_REDUCE = 8, GMG_K_AUX = 9, GMG_K_CORRECT = 10, GMG_K_FCG = 11,
+  GMG_K_RESIDUAL_RESTRICT = 12, GMG_K_COUNT = 13
 } gmg_kernel;
 int gmg_timing_enable(gmg_ctx *c, int enable);
 int gmg_timing_read(gmg_ctx *c, int kernel, int level, int prec, int64_t *count,

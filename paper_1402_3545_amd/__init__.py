@@ -30,7 +30,8 @@ EXPORTS = ("gmg_default_params", "gmg_setup", "gmg_destroy", "gmg_field_layout",
 
 # kernel ids of the timing facility (gmg_kernel in include/gmg.h)
 KERNELS = ("spmv", "residual", "line_solve", "smooth", "restrict_smooth", "prolongate",
-           "cg_spmv", "cg_tridiag", "reduce", "aux")
+           "cg_spmv", "cg_tridiag", "reduce", "aux", "correct", "fcg",
+           "residual_restrict")
 
 
 class GmgError(RuntimeError):

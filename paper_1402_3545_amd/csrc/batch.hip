@@ -22,8 +22,6 @@ namespace gmg {
 
 namespace {
 
-constexpr int kMaxHalf = 64;
-
 int half_class(int nz) {
   int h = 4;
   while (2 * h < nz) h *= 2;

@@ -439,7 +439,7 @@ int vcycle_impl(gmg_ctx* c, const T* f0, T* u0, hipStream_t s, bool zero_guess =
     const Lvl<T> V = gmg::view<T>(c, d);
     LevelBuf& B = c->lev[d];
     if (d > 0) {
-      HIP_TRY(timed(c, GMG_K_RESTRICT_SMOOTH, d, P, s, [&] {
+      HIP_TRY(timed(c, GMG_K_LINE_SOLVE, d, P, s, [&] {
         return gmg::launch_line_solve_scaled<T>(V, fl[d], static_cast<T*>(B.u), rho, s);
       }));
       cur[d] = static_cast<T*>(B.u);
@@ -450,7 +450,7 @@ int vcycle_impl(gmg_ctx* c, const T* f0, T* u0, hipStream_t s, bool zero_guess =
     } else {
       const Lvl<T> C = gmg::view<T>(c, d + 1);
       T* fc = static_cast<T*>(c->lev[d + 1].f);
-      HIP_TRY(timed(c, GMG_K_RESIDUAL, d, P, s, [&] {
+      HIP_TRY(timed(c, GMG_K_RESIDUAL_RESTRICT, d, P, s, [&] {
         return gmg::launch_resrestrict<T>(V, C, cur[d], fl[d], fc, s);
       }));
     }
@@ -521,6 +521,19 @@ int residual_norm2(gmg_ctx* c, const T* f, const T* u, T* r, float* rdown, doubl
   return GMG_OK;
 }
 
+// How many CG iterations to launch before the host reads the device state
+// again: the count still needed at the mean decay rate of ||r||^2 so far,
+// clamped to [1, 32] (doubling from the previous chunk until two iterations
+// have run).  Launches past convergence return at once, so a low guess costs
+// one more poll and a high one a few empty launches.
+int predicted_chunk(const CgState& h, int prev) {
+  if (h.iter < 2 || !(h.rr > 0.0) || !(h.rr < h.rr0)) return std::min(2 * prev, 32);
+  const double rate = log(h.rr / h.rr0) / h.iter;  // < 0
+  const double need = log(h.thresh2 / h.rr);       // < 0 until converged
+  if (!(need < 0.0)) return 1;
+  return (int)std::min(32.0, std::max(1.0, ceil(need / rate)));
+}
+
 int ensure_hist(gmg_ctx* c, int maxit) {
   if (c->dhist_len < maxit + 1) {
     dfree(c->dhist);
@@ -567,16 +580,16 @@ int fcg_impl(gmg_ctx* c, const double* f, double* u, double rtol, int maxit, int
   for (int it = 1; it <= maxit; ++it) {
     if ((st = vcycle_impl<TZ>(c, rin, z, s, true, false))) return st;
     int64_t nb = 0;
-    HIP_TRY(timed(c, GMG_K_AUX, 0, GMG_F64, s,
+    HIP_TRY(timed(c, GMG_K_FCG, 0, GMG_F64, s,
                   [&] { return gmg::launch_fcg_zq<TZ>(V, z, c->vq, c->partials, &nb, s); }));
     HIP_TRY(timed(c, GMG_K_REDUCE, 0, GMG_F64, s,
                   [&] { return gmg::launch_fcg_fin(0, c->state, c->partials, nb, nullptr, s); }));
-    HIP_TRY(timed(c, GMG_K_CG_SPMV, 0, GMG_F64, s, [&] {
+    HIP_TRY(timed(c, GMG_K_FCG, 0, GMG_F64, s, [&] {
       return gmg::launch_fcg_dir<TZ>(V, z, c->vp, c->vq, c->vr, c->state, c->partials, &nb, s);
     }));
     HIP_TRY(timed(c, GMG_K_REDUCE, 0, GMG_F64, s,
                   [&] { return gmg::launch_fcg_fin(1, c->state, c->partials, nb, nullptr, s); }));
-    HIP_TRY(timed(c, GMG_K_AUX, 0, GMG_F64, s, [&] {
+    HIP_TRY(timed(c, GMG_K_FCG, 0, GMG_F64, s, [&] {
       return gmg::launch_fcg_update(V, u, c->vr, c->vp, c->vq, mixed ? c->er32 : nullptr,
                                     c->state, c->partials, &nb, s);
     }));
@@ -838,7 +851,7 @@ int gmg_solve(gmg_ctx* c, const double* f, double* u, double rtol, int maxit, in
   for (int it = 1; it <= maxit; ++it) {
     if ((st = vcycle_impl<float>(c, c->er32, c->eu32, s, true, false))) return st;
     int64_t nb = 0;
-    HIP_TRY(timed(c, GMG_K_RESIDUAL, 0, GMG_F64, s, [&] {
+    HIP_TRY(timed(c, GMG_K_CORRECT, 0, GMG_F64, s, [&] {
       return gmg::launch_correct_residual(V0, ucur, c->eu32, f, unext, c->er32, c->partials, &nb,
                                           s);
     }));
@@ -911,6 +924,7 @@ int pcg_solve(gmg_ctx* c, const double* f, double* u, double rtol, int maxit, in
     HIP_TRY(hipMemcpyAsync(c->hstate, c->state, sizeof(CgState), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     if (c->hstate->done || done_iters >= maxit) break;
+    if (done_iters > 0) chunk = predicted_chunk(*c->hstate, chunk);
     const int nq = std::min(chunk, maxit - done_iters);
     for (int q = 0; q < nq; ++q) {
       int64_t nb1 = 0, nb2 = 0;
@@ -927,7 +941,6 @@ int pcg_solve(gmg_ctx* c, const double* f, double* u, double rtol, int maxit, in
       }));
     }
     done_iters += nq;
-    chunk = std::min(2 * chunk, 32);
   }
   HIP_TRY(timed(c, GMG_K_AUX, 0, GMG_F64, s,
                 [&] { return gmg::launch_cg_final_update(V, u, c->vp, c->state, s); }));

@@ -312,6 +312,7 @@ __device__ __forceinline__ void line_body(const Lvl<T>& L, const LineArgs<T>& a,
     fkbytes = (uint32_t)a.F.ldx * ES;
   }
 
+  const T wmu = (T(1) - a.rho) / a.rho;  // smoothers: weight of M u
   T alpha = T(0);
   if constexpr (MODE == LINE_CG) alpha = a.init ? T(0) : (T)a.st->alpha;
   double acc_rr = 0.0, acc_rz = 0.0;
@@ -378,9 +379,18 @@ __device__ __forceinline__ void line_body(const Lvl<T>& L, const LineArgs<T>& a,
       if constexpr (MODE == LINE_SOLVE) {
         rhs = real ? v.r : T(0);
       } else if constexpr (kSmooth) {
+        // With M u the column's own block and g = f + dz K_h-sum of the
+        // neighbours, r = f - A u = g - M u and u' = u + rho M^-1 r solves
+        // M (u'/rho) = g + ((1 - rho)/rho) M u: the new iterate comes out of
+        // the elimination directly and u is not read again.
         const T h = c.ce * v.ue + c.cw * v.uw + c.cn * v.unn + c.cs * v.us;
-        const T au = diag * ucur - dzk * h + cpv * uprv + cnx * v.un;
-        rhs = real ? v.f - au : T(0);
+        const T mu = diag * ucur + cpv * uprv + cnx * v.un;
+        const T g = v.f + dzk * h;
+        rhs = real ? g + wmu * mu : T(0);
+        if constexpr (MODE == LINE_SMOOTH_NORM) {
+          const double r = (active && real) ? (double)(g - mu) : 0.0;
+          acc_rr = fma(r, r, acc_rr);
+        }
         uprv = ucur;
         ucur = v.un;
       } else if constexpr (MODE == LINE_RESTRICT_SMOOTH) {
@@ -411,12 +421,6 @@ __device__ __forceinline__ void line_body(const Lvl<T>& L, const LineArgs<T>& a,
     // rows of this segment: k_t = kseg + dir t
     int kseg = k0 + dir * (g * G);
     asm volatile("" : "+v"(kseg));
-    // the smoother adds the correction to u: fetch this segment's u first
-    T useg[kSmooth ? G : 1];
-    if constexpr (kSmooth) {
-#pragma unroll
-      for (int t = 0; t < G; ++t) useg[t] = ldo<T>(rA, off(kseg + dir * t, ic));
-    }
     // recompute c' (and the pivots) of the segment from its checkpoint
     T cseg[G], pseg[G];
     T cc = g == 0 ? T(0) : ckpt[g - 1];
@@ -440,7 +444,7 @@ __device__ __forceinline__ void line_body(const Lvl<T>& L, const LineArgs<T>& a,
       // elimination: rhs_k = d'_k piv_k + (coupling to the previous row) d'_{k-1}
       // (accurate to a few units of roundoff of the column's largest entry)
       T rk = T(0);
-      if constexpr (MODE != LINE_SOLVE && MODE != LINE_SMOOTH) {
+      if constexpr (MODE == LINE_CG || MODE == LINE_RESTRICT_SMOOTH) {
         const T cpv = half ? s_sup[k] : s_sub[k];
         rk = dp[s] * pseg[t] + (s > 0 ? cpv * dp[s > 0 ? s - 1 : 0] : T(0));
       }
@@ -448,7 +452,6 @@ __device__ __forceinline__ void line_body(const Lvl<T>& L, const LineArgs<T>& a,
         acc_rr += st ? (double)rk * (double)rk : 0.0;
         acc_rz += st ? (double)rk * (double)x : 0.0;
       }
-      if constexpr (MODE == LINE_SMOOTH_NORM) acc_rr += st ? (double)rk * (double)rk : 0.0;
       if (st) {
         const uint32_t o = off(k, ic);
         if constexpr (MODE == LINE_SOLVE) {
@@ -457,7 +460,7 @@ __device__ __forceinline__ void line_body(const Lvl<T>& L, const LineArgs<T>& a,
           sto<T>(rO1, o, rk);
           sto<T>(rO0, o, a.rho * x);
         } else if constexpr (kSmooth) {
-          sto<T>(rO0, o, useg[t] + a.rho * x);
+          sto<T>(rO0, o, a.rho * x);
         } else {
           sto<T>(rW, o, rk);
           sto<T>(rO0, o, x);

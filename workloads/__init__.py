@@ -27,8 +27,11 @@ pair (1 - U[2m], U[2m+1]), cos branch.
 
 from __future__ import annotations
 
+import concurrent.futures
 import dataclasses
 import math
+import os
+import threading
 
 import numpy as np
 
@@ -40,7 +43,7 @@ _M2 = np.array([0x94D049BB133111EB], dtype=np.uint64)
 _G = np.array([GAMMA], dtype=np.uint64)
 _S30, _S27, _S31, _S11 = (np.array([v], dtype=np.uint64) for v in (30, 27, 31, 11))
 _MASK64 = (1 << 64) - 1
-_CHUNK = 1 << 22
+_CHUNK = 1 << 18
 
 STREAM_KH = 0
 STREAM_SIZES = 1 << 31
@@ -51,17 +54,31 @@ def stream_state(seed: int, stream: int) -> int:
     return (int(seed) + int(stream) * (1 << 32)) & _MASK64
 
 
+def _workers() -> int:
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
 def _chunks(seed: int, stream: int, start: int, count: int, emit) -> None:
-    """Run SplitMix64 over outputs start..start+count-1 in reused chunk buffers,
-    handing each uint64 chunk to emit(c0, c1, chunk)."""
+    """Run SplitMix64 over outputs start..start+count-1 in chunks, handing each
+    uint64 chunk to emit(c0, c1, chunk).  Outputs are independent (counter
+    based), so chunks run on a thread pool (numpy releases the GIL inside the
+    ufuncs); emit must only touch its own slice [c0, c1)."""
     s0 = np.array([stream_state(seed, stream)], dtype=np.uint64)
-    m = max(1, min(count, _CHUNK))
-    z = np.empty(m, dtype=np.uint64)
-    t = np.empty(m, dtype=np.uint64)
-    for c0 in range(0, count, _CHUNK):
+    starts = list(range(0, count, _CHUNK))
+    local = threading.local()
+
+    def run(c0):
         c1 = min(count, c0 + _CHUNK)
         w = c1 - c0
-        zz, tt = z[:w], t[:w]
+        if getattr(local, "z", None) is None:
+            m = max(1, min(count, _CHUNK))
+            local.z = np.empty(m, dtype=np.uint64)
+            local.t = np.empty(m, dtype=np.uint64)
+        zz, tt = local.z[:w], local.t[:w]
         zz.view(np.int64)[:] = np.arange(start + c0 + 1, start + c1 + 1, dtype=np.int64)
         np.multiply(zz, _G, out=zz)
         np.add(zz, s0, out=zz)
@@ -72,6 +89,15 @@ def _chunks(seed: int, stream: int, start: int, count: int, emit) -> None:
         np.right_shift(zz, _S31, out=tt)
         np.bitwise_xor(zz, tt, out=zz)
         emit(c0, c1, zz)
+
+    nw = min(_workers(), len(starts))
+    if nw <= 1:
+        for c0 in starts:
+            run(c0)
+        return
+    with concurrent.futures.ThreadPoolExecutor(max_workers=nw) as ex:
+        for fut in [ex.submit(run, c0) for c0 in starts]:
+            fut.result()
 
 
 def splitmix64(seed: int, stream: int, start: int, count: int) -> np.ndarray:
