@@ -23,6 +23,8 @@
 // Workgroup ids are remapped so that each of the 8 XCDs (each with its own L2)
 // works on a contiguous band of tiles: neighbouring tiles share halo rows.
 
+#include <type_traits>
+
 #include "gmg_internal.h"
 
 namespace gmg {
@@ -69,16 +71,11 @@ __device__ __forceinline__ Col<T> load_col(const Lvl<T>& L, int i, int j) {
   return c;
 }
 
-template <typename T>
-__device__ __forceinline__ T hsum(const Col<T>& c, const T* __restrict__ x, int64_t o) {
-  return c.ce * x[o + c.oe] + c.cw * x[o + c.ow] + c.cn * x[o + c.on] + c.cs * x[o + c.os];
-}
-
 // Sum NC per-thread values over the workgroup; thread 0 stores them to
 // partials[blockIdx.x*NC + c].  Fixed order, so results are reproducible.
-template <int NC>
+template <int NC, int NW = NTHREADS / 64>
 __device__ __forceinline__ void block_partials(double (&v)[NC], double* __restrict__ partials) {
-  __shared__ double sm[NC][NTHREADS / 64];
+  __shared__ double sm[NC][NW];
 #pragma unroll
   for (int c = 0; c < NC; ++c)
 #pragma unroll
@@ -100,52 +97,254 @@ __device__ __forceinline__ void block_partials(double (&v)[NC], double* __restri
 }
 
 // ---------------------------------------------------------------------------
-// Stencil kernels: SpMV (y = Ax) and Residual (r = f - Ax, optional ||r||^2
-// and an FP32 copy of r for the mixed-precision refinement).
+// Stencil kernels.  A workgroup is SR wavefronts; wavefront w owns grid row
+// j = tj*SR + w (wave-uniform, so the row bases of every field are scalar
+// registers and each lane needs only 32-bit byte offsets) and 64 consecutive
+// columns; each lane walks its column through the KSEG layers of the
+// workgroup's segment.  The loads of the next CH layers are issued before the
+// current CH layers are computed and stored (a register double buffer): with
+// updates in place the compiler may not move a load of layer k+1 above a
+// store to layer k itself, and without the buffer every layer would wait for
+// the previous layer's stores.  The vertical profiles of the segment are
+// staged in LDS.
 // ---------------------------------------------------------------------------
-template <typename T, int MODE>
-__global__ __launch_bounds__(NTHREADS) void k_stencil(Lvl<T> L, const T* __restrict__ x,
-                                                      const T* __restrict__ f,
-                                                      T* __restrict__ y,
-                                                      float* __restrict__ ydown,
-                                                      double* __restrict__ partials, int nti,
-                                                      int ntj) {
-  const int b = xcd_remap(blockIdx.x, gridDim.x);
+struct Geo {
+  int j, jn, js;   // the wavefront's grid row and its periodic neighbours
+  int ic, ie, iw;  // the lane's column (clamped into the grid) and its neighbours
+  bool row, act;   // the row exists (wave-uniform); the lane's column exists
+  int k0, n;       // first layer and number of layers of the segment (uniform)
+};
+
+template <int SR>
+__device__ __forceinline__ Geo stencil_geo(int nx, int ny, int nz, int nti, int ntj, int b) {
+  Geo g;
   const int ti = b % nti;
   const int r1 = b / nti;
   const int tj = r1 % ntj;
   const int kb = r1 / ntj;
-  const int i = ti * 64 + (threadIdx.x & 63);
-  const int j = tj * SROWS + (threadIdx.x >> 6);
-  double nrm[1] = {0.0};
-  if (i < L.nx && j < L.ny) {
-    const Col<T> c = load_col(L, i, j);
-    const int nz = L.nz;
-    const int k0 = kb * KSEG;
-    const int k1 = min(nz, k0 + KSEG);
-    const int64_t ldx = L.ldx;
-    int64_t o = c.base + (int64_t)k0 * ldx;
-    T um = (k0 > 0) ? x[o - ldx] : T(0);
-    T uc = x[o];
-#pragma unroll 4
-    for (int k = k0; k < k1; ++k, o += ldx) {
-      const T up = (k + 1 < nz) ? x[o + ldx] : T(0);
-      const T h = hsum(c, x, o);
-      const T dzk = L.dz[k];
-      const T au = (L.dg[k] + dzk * c.S) * uc - dzk * h + L.sub[k] * um + L.sup[k] * up;
-      if constexpr (MODE == (int)Stencil::SPMV) {
-        y[o] = au;
-      } else {
-        const T rr = f[o] - au;
-        y[o] = rr;
-        if constexpr (MODE >= (int)Stencil::RESIDUAL_NORM) nrm[0] += (double)rr * (double)rr;
-        if constexpr (MODE == (int)Stencil::RESIDUAL_NORM_DOWN) ydown[o] = (float)rr;
-      }
-      um = uc;
-      uc = up;
+  const int i = ti * 64 + (int)(threadIdx.x & 63);
+  const int j = tj * SR + __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  g.row = j < ny;
+  g.j = min(j, ny - 1);
+  g.jn = (g.j + 1 == ny) ? 0 : g.j + 1;
+  g.js = (g.j == 0) ? ny - 1 : g.j - 1;
+  g.act = i < nx;
+  g.ic = min(i, nx - 1);
+  g.ie = (g.ic + 1 == nx) ? 0 : g.ic + 1;
+  g.iw = (g.ic == 0) ? nx - 1 : g.ic - 1;
+  g.k0 = kb * KSEG;
+  g.n = min(nz - g.k0, KSEG);
+  return g;
+}
+
+template <typename T>
+struct Prof {
+  T sub, sup, dg, dz;
+};
+
+// Vertical profiles of layers k0 .. k0+KSEG-1 (clamped) into LDS.
+template <typename T>
+__device__ __forceinline__ void stage_prof(const Lvl<T>& L, int k0, Prof<T>* sp) {
+  for (int t = threadIdx.x; t < KSEG; t += blockDim.x) {
+    const int k = min(k0 + t, L.nz - 1);
+    sp[t] = Prof<T>{L.sub[k], L.sup[k], L.dg[k], L.dz[k]};
+  }
+  __syncthreads();
+}
+
+// Face couplings of the lane's column and their sum.
+template <typename T>
+struct Cf {
+  T ce, cw, cn, cs, S;
+};
+
+template <typename T>
+__device__ __forceinline__ Cf<T> col_coef(const Lvl<T>& L, const Geo& g) {
+  const int64_t row = (int64_t)g.j * L.nx;
+  Cf<T> c;
+  c.ce = L.cx[row + g.ic];
+  c.cw = L.cx[row + g.iw];
+  c.cn = L.cy[row + g.ic];
+  c.cs = L.cy[(int64_t)g.js * L.nx + g.ic];
+  c.S = c.ce + c.cw + c.cn + c.cs;
+  return c;
+}
+
+// Byte base of grid row j of a field (layer 0, column 0).
+template <typename T>
+__device__ __forceinline__ const char* rowc(const T* f, int j, int64_t jstride) {
+  return reinterpret_cast<const char*>(f + (int64_t)j * jstride);
+}
+template <typename T>
+__device__ __forceinline__ char* roww(T* f, int j, int64_t jstride) {
+  return reinterpret_cast<char*>(f + (int64_t)j * jstride);
+}
+
+// Load/store through a wave-uniform base and a 32-bit per-lane byte offset
+// (the saddr form of the global memory instructions).
+template <typename T>
+__device__ __forceinline__ T ldo(const char* base, uint32_t off) {
+  return *reinterpret_cast<const T*>(base + off);
+}
+template <typename T>
+__device__ __forceinline__ void sto(char* base, uint32_t off, T v) {
+  *reinterpret_cast<T*>(base + off) = v;
+}
+
+// The layer walk shared by the stencil kernels: P supplies the per-layer
+// input record In, load(s, In&) for layer k0+s and step(s, const In&) that
+// computes and stores layer k0+s.  FULL: the segment has all KSEG layers.
+template <int CH, bool FULL, typename P>
+__device__ __forceinline__ void walk(P& pol, int n) {
+  using In = typename P::In;
+  constexpr int NCH = KSEG / CH;
+  In buf[2][CH];
+#pragma unroll
+  for (int t = 0; t < CH; ++t) pol.load(t, buf[0][t]);
+#pragma unroll
+  for (int ch = 0; ch < NCH; ++ch) {
+    if (ch + 1 < NCH) {
+#pragma unroll
+      for (int t = 0; t < CH; ++t) pol.load((ch + 1) * CH + t, buf[(ch + 1) & 1][t]);
+    }
+#pragma unroll
+    for (int t = 0; t < CH; ++t) {
+      const int st = ch * CH + t;
+      if (FULL || st < n) pol.step(st, buf[ch & 1][t]);
+    }
+    // keep later chunks' loads from being hoisted further (registers)
+    __builtin_amdgcn_sched_barrier(0);
+  }
+}
+
+// The 7-point operator on one lane's column, rolled through registers:
+// (A x)_k = (dg_k + dz_k S) x_k - dz_k (Kh-weighted sum of the four horizontal
+// neighbours) + sub_k x_{k-1} + sup_k x_{k+1}, x_{-1} = x_{nz} = 0.
+// x is stored as TS (FP32 for the mixed-precision flexible CG), the
+// arithmetic is in T.  Byte offsets oc/oe/ow and kb refer to TS elements.
+template <typename T, typename TS = T>
+struct ColumnOp {
+  const char *rx, *rxn, *rxs;
+  uint32_t oc, oe, ow, kb;
+  int nz, k0;
+  Cf<T> c;
+  const Prof<T>* sp;
+  T xm, xc;
+
+  __device__ __forceinline__ void init(const TS* x, const Geo& g, int64_t jstride,
+                                       uint32_t kbytes, const Cf<T>& cf, const Prof<T>* prof,
+                                       int nz_) {
+    rx = rowc(x, g.j, jstride);
+    rxn = rowc(x, g.jn, jstride);
+    rxs = rowc(x, g.js, jstride);
+    oc = (uint32_t)g.ic * sizeof(TS);
+    oe = (uint32_t)g.ie * sizeof(TS);
+    ow = (uint32_t)g.iw * sizeof(TS);
+    kb = kbytes;
+    nz = nz_;
+    k0 = g.k0;
+    c = cf;
+    sp = prof;
+    xm = k0 > 0 ? (T)ldo<TS>(rx, oc + (uint32_t)(k0 - 1) * kb) : T(0);
+    xc = (T)ldo<TS>(rx, oc + (uint32_t)k0 * kb);
+  }
+  // x at k+1 (clamped address), and the four horizontal neighbours at k
+  __device__ __forceinline__ void load(uint32_t ok, uint32_t okp, T& xp, T& xe, T& xw, T& xn,
+                                       T& xs) const {
+    xp = (T)ldo<TS>(rx, oc + okp);
+    xe = (T)ldo<TS>(rx, oe + ok);
+    xw = (T)ldo<TS>(rx, ow + ok);
+    xn = (T)ldo<TS>(rxn, oc + ok);
+    xs = (T)ldo<TS>(rxs, oc + ok);
+  }
+  // (A x) at layer k0+s; advances the rolled column
+  __device__ __forceinline__ T apply(int s, T xp_raw, T xe, T xw, T xn, T xs) {
+    const Prof<T> pr = sp[s];
+    const T xp = (k0 + s + 1 < nz) ? xp_raw : T(0);
+    const T h = c.ce * xe + c.cw * xw + c.cn * xn + c.cs * xs;
+    const T ax = (pr.dg + pr.dz * c.S) * xc - pr.dz * h + pr.sub * xm + pr.sup * xp;
+    xm = xc;
+    xc = xp;
+    return ax;
+  }
+};
+
+// Layer offsets: FULL segments never reach past nz-1; ragged ones clamp.
+template <bool FULL>
+__device__ __forceinline__ uint32_t layer_off(int k, int nz, uint32_t kb) {
+  return (uint32_t)(FULL ? k : min(k, nz - 1)) * kb;
+}
+
+// SpMV (y = Ax) and Residual (r = f - Ax, optional ||r||^2 partials and an
+// FP32 copy of r for the mixed-precision refinement).
+template <typename T, int MODE, bool FULL>
+struct StencilPol {
+  struct In {
+    T xp, xe, xw, xn, xs, f;
+  };
+  ColumnOp<T> op;
+  const char* rf;
+  char *ry, *rd;
+  double nrm;
+
+  __device__ __forceinline__ void load(int s, In& v) {
+    const int k = op.k0 + s;
+    const uint32_t ok = layer_off<FULL>(k, op.nz, op.kb);
+    const uint32_t okp = (uint32_t)min(k + 1, op.nz - 1) * op.kb;
+    op.load(ok, okp, v.xp, v.xe, v.xw, v.xn, v.xs);
+    if constexpr (MODE != (int)Stencil::SPMV) v.f = ldo<T>(rf, op.oc + ok);
+  }
+  __device__ __forceinline__ void step(int s, const In& v) {
+    const uint32_t o = op.oc + layer_off<FULL>(op.k0 + s, op.nz, op.kb);
+    const T ax = op.apply(s, v.xp, v.xe, v.xw, v.xn, v.xs);
+    if constexpr (MODE == (int)Stencil::SPMV) {
+      sto<T>(ry, o, ax);
+    } else {
+      const T rr = v.f - ax;
+      sto<T>(ry, o, rr);
+      if constexpr (MODE >= (int)Stencil::RESIDUAL_NORM) nrm += (double)rr * (double)rr;
+      if constexpr (MODE == (int)Stencil::RESIDUAL_NORM_DOWN)
+        sto<float>(rd, o / sizeof(T) * sizeof(float), (float)rr);
     }
   }
-  if constexpr (MODE >= (int)Stencil::RESIDUAL_NORM) block_partials<1>(nrm, partials);
+};
+
+template <typename T, int MODE, int SR>
+__global__ __launch_bounds__(64 * SR) void k_stencil(Lvl<T> L, const T* __restrict__ x,
+                                                     const T* __restrict__ f, T* __restrict__ y,
+                                                     float* __restrict__ ydown,
+                                                     double* __restrict__ partials, int nti,
+                                                     int ntj) {
+  constexpr int CH = sizeof(T) == 8 ? 4 : 8;
+  const Geo g = stencil_geo<SR>(L.nx, L.ny, L.nz, nti, ntj, xcd_remap(blockIdx.x, gridDim.x));
+  __shared__ Prof<T> sp[KSEG];
+  stage_prof(L, g.k0, sp);
+  double nrm[1] = {0.0};
+  if (g.row && g.act) {
+    const int64_t jstride = (int64_t)L.nz * L.ldx;
+    const uint32_t kb = (uint32_t)(L.ldx * sizeof(T));
+    const Cf<T> cf = col_coef(L, g);
+    if (g.n == KSEG) {
+      StencilPol<T, MODE, true> pol;
+      pol.op.init(x, g, jstride, kb, cf, sp, L.nz);
+      pol.rf = MODE != (int)Stencil::SPMV ? rowc(f, g.j, jstride) : nullptr;
+      pol.ry = roww(y, g.j, jstride);
+      pol.rd = MODE == (int)Stencil::RESIDUAL_NORM_DOWN ? roww(ydown, g.j, jstride) : nullptr;
+      pol.nrm = 0.0;
+      walk<CH, true>(pol, g.n);
+      nrm[0] = pol.nrm;
+    } else {
+      StencilPol<T, MODE, false> pol;
+      pol.op.init(x, g, jstride, kb, cf, sp, L.nz);
+      pol.rf = MODE != (int)Stencil::SPMV ? rowc(f, g.j, jstride) : nullptr;
+      pol.ry = roww(y, g.j, jstride);
+      pol.rd = MODE == (int)Stencil::RESIDUAL_NORM_DOWN ? roww(ydown, g.j, jstride) : nullptr;
+      pol.nrm = 0.0;
+      walk<CH, false>(pol, g.n);
+      nrm[0] = pol.nrm;
+    }
+  }
+  if constexpr (MODE >= (int)Stencil::RESIDUAL_NORM) block_partials<1, SR>(nrm, partials);
 }
 
 // ---------------------------------------------------------------------------
@@ -218,18 +417,6 @@ template <typename T>
 struct StepIn<T, LINE_RESTRICT_SMOOTH> { typename Vec2<T>::type lo, hi; };
 template <typename T>
 struct StepIn<T, LINE_CG> { T r, q; };
-
-// Load/store through a wave-uniform row base (SGPRs) and a 32-bit per-lane
-// byte offset: the compiler then emits the saddr form of global memory
-// instructions, one VGPR per address.
-template <typename T>
-__device__ __forceinline__ T ldo(const char* base, uint32_t off) {
-  return *reinterpret_cast<const T*>(base + off);
-}
-template <typename T>
-__device__ __forceinline__ void sto(char* base, uint32_t off, T v) {
-  *reinterpret_cast<T*>(base + off) = v;
-}
 
 // Body of the line kernels for tile b of a level (tiles of 32 columns x LROWS
 // rows, nti tiles across; wavefront w of the workgroup owns grid row
@@ -493,83 +680,139 @@ __global__ __launch_bounds__(NTHREADS) void k_line(Lvl<T> L, LineArgs<T> a, int 
 // residual itself is never stored.  A wavefront covers 64 coarse = 128 fine
 // columns and reads each fine row pair with 16-byte vector loads.
 // ---------------------------------------------------------------------------
-template <typename T>
-__device__ __forceinline__ void resrestrict_body(const Lvl<T>& F, const Lvl<T>& C,
-                                                 const T* __restrict__ u,
-                                                 const T* __restrict__ f, T* __restrict__ fc,
-                                                 int nti, int ntj, int b) {
+template <typename T, bool FULL>
+struct ResRestrictPol {
   using V2 = typename Vec2<T>::type;
-  const int ti = b % nti;
-  const int r1 = b / nti;
-  const int tj = r1 % ntj;
-  const int kb = r1 / ntj;
-  const int I = ti * 64 + (threadIdx.x & 63);
-  const int J = tj * SROWS + (threadIdx.x >> 6);
-  if (I >= C.nx || J >= C.ny) return;
-  const int nx = F.nx, ny = F.ny, nz = F.nz;
-  const int i0 = 2 * I, j0 = 2 * J;
-  const int iw = (i0 == 0) ? nx - 1 : i0 - 1;
-  const int ie = (i0 + 2 == nx) ? 0 : i0 + 2;
-  const int js = (j0 == 0) ? ny - 1 : j0 - 1;
-  const int jn = (j0 + 2 == ny) ? 0 : j0 + 2;
-  // face couplings of the 2x2 block: a = (i0,j0), b = (i0+1,j0), c = (i0,j0+1),
-  // d = (i0+1,j0+1)
-  const int64_t r0 = (int64_t)j0 * nx, r1c = (int64_t)(j0 + 1) * nx, rs = (int64_t)js * nx;
-  const T xab = F.cx[r0 + i0], xbE = F.cx[r0 + i0 + 1], xWa = F.cx[r0 + iw];
-  const T xcd = F.cx[r1c + i0], xdE = F.cx[r1c + i0 + 1], xWc = F.cx[r1c + iw];
-  const T yac = F.cy[r0 + i0], ybd = F.cy[r0 + i0 + 1];
-  const T ycN = F.cy[r1c + i0], ydN = F.cy[r1c + i0 + 1];
-  const T ySa = F.cy[rs + i0], ySb = F.cy[rs + i0 + 1];
-  const T Sa = xab + xWa + yac + ySa;
-  const T Sb = xbE + xab + ybd + ySb;
-  const T Sc = xcd + xWc + ycN + yac;
-  const T Sd = xdE + xcd + ydN + ybd;
-  const int64_t jst = (int64_t)nz * F.ldx;
-  const int64_t ra = (int64_t)j0 * jst, rc = (int64_t)(j0 + 1) * jst;
-  const int64_t rS = (int64_t)js * jst, rN = (int64_t)jn * jst;
-  const int64_t ldx = F.ldx;
-  const int k0 = kb * KSEG, k1 = min(nz, k0 + KSEG);
-  V2 m0 = {T(0), T(0)}, m1 = {T(0), T(0)};
-  if (k0 > 0) {
-    m0 = *reinterpret_cast<const V2*>(u + ra + (int64_t)(k0 - 1) * ldx + i0);
-    m1 = *reinterpret_cast<const V2*>(u + rc + (int64_t)(k0 - 1) * ldx + i0);
+  struct In {
+    V2 p0, p1, sS, sN, f0, f1;
+    T uWa, uEb, uWc, uEd;
+  };
+  const char *ra, *rc, *rS, *rN, *fa, *fb;
+  char* ro;
+  uint32_t o2, ow, oe, oo, fkb, ckb;
+  int nz, k0;
+  // face couplings of the 2x2 block: a = (i0,j0), b = (i0+1,j0),
+  // c = (i0,j0+1), d = (i0+1,j0+1)
+  T xab, xbE, xWa, xcd, xdE, xWc, yac, ybd, ycN, ydN, ySa, ySb, Sa, Sb, Sc, Sd;
+  const Prof<T>* sp;
+  V2 m0, m1, c0, c1;
+
+  __device__ __forceinline__ void load(int s, In& v) {
+    const int k = k0 + s;
+    const uint32_t ok = layer_off<FULL>(k, nz, fkb);
+    const uint32_t okp = (uint32_t)min(k + 1, nz - 1) * fkb;
+    v.p0 = ldo<V2>(ra, o2 + okp);
+    v.p1 = ldo<V2>(rc, o2 + okp);
+    v.uWa = ldo<T>(ra, ow + ok);
+    v.uEb = ldo<T>(ra, oe + ok);
+    v.uWc = ldo<T>(rc, ow + ok);
+    v.uEd = ldo<T>(rc, oe + ok);
+    v.sS = ldo<V2>(rS, o2 + ok);
+    v.sN = ldo<V2>(rN, o2 + ok);
+    v.f0 = ldo<V2>(fa, o2 + ok);
+    v.f1 = ldo<V2>(fb, o2 + ok);
   }
-  V2 c0 = *reinterpret_cast<const V2*>(u + ra + (int64_t)k0 * ldx + i0);
-  V2 c1 = *reinterpret_cast<const V2*>(u + rc + (int64_t)k0 * ldx + i0);
-  const int64_t ocj = (int64_t)J * C.nz * C.ldx + I;
-#pragma unroll 2
-  for (int k = k0; k < k1; ++k) {
-    const int64_t ok = (int64_t)k * ldx;
-    V2 p0 = {T(0), T(0)}, p1 = {T(0), T(0)};
-    if (k + 1 < nz) {
-      p0 = *reinterpret_cast<const V2*>(u + ra + ok + ldx + i0);
-      p1 = *reinterpret_cast<const V2*>(u + rc + ok + ldx + i0);
-    }
-    const T uWa = u[ra + ok + iw], uEb = u[ra + ok + ie];
-    const T uWc = u[rc + ok + iw], uEd = u[rc + ok + ie];
-    const V2 sS = *reinterpret_cast<const V2*>(u + rS + ok + i0);
-    const V2 sN = *reinterpret_cast<const V2*>(u + rN + ok + i0);
-    const V2 f0 = *reinterpret_cast<const V2*>(f + ra + ok + i0);
-    const V2 f1 = *reinterpret_cast<const V2*>(f + rc + ok + i0);
-    const T dzk = F.dz[k], dgk = F.dg[k], sub = F.sub[k], sup = F.sup[k];
-    const T ra_ = f0.x - ((dgk + dzk * Sa) * c0.x -
-                          dzk * (xab * c0.y + xWa * uWa + yac * c1.x + ySa * sS.x) +
-                          sub * m0.x + sup * p0.x);
-    const T rb_ = f0.y - ((dgk + dzk * Sb) * c0.y -
-                          dzk * (xbE * uEb + xab * c0.x + ybd * c1.y + ySb * sS.y) +
-                          sub * m0.y + sup * p0.y);
-    const T rc_ = f1.x - ((dgk + dzk * Sc) * c1.x -
-                          dzk * (xcd * c1.y + xWc * uWc + ycN * sN.x + yac * c0.x) +
-                          sub * m1.x + sup * p1.x);
-    const T rd_ = f1.y - ((dgk + dzk * Sd) * c1.y -
-                          dzk * (xdE * uEd + xcd * c1.x + ydN * sN.y + ybd * c0.y) +
-                          sub * m1.y + sup * p1.y);
-    fc[ocj + (int64_t)k * C.ldx] = ra_ + rb_ + rc_ + rd_;
+  __device__ __forceinline__ void step(int s, const In& v) {
+    const int k = k0 + s;
+    const Prof<T> pr = sp[s];
+    const bool top = k + 1 < nz;
+    const V2 p0 = top ? v.p0 : V2{T(0), T(0)};
+    const V2 p1 = top ? v.p1 : V2{T(0), T(0)};
+    const T dzk = pr.dz, dgk = pr.dg, sub = pr.sub, sup = pr.sup;
+    const T ra_ = v.f0.x - ((dgk + dzk * Sa) * c0.x -
+                            dzk * (xab * c0.y + xWa * v.uWa + yac * c1.x + ySa * v.sS.x) +
+                            sub * m0.x + sup * p0.x);
+    const T rb_ = v.f0.y - ((dgk + dzk * Sb) * c0.y -
+                            dzk * (xbE * v.uEb + xab * c0.x + ybd * c1.y + ySb * v.sS.y) +
+                            sub * m0.y + sup * p0.y);
+    const T rc_ = v.f1.x - ((dgk + dzk * Sc) * c1.x -
+                            dzk * (xcd * c1.y + xWc * v.uWc + ycN * v.sN.x + yac * c0.x) +
+                            sub * m1.x + sup * p1.x);
+    const T rd_ = v.f1.y - ((dgk + dzk * Sd) * c1.y -
+                            dzk * (xdE * v.uEd + xcd * c1.x + ydN * v.sN.y + ybd * c0.y) +
+                            sub * m1.y + sup * p1.y);
+    sto<T>(ro, oo + layer_off<FULL>(k, nz, ckb), ra_ + rb_ + rc_ + rd_);
     m0 = c0;
     m1 = c1;
     c0 = p0;
     c1 = p1;
   }
+};
+
+// Residual of the fine level fused with the restriction (Algorithm 1: the
+// residual is only needed restricted): f_c(I,J) = sum over the 2x2 children of
+// (f - A u).  One lane per coarse column; its four children are read as two
+// 2-vectors per layer.  The fine residual itself is never stored.
+template <typename T>
+__device__ __forceinline__ void resrestrict_body(const Lvl<T>& F, const Lvl<T>& C,
+                                                 const T* __restrict__ u,
+                                                 const T* __restrict__ f, T* __restrict__ fc,
+                                                 int nti, int ntj, int b) {
+  constexpr int CH = sizeof(T) == 8 ? 1 : 2;
+  const Geo g = stencil_geo<SROWS>(C.nx, C.ny, C.nz, nti, ntj, b);
+  __shared__ Prof<T> sp[KSEG];
+  stage_prof(F, g.k0, sp);
+  if (!(g.row && g.act)) return;
+  const int nx = F.nx, ny = F.ny, nz = F.nz;
+  const int I = g.ic, J = g.j;
+  const int i0 = 2 * I, j0 = 2 * J;
+  const int iw = (i0 == 0) ? nx - 1 : i0 - 1;
+  const int ie = (i0 + 2 == nx) ? 0 : i0 + 2;
+  const int js = (j0 == 0) ? ny - 1 : j0 - 1;
+  const int jn = (j0 + 2 == ny) ? 0 : j0 + 2;
+  const int64_t jst = (int64_t)nz * F.ldx;
+  const uint32_t ES = sizeof(T);
+  auto run = [&](auto full) {
+    constexpr bool FL = decltype(full)::value;
+    ResRestrictPol<T, FL> P;
+    const int64_t r0 = (int64_t)j0 * nx, r1c = (int64_t)(j0 + 1) * nx, rs = (int64_t)js * nx;
+    P.xab = F.cx[r0 + i0];
+    P.xbE = F.cx[r0 + i0 + 1];
+    P.xWa = F.cx[r0 + iw];
+    P.xcd = F.cx[r1c + i0];
+    P.xdE = F.cx[r1c + i0 + 1];
+    P.xWc = F.cx[r1c + iw];
+    P.yac = F.cy[r0 + i0];
+    P.ybd = F.cy[r0 + i0 + 1];
+    P.ycN = F.cy[r1c + i0];
+    P.ydN = F.cy[r1c + i0 + 1];
+    P.ySa = F.cy[rs + i0];
+    P.ySb = F.cy[rs + i0 + 1];
+    P.Sa = P.xab + P.xWa + P.yac + P.ySa;
+    P.Sb = P.xbE + P.xab + P.ybd + P.ySb;
+    P.Sc = P.xcd + P.xWc + P.ycN + P.yac;
+    P.Sd = P.xdE + P.xcd + P.ydN + P.ybd;
+    P.ra = rowc(u, j0, jst);
+    P.rc = rowc(u, j0 + 1, jst);
+    P.rS = rowc(u, js, jst);
+    P.rN = rowc(u, jn, jst);
+    P.fa = rowc(f, j0, jst);
+    P.fb = rowc(f, j0 + 1, jst);
+    P.ro = roww(fc, J, (int64_t)C.nz * C.ldx);
+    P.o2 = (uint32_t)i0 * ES;
+    P.ow = (uint32_t)iw * ES;
+    P.oe = (uint32_t)ie * ES;
+    P.oo = (uint32_t)I * ES;
+    P.fkb = (uint32_t)F.ldx * ES;
+    P.ckb = (uint32_t)C.ldx * ES;
+    P.nz = nz;
+    P.k0 = g.k0;
+    P.sp = sp;
+    using V2 = typename Vec2<T>::type;
+    P.m0 = V2{T(0), T(0)};
+    P.m1 = V2{T(0), T(0)};
+    if (g.k0 > 0) {
+      P.m0 = ldo<V2>(P.ra, P.o2 + (uint32_t)(g.k0 - 1) * P.fkb);
+      P.m1 = ldo<V2>(P.rc, P.o2 + (uint32_t)(g.k0 - 1) * P.fkb);
+    }
+    P.c0 = ldo<V2>(P.ra, P.o2 + (uint32_t)g.k0 * P.fkb);
+    P.c1 = ldo<V2>(P.rc, P.o2 + (uint32_t)g.k0 * P.fkb);
+    walk<CH, FL>(P, g.n);
+  };
+  if (g.n == KSEG)
+    run(std::true_type{});
+  else
+    run(std::false_type{});
 }
 
 template <typename T>
@@ -585,42 +828,101 @@ __global__ __launch_bounds__(NTHREADS) void k_resrestrict(Lvl<T> F, Lvl<T> C,
 // r = f - A u', r32 = (float) r, partial ||r||^2.  u' goes to a different
 // buffer (neighbouring threads still read u and e).
 // ---------------------------------------------------------------------------
+template <bool FULL>
+struct CorrectPol {
+  struct In {
+    double up, ue, uw, un, us, f;
+    float ep, ee, ew, en, es;
+  };
+  const char *ru, *run, *rus, *re, *ren, *res, *rf;
+  char *ruo, *rr32;
+  uint32_t oc8, oe8, ow8, oc4, oe4, ow4, kb8, kb4;
+  int nz, k0;
+  Cf<double> c;
+  const Prof<double>* sp;
+  double xm, xc, nrm;
+
+  __device__ __forceinline__ void load(int s, In& v) {
+    const int k = k0 + s;
+    const int kc = FULL ? k : min(k, nz - 1);
+    const int kp = min(k + 1, nz - 1);
+    const uint32_t o8 = (uint32_t)kc * kb8, o4 = (uint32_t)kc * kb4;
+    v.up = ldo<double>(ru, oc8 + (uint32_t)kp * kb8);
+    v.ep = ldo<float>(re, oc4 + (uint32_t)kp * kb4);
+    v.ue = ldo<double>(ru, oe8 + o8);
+    v.ee = ldo<float>(re, oe4 + o4);
+    v.uw = ldo<double>(ru, ow8 + o8);
+    v.ew = ldo<float>(re, ow4 + o4);
+    v.un = ldo<double>(run, oc8 + o8);
+    v.en = ldo<float>(ren, oc4 + o4);
+    v.us = ldo<double>(rus, oc8 + o8);
+    v.es = ldo<float>(res, oc4 + o4);
+    v.f = ldo<double>(rf, oc8 + o8);
+  }
+  __device__ __forceinline__ void step(int s, const In& v) {
+    const int k = k0 + s;
+    const Prof<double> pr = sp[s];
+    const double xp = (k + 1 < nz) ? v.up + (double)v.ep : 0.0;
+    const double h = c.ce * (v.ue + (double)v.ee) + c.cw * (v.uw + (double)v.ew) +
+                     c.cn * (v.un + (double)v.en) + c.cs * (v.us + (double)v.es);
+    const double au = (pr.dg + pr.dz * c.S) * xc - pr.dz * h + pr.sub * xm + pr.sup * xp;
+    const double rr = v.f - au;
+    const int kc = FULL ? k : min(k, nz - 1);
+    sto<double>(ruo, oc8 + (uint32_t)kc * kb8, xc);
+    sto<float>(rr32, oc4 + (uint32_t)kc * kb4, (float)rr);
+    nrm += rr * rr;
+    xm = xc;
+    xc = xp;
+  }
+};
+
 __device__ __forceinline__ void correct_residual_body(
     const Lvl<double>& L, const double* __restrict__ u, const float* __restrict__ e,
     const double* __restrict__ f, double* __restrict__ uout, float* __restrict__ r32,
     double* __restrict__ partials, int nti, int ntj, int b) {
-  const int ti = b % nti;
-  const int r1 = b / nti;
-  const int tj = r1 % ntj;
-  const int kb = r1 / ntj;
-  const int i = ti * 64 + (threadIdx.x & 63);
-  const int j = tj * SROWS + (threadIdx.x >> 6);
+  const Geo g = stencil_geo<SROWS>(L.nx, L.ny, L.nz, nti, ntj, b);
+  __shared__ Prof<double> sp[KSEG];
+  stage_prof(L, g.k0, sp);
   double nrm[1] = {0.0};
-  if (i < L.nx && j < L.ny) {
-    const Col<double> c = load_col(L, i, j);
-    const int nz = L.nz;
-    const int k0 = kb * KSEG;
-    const int k1 = min(nz, k0 + KSEG);
-    const int64_t ldx = L.ldx;
-    int64_t o = c.base + (int64_t)k0 * ldx;
-    double um = (k0 > 0) ? u[o - ldx] + (double)e[o - ldx] : 0.0;
-    double uc = u[o] + (double)e[o];
-#pragma unroll 2
-    for (int k = k0; k < k1; ++k, o += ldx) {
-      const double up = (k + 1 < nz) ? u[o + ldx] + (double)e[o + ldx] : 0.0;
-      const double h = c.ce * (u[o + c.oe] + (double)e[o + c.oe]) +
-                       c.cw * (u[o + c.ow] + (double)e[o + c.ow]) +
-                       c.cn * (u[o + c.on] + (double)e[o + c.on]) +
-                       c.cs * (u[o + c.os] + (double)e[o + c.os]);
-      const double dzk = L.dz[k];
-      const double au = (L.dg[k] + dzk * c.S) * uc - dzk * h + L.sub[k] * um + L.sup[k] * up;
-      const double rr = f[o] - au;
-      uout[o] = uc;
-      r32[o] = (float)rr;
-      nrm[0] += rr * rr;
-      um = uc;
-      uc = up;
-    }
+  if (g.row && g.act) {
+    const int64_t jst = (int64_t)L.nz * L.ldx;
+    auto run = [&](auto full) {
+      constexpr bool FL = decltype(full)::value;
+      CorrectPol<FL> P;
+      P.ru = rowc(u, g.j, jst);
+      P.run = rowc(u, g.jn, jst);
+      P.rus = rowc(u, g.js, jst);
+      P.re = rowc(e, g.j, jst);
+      P.ren = rowc(e, g.jn, jst);
+      P.res = rowc(e, g.js, jst);
+      P.rf = rowc(f, g.j, jst);
+      P.ruo = roww(uout, g.j, jst);
+      P.rr32 = roww(r32, g.j, jst);
+      P.oc8 = (uint32_t)g.ic * 8;
+      P.oe8 = (uint32_t)g.ie * 8;
+      P.ow8 = (uint32_t)g.iw * 8;
+      P.oc4 = (uint32_t)g.ic * 4;
+      P.oe4 = (uint32_t)g.ie * 4;
+      P.ow4 = (uint32_t)g.iw * 4;
+      P.kb8 = (uint32_t)L.ldx * 8;
+      P.kb4 = (uint32_t)L.ldx * 4;
+      P.nz = L.nz;
+      P.k0 = g.k0;
+      P.c = col_coef(L, g);
+      P.sp = sp;
+      P.nrm = 0.0;
+      P.xm = g.k0 > 0 ? ldo<double>(P.ru, P.oc8 + (uint32_t)(g.k0 - 1) * P.kb8) +
+                            (double)ldo<float>(P.re, P.oc4 + (uint32_t)(g.k0 - 1) * P.kb4)
+                      : 0.0;
+      P.xc = ldo<double>(P.ru, P.oc8 + (uint32_t)g.k0 * P.kb8) +
+             (double)ldo<float>(P.re, P.oc4 + (uint32_t)g.k0 * P.kb4);
+      walk<2, FL>(P, g.n);
+      nrm[0] = P.nrm;
+    };
+    if (g.n == KSEG)
+      run(std::true_type{});
+    else
+      run(std::false_type{});
   }
   block_partials<1>(nrm, partials);
 }
@@ -636,33 +938,66 @@ __global__ __launch_bounds__(NTHREADS) void k_correct_residual(
 // ---------------------------------------------------------------------------
 // Prolongate: uf += P uc (cell-centred bilinear, 9/3/3/1 over 16, periodic)
 // ---------------------------------------------------------------------------
+template <typename T, bool FULL>
+struct ProlongPol {
+  struct In {
+    T a, b, c, d, u;
+  };
+  const char *rc0, *rc1;
+  char* rf;
+  uint32_t oI, oI2, of, ckb, fkb;
+  int nz, k0;
+
+  __device__ __forceinline__ void load(int s, In& v) {
+    const int k = k0 + s;
+    const uint32_t okc = layer_off<FULL>(k, nz, ckb);
+    v.a = ldo<T>(rc0, oI + okc);
+    v.b = ldo<T>(rc0, oI2 + okc);
+    v.c = ldo<T>(rc1, oI + okc);
+    v.d = ldo<T>(rc1, oI2 + okc);
+    v.u = ldo<T>(rf, of + layer_off<FULL>(k, nz, fkb));
+  }
+  __device__ __forceinline__ void step(int s, const In& v) {
+    const T p = T(9) * v.a + T(3) * v.b + T(3) * v.c + v.d;
+    sto<T>(rf, of + layer_off<FULL>(k0 + s, nz, fkb), v.u + p * T(0.0625));
+  }
+};
+
+// One lane per fine column (i, j); its coarse parent (I, J) = (i/2, j/2) and
+// the coarse neighbours on the child's side, I2 = I -+ 1, J2 = J -+ 1
+// (periodic), weighted 9/3/3/1 over 16.
 template <typename T>
 __device__ __forceinline__ void prolongate_body(const Lvl<T>& C, const Lvl<T>& F,
                                                 const T* __restrict__ uc, T* __restrict__ uf,
                                                 int nti, int ntj, int b) {
-  const int ti = b % nti;
-  const int r1 = b / nti;
-  const int tj = r1 % ntj;
-  const int kb = r1 / ntj;
-  const int i = ti * 64 + (threadIdx.x & 63);
-  const int j = tj * SROWS + (threadIdx.x >> 6);
-  if (i >= F.nx || j >= F.ny) return;
-  const int I = i >> 1, J = j >> 1;
-  int I2 = I + ((i & 1) ? 1 : -1);
-  int J2 = J + ((j & 1) ? 1 : -1);
+  const Geo g = stencil_geo<SROWS>(F.nx, F.ny, F.nz, nti, ntj, b);
+  if (!(g.row && g.act)) return;
+  const int I = g.ic >> 1, J = g.j >> 1;
+  int I2 = I + ((g.ic & 1) ? 1 : -1);
+  int J2 = J + ((g.j & 1) ? 1 : -1);
   I2 = (I2 < 0) ? C.nx - 1 : (I2 == C.nx ? 0 : I2);
   J2 = (J2 < 0) ? C.ny - 1 : (J2 == C.ny ? 0 : J2);
-  const int64_t cjs = (int64_t)C.nz * C.ldx;
-  const int64_t c00 = (int64_t)J * cjs + I, c10 = (int64_t)J * cjs + I2;
-  const int64_t c01 = (int64_t)J2 * cjs + I, c11 = (int64_t)J2 * cjs + I2;
-  const int64_t fb = (int64_t)j * F.nz * F.ldx + i;
-  const int k0 = kb * KSEG, k1 = min(F.nz, k0 + KSEG);
-#pragma unroll 4
-  for (int k = k0; k < k1; ++k) {
-    const int64_t kc = (int64_t)k * C.ldx;
-    const T v = T(9) * uc[c00 + kc] + T(3) * uc[c10 + kc] + T(3) * uc[c01 + kc] + uc[c11 + kc];
-    uf[fb + (int64_t)k * F.ldx] += v * T(0.0625);
-  }
+  const uint32_t ES = sizeof(T);
+  auto run = [&](auto full) {
+    constexpr bool FL = decltype(full)::value;
+    ProlongPol<T, FL> P;
+    const int64_t cjs = (int64_t)C.nz * C.ldx;
+    P.rc0 = rowc(uc, J, cjs);
+    P.rc1 = rowc(uc, J2, cjs);
+    P.rf = roww(uf, g.j, (int64_t)F.nz * F.ldx);
+    P.oI = (uint32_t)I * ES;
+    P.oI2 = (uint32_t)I2 * ES;
+    P.of = (uint32_t)g.ic * ES;
+    P.ckb = (uint32_t)C.ldx * ES;
+    P.fkb = (uint32_t)F.ldx * ES;
+    P.nz = F.nz;
+    P.k0 = g.k0;
+    walk<4, FL>(P, g.n);
+  };
+  if (g.n == KSEG)
+    run(std::true_type{});
+  else
+    run(std::false_type{});
 }
 
 template <typename T>
@@ -676,50 +1011,75 @@ __global__ __launch_bounds__(NTHREADS) void k_prolongate(Lvl<T> C, Lvl<T> F,
 // CG, first fused kernel ("SpMV" of Sec. 3.1):
 //   u += alpha p;  p = z + beta p;  q = A z + beta q;  partial <p, q>
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(NTHREADS) void k_cg_p1(Lvl<double> L, double* __restrict__ u,
-                                                    double* __restrict__ p,
-                                                    const double* __restrict__ z,
-                                                    double* __restrict__ q,
-                                                    const CgState* __restrict__ st,
-                                                    double* __restrict__ partials, int nti,
-                                                    int ntj) {
-  if (st->done) return;
-  const double alpha = st->alpha, beta = st->beta;
-  const int b = xcd_remap(blockIdx.x, gridDim.x);
-  const int ti = b % nti;
-  const int r1 = b / nti;
-  const int tj = r1 % ntj;
-  const int kb = r1 / ntj;
-  const int i = ti * 64 + (threadIdx.x & 63);
-  const int j = tj * SROWS + (threadIdx.x >> 6);
-  double pq[1] = {0.0};
-  if (i < L.nx && j < L.ny) {
-    const Col<double> c = load_col(L, i, j);
-    const int nz = L.nz;
-    const int k0 = kb * KSEG;
-    const int k1 = min(nz, k0 + KSEG);
-    const int64_t ldx = L.ldx;
-    int64_t o = c.base + (int64_t)k0 * ldx;
-    double zm = (k0 > 0) ? z[o - ldx] : 0.0;
-    double zc = z[o];
-#pragma unroll 4
-    for (int k = k0; k < k1; ++k, o += ldx) {
-      const double zp = (k + 1 < nz) ? z[o + ldx] : 0.0;
-      const double dzk = L.dz[k];
-      const double az = (L.dg[k] + dzk * c.S) * zc - dzk * hsum(c, z, o) + L.sub[k] * zm +
-                        L.sup[k] * zp;
-      const double pold = p[o];
-      u[o] += alpha * pold;
-      const double pn = zc + beta * pold;
-      const double qn = az + beta * q[o];
-      p[o] = pn;
-      q[o] = qn;
-      pq[0] += pn * qn;
-      zm = zc;
-      zc = zp;
-    }
+template <bool FULL>
+struct CgP1Pol {
+  struct In {
+    double xp, xe, xw, xn, xs, p, q, u;
+  };
+  ColumnOp<double> op;  // on z
+  char *ru, *rp, *rq;
+  double alpha, beta, pq;
+
+  __device__ __forceinline__ void load(int s, In& v) {
+    const int k = op.k0 + s;
+    const uint32_t ok = layer_off<FULL>(k, op.nz, op.kb);
+    const uint32_t okp = (uint32_t)min(k + 1, op.nz - 1) * op.kb;
+    op.load(ok, okp, v.xp, v.xe, v.xw, v.xn, v.xs);
+    v.p = ldo<double>(rp, op.oc + ok);
+    v.q = ldo<double>(rq, op.oc + ok);
+    v.u = ldo<double>(ru, op.oc + ok);
   }
-  block_partials<1>(pq, partials);
+  __device__ __forceinline__ void step(int s, const In& v) {
+    const uint32_t o = op.oc + layer_off<FULL>(op.k0 + s, op.nz, op.kb);
+    const double zc = op.xc;
+    const double az = op.apply(s, v.xp, v.xe, v.xw, v.xn, v.xs);
+    const double pn = zc + beta * v.p;
+    const double qn = az + beta * v.q;
+    sto<double>(ru, o, v.u + alpha * v.p);
+    sto<double>(rp, o, pn);
+    sto<double>(rq, o, qn);
+    pq += pn * qn;
+  }
+};
+
+template <int SR>
+__global__ __launch_bounds__(64 * SR) void k_cg_p1(Lvl<double> L, double* __restrict__ u,
+                                                   double* __restrict__ p,
+                                                   const double* __restrict__ z,
+                                                   double* __restrict__ q,
+                                                   const CgState* __restrict__ st,
+                                                   double* __restrict__ partials, int nti,
+                                                   int ntj) {
+  if (st->done) return;  // uniform: the solve has already stopped
+  constexpr int CH = 2;
+  const double alpha = st->alpha, beta = st->beta;
+  const Geo g = stencil_geo<SR>(L.nx, L.ny, L.nz, nti, ntj, xcd_remap(blockIdx.x, gridDim.x));
+  __shared__ Prof<double> sp[KSEG];
+  stage_prof(L, g.k0, sp);
+  double pq[1] = {0.0};
+  if (g.row && g.act) {
+    const int64_t jstride = (int64_t)L.nz * L.ldx;
+    const uint32_t kb = (uint32_t)(L.ldx * sizeof(double));
+    const Cf<double> cf = col_coef(L, g);
+    auto run = [&](auto full) {
+      constexpr bool F = decltype(full)::value;
+      CgP1Pol<F> pol;
+      pol.op.init(z, g, jstride, kb, cf, sp, L.nz);
+      pol.ru = roww(u, g.j, jstride);
+      pol.rp = roww(p, g.j, jstride);
+      pol.rq = roww(q, g.j, jstride);
+      pol.alpha = alpha;
+      pol.beta = beta;
+      pol.pq = 0.0;
+      walk<CH, F>(pol, g.n);
+      pq[0] = pol.pq;
+    };
+    if (g.n == KSEG)
+      run(std::true_type{});
+    else
+      run(std::false_type{});
+  }
+  block_partials<1, SR>(pq, partials);
 }
 
 // ---------------------------------------------------------------------------
@@ -753,6 +1113,39 @@ __global__ __launch_bounds__(NTHREADS) void k_fcg_zq(Lvl<double> L, const TZ* __
   block_partials<1>(acc, partials);
 }
 
+template <typename TZ, bool FULL>
+struct FcgDirPol {
+  struct In {
+    double xp, xe, xw, xn, xs, p, q, r;
+  };
+  ColumnOp<double, TZ> op;  // on z
+  char *rp, *rq;
+  const char* rr;
+  uint32_t oc, kb;
+  double beta, pq, pr;
+
+  __device__ __forceinline__ void load(int s, In& v) {
+    const int k = op.k0 + s;
+    op.load(layer_off<FULL>(k, op.nz, op.kb), (uint32_t)min(k + 1, op.nz - 1) * op.kb, v.xp,
+            v.xe, v.xw, v.xn, v.xs);
+    const uint32_t o = oc + layer_off<FULL>(k, op.nz, kb);
+    v.p = ldo<double>(rp, o);
+    v.q = ldo<double>(rq, o);
+    v.r = ldo<double>(rr, o);
+  }
+  __device__ __forceinline__ void step(int s, const In& v) {
+    const uint32_t o = oc + layer_off<FULL>(op.k0 + s, op.nz, kb);
+    const double zc = op.xc;
+    const double az = op.apply(s, v.xp, v.xe, v.xw, v.xn, v.xs);
+    const double pn = zc + beta * v.p;
+    const double qn = az + beta * v.q;
+    sto<double>(rp, o, pn);
+    sto<double>(rq, o, qn);
+    pq += pn * qn;
+    pr += pn * v.r;
+  }
+};
+
 template <typename TZ>
 __global__ __launch_bounds__(NTHREADS) void k_fcg_dir(Lvl<double> L, const TZ* __restrict__ z,
                                                       double* __restrict__ p,
@@ -762,41 +1155,65 @@ __global__ __launch_bounds__(NTHREADS) void k_fcg_dir(Lvl<double> L, const TZ* _
                                                       double* __restrict__ partials, int nti,
                                                       int ntj) {
   const double beta = st->beta;
-  const int b = xcd_remap(blockIdx.x, gridDim.x);
-  const int ti = b % nti;
-  const int r1 = b / nti;
-  const int tj = r1 % ntj;
-  const int kb = r1 / ntj;
-  const int i = ti * 64 + (threadIdx.x & 63);
-  const int j = tj * SROWS + (threadIdx.x >> 6);
+  const Geo g = stencil_geo<SROWS>(L.nx, L.ny, L.nz, nti, ntj, xcd_remap(blockIdx.x, gridDim.x));
+  __shared__ Prof<double> sp[KSEG];
+  stage_prof(L, g.k0, sp);
   double acc[2] = {0.0, 0.0};
-  if (i < L.nx && j < L.ny) {
-    const Col<double> c = load_col(L, i, j);
-    const int nz = L.nz;
-    const int k0 = kb * KSEG;
-    const int k1 = min(nz, k0 + KSEG);
-    const int64_t ldx = L.ldx;
-    int64_t o = c.base + (int64_t)k0 * ldx;
-    double zm = (k0 > 0) ? (double)z[o - ldx] : 0.0;
-    double zc = (double)z[o];
-    for (int k = k0; k < k1; ++k, o += ldx) {
-      const double zp = (k + 1 < nz) ? (double)z[o + ldx] : 0.0;
-      const double h = c.ce * (double)z[o + c.oe] + c.cw * (double)z[o + c.ow] +
-                       c.cn * (double)z[o + c.on] + c.cs * (double)z[o + c.os];
-      const double dzk = L.dz[k];
-      const double az = (L.dg[k] + dzk * c.S) * zc - dzk * h + L.sub[k] * zm + L.sup[k] * zp;
-      const double pn = zc + beta * p[o];
-      const double qn = az + beta * q[o];
-      p[o] = pn;
-      q[o] = qn;
-      acc[0] += pn * qn;
-      acc[1] += pn * r[o];
-      zm = zc;
-      zc = zp;
-    }
+  if (g.row && g.act) {
+    const int64_t jst = (int64_t)L.nz * L.ldx;
+    auto run = [&](auto full) {
+      constexpr bool FL = decltype(full)::value;
+      FcgDirPol<TZ, FL> P;
+      P.op.init(z, g, jst, (uint32_t)(L.ldx * sizeof(TZ)), col_coef(L, g), sp, L.nz);
+      P.rp = roww(p, g.j, jst);
+      P.rq = roww(q, g.j, jst);
+      P.rr = rowc(r, g.j, jst);
+      P.oc = (uint32_t)g.ic * 8;
+      P.kb = (uint32_t)L.ldx * 8;
+      P.beta = beta;
+      P.pq = 0.0;
+      P.pr = 0.0;
+      walk<2, FL>(P, g.n);
+      acc[0] = P.pq;
+      acc[1] = P.pr;
+    };
+    if (g.n == KSEG)
+      run(std::true_type{});
+    else
+      run(std::false_type{});
   }
   block_partials<2>(acc, partials);
 }
+
+template <bool FULL>
+struct FcgUpdPol {
+  struct In {
+    double u, r, p, q;
+  };
+  char *ru, *rr;
+  const char *rp, *rq;
+  char* rd;  // FP32 copy of r (mixed precision) or null
+  uint32_t oc, kb, oc4, kb4;
+  int nz, k0;
+  double alpha, rr2;
+
+  __device__ __forceinline__ void load(int s, In& v) {
+    const uint32_t o = oc + layer_off<FULL>(k0 + s, nz, kb);
+    v.u = ldo<double>(ru, o);
+    v.r = ldo<double>(rr, o);
+    v.p = ldo<double>(rp, o);
+    v.q = ldo<double>(rq, o);
+  }
+  __device__ __forceinline__ void step(int s, const In& v) {
+    const int kc = FULL ? k0 + s : min(k0 + s, nz - 1);
+    const uint32_t o = oc + (uint32_t)kc * kb;
+    sto<double>(ru, o, v.u + alpha * v.p);
+    const double rn = v.r - alpha * v.q;
+    sto<double>(rr, o, rn);
+    if (rd) sto<float>(rd, oc4 + (uint32_t)kc * kb4, (float)rn);
+    rr2 += rn * rn;
+  }
+};
 
 __global__ __launch_bounds__(NTHREADS) void k_fcg_update(Lvl<double> L, double* __restrict__ u,
                                                          double* __restrict__ r,
@@ -807,25 +1224,33 @@ __global__ __launch_bounds__(NTHREADS) void k_fcg_update(Lvl<double> L, double* 
                                                          double* __restrict__ partials, int nti,
                                                          int ntj) {
   const double alpha = st->alpha;
-  const int b = xcd_remap(blockIdx.x, gridDim.x);
-  const int ti = b % nti;
-  const int r1 = b / nti;
-  const int tj = r1 % ntj;
-  const int kb = r1 / ntj;
-  const int i = ti * 64 + (threadIdx.x & 63);
-  const int j = tj * SROWS + (threadIdx.x >> 6);
+  const Geo g = stencil_geo<SROWS>(L.nx, L.ny, L.nz, nti, ntj, xcd_remap(blockIdx.x, gridDim.x));
   double acc[1] = {0.0};
-  if (i < L.nx && j < L.ny) {
-    const int64_t base = (int64_t)j * L.nz * L.ldx + i;
-    const int k0 = kb * KSEG, k1 = min(L.nz, k0 + KSEG);
-    for (int k = k0; k < k1; ++k) {
-      const int64_t o = base + (int64_t)k * L.ldx;
-      u[o] += alpha * p[o];
-      const double rn = r[o] - alpha * q[o];
-      r[o] = rn;
-      if (rdown) rdown[o] = (float)rn;
-      acc[0] += rn * rn;
-    }
+  if (g.row && g.act) {
+    const int64_t jst = (int64_t)L.nz * L.ldx;
+    auto run = [&](auto full) {
+      constexpr bool FL = decltype(full)::value;
+      FcgUpdPol<FL> P;
+      P.ru = roww(u, g.j, jst);
+      P.rr = roww(r, g.j, jst);
+      P.rp = rowc(p, g.j, jst);
+      P.rq = rowc(q, g.j, jst);
+      P.rd = rdown ? roww(rdown, g.j, jst) : nullptr;
+      P.oc = (uint32_t)g.ic * 8;
+      P.kb = (uint32_t)L.ldx * 8;
+      P.oc4 = (uint32_t)g.ic * 4;
+      P.kb4 = (uint32_t)L.ldx * 4;
+      P.nz = L.nz;
+      P.k0 = g.k0;
+      P.alpha = alpha;
+      P.rr2 = 0.0;
+      walk<4, FL>(P, g.n);
+      acc[0] = P.rr2;
+    };
+    if (g.n == KSEG)
+      run(std::true_type{});
+    else
+      run(std::false_type{});
   }
   block_partials<1>(acc, partials);
 }
@@ -1192,24 +1617,25 @@ int64_t line_blocks(int nx, int ny) { return (int64_t)cdiv(nx, 32) * cdiv(ny, LR
 template <typename T>
 hipError_t launch_stencil(const Lvl<T>& L, Stencil mode, const T* x, const T* f, T* y,
                           float* ydown, double* partials, int64_t* nblocks, hipStream_t s) {
-  const int nti = cdiv(L.nx, 64), ntj = cdiv(L.ny, SROWS), nkb = cdiv(L.nz, KSEG);
-  const dim3 grid(nti * ntj * nkb), block(NTHREADS);
+  constexpr int SR = SROWS;
+  const int nti = cdiv(L.nx, 64), ntj = cdiv(L.ny, SR), nkb = cdiv(L.nz, KSEG);
+  const dim3 grid(nti * ntj * nkb), block(64 * SR);
   if (nblocks) *nblocks = (int64_t)nti * ntj * nkb;
   switch (mode) {
     case Stencil::SPMV:
-      hipLaunchKernelGGL((k_stencil<T, 0>), grid, block, 0, s, L, x, f, y, ydown, partials,
+      hipLaunchKernelGGL((k_stencil<T, 0, SR>), grid, block, 0, s, L, x, f, y, ydown, partials,
                          nti, ntj);
       break;
     case Stencil::RESIDUAL:
-      hipLaunchKernelGGL((k_stencil<T, 1>), grid, block, 0, s, L, x, f, y, ydown, partials,
+      hipLaunchKernelGGL((k_stencil<T, 1, SR>), grid, block, 0, s, L, x, f, y, ydown, partials,
                          nti, ntj);
       break;
     case Stencil::RESIDUAL_NORM:
-      hipLaunchKernelGGL((k_stencil<T, 2>), grid, block, 0, s, L, x, f, y, ydown, partials,
+      hipLaunchKernelGGL((k_stencil<T, 2, SR>), grid, block, 0, s, L, x, f, y, ydown, partials,
                          nti, ntj);
       break;
     case Stencil::RESIDUAL_NORM_DOWN:
-      hipLaunchKernelGGL((k_stencil<T, 3>), grid, block, 0, s, L, x, f, y, ydown, partials,
+      hipLaunchKernelGGL((k_stencil<T, 3, SR>), grid, block, 0, s, L, x, f, y, ydown, partials,
                          nti, ntj);
       break;
   }
@@ -1300,9 +1726,10 @@ hipError_t launch_prolongate(const Lvl<T>& C, const Lvl<T>& F, const T* uc, T* u
 
 hipError_t launch_cg_p1(const Lvl<double>& L, double* u, double* p, const double* z, double* q,
                         const CgState* st, double* partials, int64_t* nblocks, hipStream_t s) {
-  const int nti = cdiv(L.nx, 64), ntj = cdiv(L.ny, SROWS), nkb = cdiv(L.nz, KSEG);
+  constexpr int SR = SROWS;
+  const int nti = cdiv(L.nx, 64), ntj = cdiv(L.ny, SR), nkb = cdiv(L.nz, KSEG);
   *nblocks = (int64_t)nti * ntj * nkb;
-  hipLaunchKernelGGL(k_cg_p1, dim3(nti * ntj * nkb), dim3(NTHREADS), 0, s, L, u, p, z, q, st,
+  hipLaunchKernelGGL(k_cg_p1<SR>, dim3(nti * ntj * nkb), dim3(64 * SR), 0, s, L, u, p, z, q, st,
                      partials, nti, ntj);
   return hipGetLastError();
 }
