@@ -154,6 +154,11 @@ def main():
                          "value is only the whole-path figure with all four")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run the plain copy used to calibrate traffic counters")
+    ap.add_argument("--tune", choices=("auto", "off", "force"), default="auto",
+                    help="launch shapes: stored table or autotune (auto), defaults (off), "
+                         "always autotune (force); done before the warm-up, untimed")
+    ap.add_argument("--tune-out", default=None,
+                    help="write the launch-shape table of this run (JSON) to this path")
     args = ap.parse_args()
     solves = [x for x in args.solves.split(",") if x]
     if any(x not in SOLVES for x in solves) or not solves:
@@ -187,6 +192,26 @@ def main():
     fd = ctx64.to_device(f)
     ud = ctx64.empty()
     torch.cuda.synchronize()
+
+    # launch shapes (untimed setup)
+    shapes, store = {}, {}
+    for tag, c in (("f64", ctx64), ("mixed", ctx32)):
+        if args.tune == "off":
+            src = "defaults"
+        elif args.tune == "force":
+            G.gmg_autotune(c, reps=3)
+            src = "autotuned"
+        else:
+            _, stored = G.tuned(c, reps=3)
+            src = "stored" if stored else "autotuned"
+        table = G.launch_table(c)
+        store[G.launch_key(c)] = table
+        shapes[tag] = {"source": src, **{k: v for k, v in table.items()
+                                         if k.split("/")[1] == "0"}}
+        log(f"[bench] launch shapes {tag}: {src}")
+    if args.tune_out:
+        with open(args.tune_out, "w") as fh:
+            json.dump(store, fh, indent=1, sort_keys=True)
 
     def step():
         out = {}
@@ -299,6 +324,7 @@ def main():
             "algorithmic_bytes": bytes_dom,
         },
         "kernel_breakdown_ms": breakdown,
+        "launch_shapes": shapes,
         "cpu_baseline": base,
     }
     print(json.dumps(line), flush=True)

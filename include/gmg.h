@@ -202,6 +202,32 @@ int gmg_timing_enable(gmg_ctx *c, int enable);
 int gmg_timing_read(gmg_ctx *c, int kernel, int level, int prec, int64_t *count,
                     double *total_ms);
 
+/* Launch shapes and the autotuner.  Sec. 5.1 fixes one thread-block layout
+ * for every kernel; here each kernel kind (gmg_kernel), level and precision
+ * has its own shape, which only changes how the work is cut into workgroups:
+ *   rows  - grid rows per workgroup of the stencil kernels (SpMV, residual,
+ *           fused residual+restriction, prolongation, CG direction kernel,
+ *           refinement update, flexible-CG kernels): 4, 8 or 16 wavefronts
+ *           of 64 columns.  Line kernels always use 4 wavefronts of 32
+ *           columns; their rows value is stored but not used.
+ *   group - tile columns per dispatch group: tiles are walked group by group
+ *           and tile rows follow each other inside a group, so that a tile's
+ *           neighbours run close in time and share an XCD's L2; 0 walks the
+ *           tiles row by row (the default).
+ * Results are identical for every shape except for the summation order of
+ * the FP64 reductions (norms and dot products).
+ * gmg_set_launch / gmg_get_launch: one entry of the context's table;
+ * GMG_EINVAL for a bad kernel id, level or precision, rows not in {4, 8, 16}
+ * or group outside [0, 4096], and for batched contexts.
+ * gmg_autotune: for every level and for the precisions the context's solvers
+ * use, runs each candidate shape (rows 4/8/16, group 0/1/2/4/8) of each kernel
+ * kind `reps` times on the context's own work buffers (their contents are
+ * overwritten; caller memory is not touched), times it with HIP events on
+ * `stream` and keeps the fastest.  Synchronises `stream`.  reps in [1, 1000]. */
+int gmg_set_launch(gmg_ctx *c, int kernel, int level, int prec, int rows, int group);
+int gmg_get_launch(const gmg_ctx *c, int kernel, int level, int prec, int *rows, int *group);
+int gmg_autotune(gmg_ctx *c, int reps, void *stream);
+
 /* Message describing the calling thread's last non-OK status. */
 const char *gmg_last_error(void);
 

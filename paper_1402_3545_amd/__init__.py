@@ -26,7 +26,8 @@ GMG_F64, GMG_F32 = 0, 1
 EXPORTS = ("gmg_default_params", "gmg_setup", "gmg_destroy", "gmg_field_layout", "spmv",
            "line_solve", "line_smooth", "gmg_residual", "gmg_restrict_smooth", "gmg_prolongate",
            "gmg_vcycle", "gmg_solve", "pcg_solve", "gmg_batch_setup", "gmg_batch_layout",
-           "gmg_batch_solve", "gmg_timing_enable", "gmg_timing_read", "gmg_last_error")
+           "gmg_batch_solve", "gmg_timing_enable", "gmg_timing_read", "gmg_set_launch",
+           "gmg_get_launch", "gmg_autotune", "gmg_last_error")
 
 # kernel ids of the timing facility (gmg_kernel in include/gmg.h)
 KERNELS = ("spmv", "residual", "line_solve", "smooth", "restrict_smooth", "prolongate",
@@ -90,6 +91,9 @@ def _load():
                                   dblp, vp]),
         "gmg_timing_enable": (i32, [vp, i32]),
         "gmg_timing_read": (i32, [vp, i32, i32, i32, i64p, dblp]),
+        "gmg_set_launch": (i32, [vp, i32, i32, i32, i32, i32]),
+        "gmg_get_launch": (i32, [vp, i32, i32, i32, intp, intp]),
+        "gmg_autotune": (i32, [vp, i32, vp]),
         "gmg_last_error": (C.c_char_p, []),
     }
     for name, (res, args) in sig.items():
@@ -406,3 +410,76 @@ def gmg_timing_table(ctx):
 
 def gmg_last_error() -> str:
     return _lib.gmg_last_error().decode()
+
+
+# ---------------------------------------------------------------------------
+# Launch shapes (per kernel kind, level and precision) and the autotuner
+# ---------------------------------------------------------------------------
+# kernel kinds whose launch shape the solvers use
+TUNED_KERNELS = ("spmv", "residual", "line_solve", "smooth", "prolongate", "cg_spmv",
+                 "cg_tridiag", "correct", "fcg", "residual_restrict")
+LAUNCH_TABLE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "launch_shapes.json")
+
+
+def _kid(kernel):
+    return KERNELS.index(kernel) if isinstance(kernel, str) else int(kernel)
+
+
+def gmg_set_launch(ctx, kernel, level, prec, rows, group):
+    _check(_lib.gmg_set_launch(ctx.handle, _kid(kernel), int(level), int(prec), int(rows),
+                               int(group)))
+
+
+def gmg_get_launch(ctx, kernel, level, prec):
+    rows, group = C.c_int(), C.c_int()
+    _check(_lib.gmg_get_launch(ctx.handle, _kid(kernel), int(level), int(prec), C.byref(rows),
+                               C.byref(group)))
+    return rows.value, group.value
+
+
+def gmg_autotune(ctx, reps=3, stream=None):
+    """Time every candidate launch shape of every kernel the solvers use and keep
+    the fastest (overwrites the context's work buffers; synchronises)."""
+    _check(_lib.gmg_autotune(ctx.handle, int(reps), _stream(stream)))
+
+
+def launch_table(ctx):
+    """{"kernel/level/prec": [rows, group]} for every tuned kernel kind."""
+    out = {}
+    for k in TUNED_KERNELS:
+        for lvl in range(ctx.nlevels):
+            for prec in (GMG_F64, GMG_F32):
+                out[f"{k}/{lvl}/{prec}"] = list(gmg_get_launch(ctx, k, lvl, prec))
+    return out
+
+
+def apply_launch_table(ctx, table):
+    for key, (rows, group) in table.items():
+        k, lvl, prec = key.split("/")
+        if int(lvl) < ctx.nlevels:
+            gmg_set_launch(ctx, k, int(lvl), int(prec), rows, group)
+
+
+def launch_key(ctx):
+    """Key of a context's tuned shapes: device, grid, levels and preconditioner
+    precision."""
+    import torch
+    dev = torch.cuda.get_device_properties(torch.cuda.current_device())
+    arch = getattr(dev, "gcnArchName", dev.name).split(":")[0]
+    return f"{arch}|{ctx.nx}x{ctx.ny}x{ctx.nz}|L{ctx.nlevels}|p{ctx.prec_precond}"
+
+
+def tuned(ctx, reps=3, path=LAUNCH_TABLE, stream=None):
+    """Apply the stored launch shapes for this context's key, or run the
+    autotuner and return the new table.  Returns (table, from_store)."""
+    import json
+    key = launch_key(ctx)
+    store = {}
+    if path and os.path.exists(path):
+        with open(path) as fh:
+            store = json.load(fh)
+    if key in store:
+        apply_launch_table(ctx, store[key])
+        return store[key], True
+    gmg_autotune(ctx, reps, stream)
+    return launch_table(ctx), False

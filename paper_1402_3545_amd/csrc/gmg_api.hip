@@ -11,6 +11,8 @@
 #include <algorithm>
 #include <new>
 
+#include <type_traits>
+
 #include "gmg_internal.h"
 
 using gmg::CgState;
@@ -149,7 +151,6 @@ int gmg_destroy(gmg_ctx* c) {
     if (L.u) (void)hipFree(L.u);
     if (L.ualt) (void)hipFree(L.ualt);
     if (L.f) (void)hipFree(L.f);
-    if (L.r) (void)hipFree(L.r);
   }
   dfree(c->dz64); dfree(c->dz32);
   dfree(c->vr); dfree(c->vz); dfree(c->vp); dfree(c->vq); dfree(c->vt);
@@ -283,7 +284,7 @@ int gmg::setup_impl(const gmg_params* p, void* stream, gmg_ctx** out, bool field
   hipStream_t s = as_stream(stream);
   for (int d = 0; d < c->nlevels; ++d) {
     LevelBuf& L = c->lev[d];
-    for (void* q : {L.u, L.ualt, L.f, L.r})
+    for (void* q : {L.u, L.ualt, L.f})
       if (q && (e = hipMemsetAsync(q, 0, (size_t)L.elems * c->esize, s)) != hipSuccess)
         return cleanup(hip_fail(e, "hipMemsetAsync"));
   }
@@ -341,23 +342,25 @@ hipEvent_t pool_event(gmg_ctx* c) {
 
 // Enqueue one kernel launch; while timing is on, bracket it by two events on
 // the launch stream.
+// A launcher that takes a gmg::Shape gets the context's launch shape of
+// (kind, level, prec).
 template <typename F>
 hipError_t timed(gmg_ctx* c, int kind, int level, int prec, hipStream_t s, F&& launch) {
-  if (!c->timing) return launch();
+  auto go = [&]() -> hipError_t {
+    if constexpr (std::is_invocable_v<F, gmg::Shape>)
+      return launch(c->shape[gmg::tslot(kind, level, prec)]);
+    else
+      return launch();
+  };
+  if (!c->timing) return go();
   hipEvent_t a = pool_event(c), b = pool_event(c);
   if (!a || !b) return hipErrorOutOfMemory;
   hipError_t e = hipEventRecord(a, s);
   if (e != hipSuccess) return e;
-  if ((e = launch()) != hipSuccess) return e;
+  if ((e = go()) != hipSuccess) return e;
   if ((e = hipEventRecord(b, s)) != hipSuccess) return e;
   c->pending.push_back({kind, level, prec, a, b});
   return hipSuccess;
-}
-
-constexpr int kMaxLevels = 20;
-
-size_t tslot(int kind, int level, int prec) {
-  return ((size_t)kind * kMaxLevels + level) * 2 + prec;
 }
 
 int drain_timing(gmg_ctx* c) {
@@ -365,7 +368,7 @@ int drain_timing(gmg_ctx* c) {
     HIP_TRY(hipEventSynchronize(t.b));
     float ms = 0.0f;
     HIP_TRY(hipEventElapsedTime(&ms, t.a, t.b));
-    const size_t q = tslot(t.kind, t.level, t.prec);
+    const size_t q = gmg::tslot(t.kind, t.level, t.prec);
     c->tcount[q] += 1;
     c->tms[q] += ms;
   }
@@ -382,7 +385,7 @@ hipError_t smooth_steps(gmg_ctx* c, int d, const T* f, T* cur, T* other, int n, 
   const Lvl<T> L = gmg::view<T>(c, d);
   for (int q = 0; q < n; ++q) {
     hipError_t e = timed(c, GMG_K_SMOOTH, d, prec_of<T>(), s,
-                         [&] { return gmg::launch_smooth<T>(L, f, cur, other, rho, s); });
+                         [&](gmg::Shape sh) { return gmg::launch_smooth<T>(L, f, cur, other, rho, s, sh); });
     if (e != hipSuccess) return e;
     std::swap(cur, other);
   }
@@ -417,7 +420,7 @@ int vcycle_impl(gmg_ctx* c, const T* f0, T* u0, hipStream_t s, bool zero_guess =
     pre_done = 1;
   } else if (zero_guess) {
     HIP_TRY(timed(c, GMG_K_LINE_SOLVE, 0, P, s,
-                  [&] { return gmg::launch_line_solve_scaled<T>(V0, f0, ualt0, rho, s); }));
+                  [&](gmg::Shape sh) { return gmg::launch_line_solve_scaled<T>(V0, f0, ualt0, rho, s, sh); }));
     pre_done = 1;
   }
   if (L == 1) {
@@ -432,15 +435,15 @@ int vcycle_impl(gmg_ctx* c, const T* f0, T* u0, hipStream_t s, bool zero_guess =
   }
   if (!pre_done)
     HIP_TRY(timed(c, GMG_K_SMOOTH, 0, P, s,
-                  [&] { return gmg::launch_smooth<T>(V0, f0, u0, ualt0, rho, s); }));
+                  [&](gmg::Shape sh) { return gmg::launch_smooth<T>(V0, f0, u0, ualt0, rho, s, sh); }));
   cur[0] = ualt0;
   // descend
   for (int d = 0; d < L; ++d) {
     const Lvl<T> V = gmg::view<T>(c, d);
     LevelBuf& B = c->lev[d];
     if (d > 0) {
-      HIP_TRY(timed(c, GMG_K_LINE_SOLVE, d, P, s, [&] {
-        return gmg::launch_line_solve_scaled<T>(V, fl[d], static_cast<T*>(B.u), rho, s);
+      HIP_TRY(timed(c, GMG_K_LINE_SOLVE, d, P, s, [&](gmg::Shape sh) {
+        return gmg::launch_line_solve_scaled<T>(V, fl[d], static_cast<T*>(B.u), rho, s, sh);
       }));
       cur[d] = static_cast<T*>(B.u);
     }
@@ -450,8 +453,8 @@ int vcycle_impl(gmg_ctx* c, const T* f0, T* u0, hipStream_t s, bool zero_guess =
     } else {
       const Lvl<T> C = gmg::view<T>(c, d + 1);
       T* fc = static_cast<T*>(c->lev[d + 1].f);
-      HIP_TRY(timed(c, GMG_K_RESIDUAL_RESTRICT, d, P, s, [&] {
-        return gmg::launch_resrestrict<T>(V, C, cur[d], fl[d], fc, s);
+      HIP_TRY(timed(c, GMG_K_RESIDUAL_RESTRICT, d, P, s, [&](gmg::Shape sh) {
+        return gmg::launch_resrestrict<T>(V, C, cur[d], fl[d], fc, s, sh);
       }));
     }
   }
@@ -460,12 +463,12 @@ int vcycle_impl(gmg_ctx* c, const T* f0, T* u0, hipStream_t s, bool zero_guess =
     const Lvl<T> V = gmg::view<T>(c, d);
     const Lvl<T> C = gmg::view<T>(c, d + 1);
     HIP_TRY(timed(c, GMG_K_PROLONGATE, d + 1, P, s,
-                  [&] { return gmg::launch_prolongate<T>(C, V, cur[d + 1], cur[d], s); }));
+                  [&](gmg::Shape sh) { return gmg::launch_prolongate<T>(C, V, cur[d + 1], cur[d], s, sh); }));
     T* other = (d == 0) ? u0
                         : (cur[d] == c->lev[d].u ? static_cast<T*>(c->lev[d].ualt)
                                                  : static_cast<T*>(c->lev[d].u));
     HIP_TRY(timed(c, GMG_K_SMOOTH, d, P, s,
-                  [&] { return gmg::launch_smooth<T>(V, fl[d], cur[d], other, rho, s); }));
+                  [&](gmg::Shape sh) { return gmg::launch_smooth<T>(V, fl[d], cur[d], other, rho, s, sh); }));
     cur[d] = other;
   }
   return GMG_OK;
@@ -508,10 +511,10 @@ int residual_norm2(gmg_ctx* c, const T* f, const T* u, T* r, float* rdown, doubl
   const Lvl<T> V = gmg::view<T>(c, 0);
   int64_t nb = 0;
   double* dst = c->partials + c->max_partials;
-  HIP_TRY(timed(c, GMG_K_RESIDUAL, 0, prec_of<T>(), s, [&] {
+  HIP_TRY(timed(c, GMG_K_RESIDUAL, 0, prec_of<T>(), s, [&](gmg::Shape sh) {
     return gmg::launch_stencil<T>(
         V, rdown ? Stencil::RESIDUAL_NORM_DOWN : Stencil::RESIDUAL_NORM, u, f, r, rdown,
-        c->partials, &nb, s);
+        c->partials, &nb, s, sh);
   }));
   HIP_TRY(timed(c, GMG_K_REDUCE, 0, GMG_F64, s,
                 [&] { return gmg::launch_reduce(c->partials, nb, 1, dst, s); }));
@@ -584,14 +587,14 @@ int fcg_impl(gmg_ctx* c, const double* f, double* u, double rtol, int maxit, int
                   [&] { return gmg::launch_fcg_zq<TZ>(V, z, c->vq, c->partials, &nb, s); }));
     HIP_TRY(timed(c, GMG_K_REDUCE, 0, GMG_F64, s,
                   [&] { return gmg::launch_fcg_fin(0, c->state, c->partials, nb, nullptr, s); }));
-    HIP_TRY(timed(c, GMG_K_FCG, 0, GMG_F64, s, [&] {
-      return gmg::launch_fcg_dir<TZ>(V, z, c->vp, c->vq, c->vr, c->state, c->partials, &nb, s);
+    HIP_TRY(timed(c, GMG_K_FCG, 0, GMG_F64, s, [&](gmg::Shape sh) {
+      return gmg::launch_fcg_dir<TZ>(V, z, c->vp, c->vq, c->vr, c->state, c->partials, &nb, s, sh);
     }));
     HIP_TRY(timed(c, GMG_K_REDUCE, 0, GMG_F64, s,
                   [&] { return gmg::launch_fcg_fin(1, c->state, c->partials, nb, nullptr, s); }));
-    HIP_TRY(timed(c, GMG_K_FCG, 0, GMG_F64, s, [&] {
+    HIP_TRY(timed(c, GMG_K_FCG, 0, GMG_F64, s, [&](gmg::Shape sh) {
       return gmg::launch_fcg_update(V, u, c->vr, c->vp, c->vq, mixed ? c->er32 : nullptr,
-                                    c->state, c->partials, &nb, s);
+                                    c->state, c->partials, &nb, s, sh);
     }));
     HIP_TRY(timed(c, GMG_K_REDUCE, 0, GMG_F64, s,
                   [&] { return gmg::launch_fcg_fin(2, c->state, c->partials, nb, c->dhist, s); }));
@@ -615,6 +618,166 @@ int fcg_impl(gmg_ctx* c, const double* f, double* u, double rtol, int maxit, int
   return GMG_OK;
 }
 
+// ---- autotuner --------------------------------------------------------------
+// Candidate launch shapes: rows per workgroup (stencil kernels only) and tile
+// columns per dispatch group (0 = row-major).
+constexpr int kTuneRows[] = {4, 8, 16};
+constexpr int kTuneGroups[] = {0, 1, 2, 4, 8};
+
+// Time `reps` launches of every candidate shape of one kernel kind and store
+// the fastest in the context's table.  `nti` is the kernel's tile count across
+// (groups at or above it are row-major again and are skipped).
+template <typename F>
+int tune_kind(gmg_ctx* c, int kind, int level, int prec, bool stencil, int nti, int reps,
+              hipStream_t s, hipEvent_t ea, hipEvent_t eb, F&& launch) {
+  gmg::Shape best{};
+  float best_ms = 0.0f;
+  bool have = false;
+  for (int rows : kTuneRows) {
+    if (!stencil && rows != 4) continue;
+    for (int group : kTuneGroups) {
+      if (group >= nti) continue;
+      const gmg::Shape sh{rows, group};
+      HIP_TRY(launch(sh));  // warm-up
+      HIP_TRY(hipEventRecord(ea, s));
+      for (int q = 0; q < reps; ++q) HIP_TRY(launch(sh));
+      HIP_TRY(hipEventRecord(eb, s));
+      HIP_TRY(hipEventSynchronize(eb));
+      float ms = 0.0f;
+      HIP_TRY(hipEventElapsedTime(&ms, ea, eb));
+      if (!have || ms < best_ms) {
+        best = sh;
+        best_ms = ms;
+        have = true;
+      }
+    }
+  }
+  c->shape[gmg::tslot(kind, level, prec)] = best;
+  return GMG_OK;
+}
+
+// The kernels the solvers launch on level d in precision T, run on the
+// context's own work buffers (level 0: the solver vectors).
+template <typename T>
+int tune_levels(gmg_ctx* c, int reps, hipStream_t s, hipEvent_t ea, hipEvent_t eb) {
+  using gmg::Shape;
+  const int P = prec_of<T>();
+  const int L = c->nlevels;
+  const T rho = (T)c->p.rho;
+  for (int d = 0; d < L; ++d) {
+    const Lvl<T> V = gmg::view<T>(c, d);
+    T *x0, *x1, *x2;
+    if (d > 0) {
+      x0 = static_cast<T*>(c->lev[d].u);
+      x1 = static_cast<T*>(c->lev[d].ualt);
+      x2 = static_cast<T*>(c->lev[d].f);
+    } else if constexpr (sizeof(T) == 8) {
+      x0 = reinterpret_cast<T*>(c->vt);
+      x1 = reinterpret_cast<T*>(c->vz);
+      x2 = reinterpret_cast<T*>(c->vr);
+    } else {
+      x0 = reinterpret_cast<T*>(c->eu32);
+      x1 = static_cast<T*>(c->lev[0].ualt);
+      x2 = reinterpret_cast<T*>(c->er32);
+    }
+    if (!x0 || !x1 || !x2 || (d + 1 < L && (!c->lev[d + 1].u || !c->lev[d + 1].f)))
+      return fail(GMG_EINVAL, "autotune: level %d work buffers are missing", d);
+    const int nts = (int)gmg::stencil_tiles_x(V.nx), ntl = (int)gmg::line_tiles_x(V.nx);
+    int64_t nb = 0;
+    int st;
+    if ((st = tune_kind(c, GMG_K_SPMV, d, P, true, nts, reps, s, ea, eb, [&](Shape sh) {
+           return gmg::launch_stencil<T>(V, Stencil::SPMV, x0, nullptr, x1, nullptr, nullptr,
+                                         nullptr, s, sh);
+         })))
+      return st;
+    if ((st = tune_kind(c, GMG_K_RESIDUAL, d, P, true, nts, reps, s, ea, eb, [&](Shape sh) {
+           return gmg::launch_stencil<T>(V, Stencil::RESIDUAL_NORM, x0, x2, x1, nullptr,
+                                         c->partials, &nb, s, sh);
+         })))
+      return st;
+    if ((st = tune_kind(c, GMG_K_LINE_SOLVE, d, P, false, ntl, reps, s, ea, eb, [&](Shape sh) {
+           return gmg::launch_line_solve_scaled<T>(V, x2, x1, rho, s, sh);
+         })))
+      return st;
+    if ((st = tune_kind(c, GMG_K_SMOOTH, d, P, false, ntl, reps, s, ea, eb, [&](Shape sh) {
+           return gmg::launch_smooth<T>(V, x2, x0, x1, rho, s, sh);
+         })))
+      return st;
+    if (d + 1 < L) {
+      const Lvl<T> C = gmg::view<T>(c, d + 1);
+      T* fc = static_cast<T*>(c->lev[d + 1].f);
+      T* uc = static_cast<T*>(c->lev[d + 1].u);
+      if ((st = tune_kind(c, GMG_K_RESIDUAL_RESTRICT, d, P, true,
+                          (int)gmg::stencil_tiles_x(C.nx), reps, s, ea, eb, [&](Shape sh) {
+                            return gmg::launch_resrestrict<T>(V, C, x0, x2, fc, s, sh);
+                          })))
+        return st;
+      // prolongation from level d+1 onto level d, kept under the coarse level
+      if ((st = tune_kind(c, GMG_K_PROLONGATE, d + 1, P, true, nts, reps, s, ea, eb,
+                          [&](Shape sh) {
+                            return gmg::launch_prolongate<T>(C, V, uc, x1, s, sh);
+                          })))
+        return st;
+    }
+  }
+  return GMG_OK;
+}
+
+// The FP64 finest-level solver kernels: CG, refinement update, flexible CG.
+int tune_solver(gmg_ctx* c, int reps, hipStream_t s, hipEvent_t ea, hipEvent_t eb) {
+  using gmg::Shape;
+  const Lvl<double> V = gmg::view<double>(c, 0);
+  const int nts = (int)gmg::stencil_tiles_x(V.nx), ntl = (int)gmg::line_tiles_x(V.nx);
+  const bool mixed = c->p.prec_precond == GMG_F32;
+  if (!c->vt || !c->vp || !c->vz || !c->vq || !c->vr || !c->partials || !c->state ||
+      (mixed && (!c->er32 || !c->eu32)))
+    return fail(GMG_EINVAL, "autotune: solver work buffers are missing");
+  // a running CG state with alpha = beta = 0: the kernels then leave r and u
+  // unchanged
+  gmg::CgState idle{};
+  idle.maxit = 1 << 30;
+  HIP_TRY(hipMemcpyAsync(c->state, &idle, sizeof(idle), hipMemcpyHostToDevice, s));
+  int64_t nb = 0;
+  int st;
+  if ((st = tune_kind(c, GMG_K_CG_SPMV, 0, GMG_F64, true, nts, reps, s, ea, eb, [&](Shape sh) {
+         return gmg::launch_cg_p1(V, c->vt, c->vp, c->vz, c->vq, c->state, c->partials, &nb, s,
+                                  sh);
+       })))
+    return st;
+  if ((st = tune_kind(c, GMG_K_CG_TRIDIAG, 0, GMG_F64, false, ntl, reps, s, ea, eb,
+                      [&](Shape sh) {
+                        return gmg::launch_cg_p2(V, c->vr, c->vq, c->vz, c->state, 0,
+                                                 c->partials, &nb, s, sh);
+                      })))
+    return st;
+  if (mixed) {
+    if ((st = tune_kind(c, GMG_K_RESIDUAL, 0, GMG_F64, true, nts, reps, s, ea, eb,
+                        [&](Shape sh) {
+                          return gmg::launch_stencil<double>(V, Stencil::RESIDUAL_NORM_DOWN,
+                                                             c->vt, c->vr, c->vz, c->er32,
+                                                             c->partials, &nb, s, sh);
+                        })))
+      return st;
+    if ((st = tune_kind(c, GMG_K_CORRECT, 0, GMG_F64, true, nts, reps, s, ea, eb,
+                        [&](Shape sh) {
+                          return gmg::launch_correct_residual(V, c->vt, c->eu32, c->vr, c->vz,
+                                                              c->er32, c->partials, &nb, s, sh);
+                        })))
+      return st;
+  }
+  if ((st = tune_kind(c, GMG_K_FCG, 0, GMG_F64, true, nts, reps, s, ea, eb, [&](Shape sh) {
+         hipError_t e = mixed ? gmg::launch_fcg_dir<float>(V, c->eu32, c->vp, c->vq, c->vr,
+                                                            c->state, c->partials, &nb, s, sh)
+                              : gmg::launch_fcg_dir<double>(V, c->vz, c->vp, c->vq, c->vr,
+                                                             c->state, c->partials, &nb, s, sh);
+         if (e != hipSuccess) return e;
+         return gmg::launch_fcg_update(V, c->vt, c->vr, c->vp, c->vq, mixed ? c->er32 : nullptr,
+                                       c->state, c->partials, &nb, s, sh);
+       })))
+    return st;
+  return GMG_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -624,8 +787,8 @@ int gmg_timing_enable(gmg_ctx* c, int enable) {
   if (enable) {
     c->pending.clear();
     c->evused = 0;
-    c->tcount.assign((size_t)GMG_K_COUNT * kMaxLevels * 2, 0);
-    c->tms.assign((size_t)GMG_K_COUNT * kMaxLevels * 2, 0.0);
+    c->tcount.assign((size_t)GMG_K_COUNT * gmg::kMaxLevels * 2, 0);
+    c->tms.assign((size_t)GMG_K_COUNT * gmg::kMaxLevels * 2, 0.0);
   }
   c->timing = enable != 0;
   return GMG_OK;
@@ -647,11 +810,57 @@ int gmg_timing_read(gmg_ctx* c, int kernel, int level, int prec, int64_t* count,
   int64_t n = 0;
   double ms = 0.0;
   for (int d = (level < 0 ? 0 : level); d <= (level < 0 ? c->nlevels - 1 : level); ++d) {
-    n += c->tcount[tslot(kernel, d, prec)];
-    ms += c->tms[tslot(kernel, d, prec)];
+    n += c->tcount[gmg::tslot(kernel, d, prec)];
+    ms += c->tms[gmg::tslot(kernel, d, prec)];
   }
   if (count) *count = n;
   if (total_ms) *total_ms = ms;
+  return GMG_OK;
+}
+
+int gmg_set_launch(gmg_ctx* c, int kernel, int level, int prec, int rows, int group) {
+  if (!c || c->batch) return fail(GMG_EINVAL, "context is NULL or batched");
+  if (kernel < 0 || kernel >= GMG_K_COUNT) return fail(GMG_EINVAL, "bad kernel id %d", kernel);
+  if (level < 0 || level >= c->nlevels) return fail(GMG_EINVAL, "bad level %d", level);
+  int st;
+  if ((st = check_prec(prec))) return st;
+  if (rows != 4 && rows != 8 && rows != 16)
+    return fail(GMG_EINVAL, "rows must be 4, 8 or 16 (got %d)", rows);
+  if (group < 0 || group > 4096) return fail(GMG_EINVAL, "group must be in [0, 4096]");
+  c->shape[gmg::tslot(kernel, level, prec)] = gmg::Shape{rows, group};
+  return GMG_OK;
+}
+
+int gmg_get_launch(const gmg_ctx* c, int kernel, int level, int prec, int* rows, int* group) {
+  if (!c || c->batch) return fail(GMG_EINVAL, "context is NULL or batched");
+  if (kernel < 0 || kernel >= GMG_K_COUNT) return fail(GMG_EINVAL, "bad kernel id %d", kernel);
+  if (level < 0 || level >= c->nlevels) return fail(GMG_EINVAL, "bad level %d", level);
+  int st;
+  if ((st = check_prec(prec))) return st;
+  const gmg::Shape sh = c->shape[gmg::tslot(kernel, level, prec)];
+  if (rows) *rows = sh.rows;
+  if (group) *group = sh.group;
+  return GMG_OK;
+}
+
+int gmg_autotune(gmg_ctx* c, int reps, void* stream) {
+  if (!c || c->batch) return fail(GMG_EINVAL, "context is NULL or batched");
+  if (reps < 1 || reps > 1000) return fail(GMG_EINVAL, "reps must be in [1, 1000]");
+  hipStream_t s = as_stream(stream);
+  hipEvent_t ea = nullptr, eb = nullptr;
+  HIP_TRY(hipEventCreate(&ea));
+  if (hipEventCreate(&eb) != hipSuccess) {
+    (void)hipEventDestroy(ea);
+    return fail(GMG_EHIP, "hipEventCreate failed");
+  }
+  int st = c->p.prec_precond == GMG_F32 ? tune_levels<float>(c, reps, s, ea, eb)
+                                         : tune_levels<double>(c, reps, s, ea, eb);
+  if (!st) st = tune_solver(c, reps, s, ea, eb);
+  const hipError_t e = hipStreamSynchronize(s);
+  (void)hipEventDestroy(ea);
+  (void)hipEventDestroy(eb);
+  if (st) return st;
+  if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
   return GMG_OK;
 }
 
@@ -662,16 +871,16 @@ int spmv(gmg_ctx* c, int level, int prec, const void* x, void* y, void* stream) 
   if (x == y) return fail(GMG_EINVAL, "spmv: x and y must not overlap");
   hipStream_t s = as_stream(stream);
   if (prec == GMG_F64)
-    HIP_TRY(timed(c, GMG_K_SPMV, level, prec, s, [&] {
+    HIP_TRY(timed(c, GMG_K_SPMV, level, prec, s, [&](gmg::Shape sh) {
       return gmg::launch_stencil<double>(gmg::view<double>(c, level), Stencil::SPMV,
                                          (const double*)x, nullptr, (double*)y, nullptr, nullptr,
-                                         nullptr, s);
+                                         nullptr, s, sh);
     }));
   else
-    HIP_TRY(timed(c, GMG_K_SPMV, level, prec, s, [&] {
+    HIP_TRY(timed(c, GMG_K_SPMV, level, prec, s, [&](gmg::Shape sh) {
       return gmg::launch_stencil<float>(gmg::view<float>(c, level), Stencil::SPMV,
                                         (const float*)x, nullptr, (float*)y, nullptr, nullptr,
-                                        nullptr, s);
+                                        nullptr, s, sh);
     }));
   return GMG_OK;
 }
@@ -682,14 +891,14 @@ int line_solve(gmg_ctx* c, int level, int prec, const void* r, void* z, void* st
   if ((st = check_prec(prec)) || (st = check_ptrs({r, z}))) return st;
   hipStream_t s = as_stream(stream);
   if (prec == GMG_F64)
-    HIP_TRY(timed(c, GMG_K_LINE_SOLVE, level, prec, s, [&] {
+    HIP_TRY(timed(c, GMG_K_LINE_SOLVE, level, prec, s, [&](gmg::Shape sh) {
       return gmg::launch_line_solve<double>(gmg::view<double>(c, level), (const double*)r,
-                                            (double*)z, s);
+                                            (double*)z, s, sh);
     }));
   else
-    HIP_TRY(timed(c, GMG_K_LINE_SOLVE, level, prec, s, [&] {
+    HIP_TRY(timed(c, GMG_K_LINE_SOLVE, level, prec, s, [&](gmg::Shape sh) {
       return gmg::launch_line_solve<float>(gmg::view<float>(c, level), (const float*)r,
-                                           (float*)z, s);
+                                           (float*)z, s, sh);
     }));
   return GMG_OK;
 }
@@ -718,15 +927,14 @@ int gmg_residual(gmg_ctx* c, int level, int prec, const void* f, const void* u, 
   int64_t nb = 0;
   const Stencil mode = norm2 ? Stencil::RESIDUAL_NORM : Stencil::RESIDUAL;
   if (prec == GMG_F64)
-    HIP_TRY(timed(c, GMG_K_RESIDUAL, level, prec, s, [&] {
+    HIP_TRY(timed(c, GMG_K_RESIDUAL, level, prec, s, [&](gmg::Shape sh) {
       return gmg::launch_stencil<double>(gmg::view<double>(c, level), mode, (const double*)u,
-                                         (const double*)f, (double*)r, nullptr, c->partials, &nb,
-                                         s);
+                                         (const double*)f, (double*)r, nullptr, c->partials, &nb, s, sh);
     }));
   else
-    HIP_TRY(timed(c, GMG_K_RESIDUAL, level, prec, s, [&] {
+    HIP_TRY(timed(c, GMG_K_RESIDUAL, level, prec, s, [&](gmg::Shape sh) {
       return gmg::launch_stencil<float>(gmg::view<float>(c, level), mode, (const float*)u,
-                                        (const float*)f, (float*)r, nullptr, c->partials, &nb, s);
+                                        (const float*)f, (float*)r, nullptr, c->partials, &nb, s, sh);
     }));
   if (norm2) {
     double* dst = c->partials + c->max_partials;
@@ -748,17 +956,16 @@ int gmg_restrict_smooth(gmg_ctx* c, int level, int prec, const void* rf, void* f
   if (fc == uc) return fail(GMG_EINVAL, "fc and uc must differ");
   hipStream_t s = as_stream(stream);
   if (prec == GMG_F64)
-    HIP_TRY(timed(c, GMG_K_RESTRICT_SMOOTH, level, prec, s, [&] {
+    HIP_TRY(timed(c, GMG_K_RESTRICT_SMOOTH, level, prec, s, [&](gmg::Shape sh) {
       return gmg::launch_restrict_smooth<double>(gmg::view<double>(c, level),
                                                  gmg::view<double>(c, level - 1),
-                                                 (const double*)rf, (double*)fc, (double*)uc, rho,
-                                                 s);
+                                                 (const double*)rf, (double*)fc, (double*)uc, rho, s, sh);
     }));
   else
-    HIP_TRY(timed(c, GMG_K_RESTRICT_SMOOTH, level, prec, s, [&] {
+    HIP_TRY(timed(c, GMG_K_RESTRICT_SMOOTH, level, prec, s, [&](gmg::Shape sh) {
       return gmg::launch_restrict_smooth<float>(gmg::view<float>(c, level),
                                                 gmg::view<float>(c, level - 1), (const float*)rf,
-                                                (float*)fc, (float*)uc, (float)rho, s);
+                                                (float*)fc, (float*)uc, (float)rho, s, sh);
     }));
   return GMG_OK;
 }
@@ -770,16 +977,16 @@ int gmg_prolongate(gmg_ctx* c, int level, int prec, const void* uc, void* uf, vo
   if ((st = check_prec(prec)) || (st = check_ptrs({uc, uf}))) return st;
   hipStream_t s = as_stream(stream);
   if (prec == GMG_F64)
-    HIP_TRY(timed(c, GMG_K_PROLONGATE, level, prec, s, [&] {
+    HIP_TRY(timed(c, GMG_K_PROLONGATE, level, prec, s, [&](gmg::Shape sh) {
       return gmg::launch_prolongate<double>(gmg::view<double>(c, level),
                                             gmg::view<double>(c, level - 1), (const double*)uc,
-                                            (double*)uf, s);
+                                            (double*)uf, s, sh);
     }));
   else
-    HIP_TRY(timed(c, GMG_K_PROLONGATE, level, prec, s, [&] {
+    HIP_TRY(timed(c, GMG_K_PROLONGATE, level, prec, s, [&](gmg::Shape sh) {
       return gmg::launch_prolongate<float>(gmg::view<float>(c, level),
                                            gmg::view<float>(c, level - 1), (const float*)uc,
-                                           (float*)uf, s);
+                                           (float*)uf, s, sh);
     }));
   return GMG_OK;
 }
@@ -816,8 +1023,8 @@ int gmg_solve(gmg_ctx* c, const double* f, double* u, double rtol, int maxit, in
     const double rho = c->p.rho;
     for (int it = 0;; ++it) {
       int64_t nb = 0;
-      HIP_TRY(timed(c, GMG_K_SMOOTH, 0, GMG_F64, s, [&] {
-        return gmg::launch_smooth_norm<double>(V0, f, u, ualt0, rho, c->partials, &nb, s);
+      HIP_TRY(timed(c, GMG_K_SMOOTH, 0, GMG_F64, s, [&](gmg::Shape sh) {
+        return gmg::launch_smooth_norm<double>(V0, f, u, ualt0, rho, c->partials, &nb, s, sh);
       }));
       if ((st = reduce_read(c, nb, &rr, s))) return st;
       if (it == 0) {
@@ -851,9 +1058,8 @@ int gmg_solve(gmg_ctx* c, const double* f, double* u, double rtol, int maxit, in
   for (int it = 1; it <= maxit; ++it) {
     if ((st = vcycle_impl<float>(c, c->er32, c->eu32, s, true, false))) return st;
     int64_t nb = 0;
-    HIP_TRY(timed(c, GMG_K_CORRECT, 0, GMG_F64, s, [&] {
-      return gmg::launch_correct_residual(V0, ucur, c->eu32, f, unext, c->er32, c->partials, &nb,
-                                          s);
+    HIP_TRY(timed(c, GMG_K_CORRECT, 0, GMG_F64, s, [&](gmg::Shape sh) {
+      return gmg::launch_correct_residual(V0, ucur, c->eu32, f, unext, c->er32, c->partials, &nb, s, sh);
     }));
     std::swap(ucur, unext);
     if ((st = reduce_read(c, nb, &rr, s))) return st;
@@ -903,12 +1109,12 @@ int pcg_solve(gmg_ctx* c, const double* f, double* u, double rtol, int maxit, in
   init.thresh2 = rtol * rtol;  // scaled by ||r_0||^2 on the device
   HIP_TRY(hipMemcpyAsync(c->state, &init, sizeof(CgState), hipMemcpyHostToDevice, s));
   int64_t nb = 0;
-  HIP_TRY(timed(c, GMG_K_RESIDUAL, 0, GMG_F64, s, [&] {
+  HIP_TRY(timed(c, GMG_K_RESIDUAL, 0, GMG_F64, s, [&](gmg::Shape sh) {
     return gmg::launch_stencil<double>(V, Stencil::RESIDUAL, u, f, c->vr, nullptr, nullptr,
-                                       nullptr, s);
+                                       nullptr, s, sh);
   }));
-  HIP_TRY(timed(c, GMG_K_CG_TRIDIAG, 0, GMG_F64, s, [&] {
-    return gmg::launch_cg_p2(V, c->vr, c->vr, c->vz, c->state, 1, c->partials, &nb, s);
+  HIP_TRY(timed(c, GMG_K_CG_TRIDIAG, 0, GMG_F64, s, [&](gmg::Shape sh) {
+    return gmg::launch_cg_p2(V, c->vr, c->vr, c->vz, c->state, 1, c->partials, &nb, s, sh);
   }));
   HIP_TRY(timed(c, GMG_K_REDUCE, 0, GMG_F64, s,
                 [&] { return gmg::launch_cg_fin2(c->state, c->partials, nb, 1, c->dhist, s); }));
@@ -928,13 +1134,13 @@ int pcg_solve(gmg_ctx* c, const double* f, double* u, double rtol, int maxit, in
     const int nq = std::min(chunk, maxit - done_iters);
     for (int q = 0; q < nq; ++q) {
       int64_t nb1 = 0, nb2 = 0;
-      HIP_TRY(timed(c, GMG_K_CG_SPMV, 0, GMG_F64, s, [&] {
-        return gmg::launch_cg_p1(V, u, c->vp, c->vz, c->vq, c->state, c->partials, &nb1, s);
+      HIP_TRY(timed(c, GMG_K_CG_SPMV, 0, GMG_F64, s, [&](gmg::Shape sh) {
+        return gmg::launch_cg_p1(V, u, c->vp, c->vz, c->vq, c->state, c->partials, &nb1, s, sh);
       }));
       HIP_TRY(timed(c, GMG_K_REDUCE, 0, GMG_F64, s,
                     [&] { return gmg::launch_cg_fin1(c->state, c->partials, nb1, s); }));
-      HIP_TRY(timed(c, GMG_K_CG_TRIDIAG, 0, GMG_F64, s, [&] {
-        return gmg::launch_cg_p2(V, c->vr, c->vq, c->vz, c->state, 0, c->partials, &nb2, s);
+      HIP_TRY(timed(c, GMG_K_CG_TRIDIAG, 0, GMG_F64, s, [&](gmg::Shape sh) {
+        return gmg::launch_cg_p2(V, c->vr, c->vq, c->vz, c->state, 0, c->partials, &nb2, s, sh);
       }));
       HIP_TRY(timed(c, GMG_K_REDUCE, 0, GMG_F64, s, [&] {
         return gmg::launch_cg_fin2(c->state, c->partials, nb2, 0, c->dhist, s);

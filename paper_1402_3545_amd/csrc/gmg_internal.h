@@ -83,10 +83,27 @@ struct LevelBuf {
   float *cx32 = nullptr, *cy32 = nullptr, *sub32 = nullptr, *sup32 = nullptr,
         *dg32 = nullptr;
   // V-cycle work fields in the context's precond precision (bytes per
-  // element = esize): u, ualt (ping-pong partner), f, r.  Level 0 uses the
-  // caller's f and u, so only ualt and r are allocated there.
-  void *u = nullptr, *ualt = nullptr, *f = nullptr, *r = nullptr;
+  // element = esize): u, ualt (ping-pong partner), f.  Level 0 uses the
+  // caller's f and u, so only ualt is allocated there.  (The residual is
+  // never stored: it is fused with the restriction.)
+  void *u = nullptr, *ualt = nullptr, *f = nullptr;
 };
+
+// Launch shape of a kernel: rows = grid rows per workgroup of the stencil
+// kernels (4, 8 or 16 wavefronts of 64 columns; the line kernels always use 4
+// wavefronts of 32 columns), group = tile columns per dispatch group (tiles
+// are walked group by group, tile rows inside a group; 0 = row-major order).
+struct Shape {
+  int rows = 4;
+  int group = 0;
+};
+
+constexpr int kMaxLevels = 20;
+
+// Slot of (kernel kind, level, precision) in the per-context tables.
+inline size_t tslot(int kind, int level, int prec) {
+  return ((size_t)kind * kMaxLevels + level) * 2 + prec;
+}
 
 }  // namespace gmg
 
@@ -101,6 +118,10 @@ struct Batch;
 
 struct gmg_ctx {
   gmg_params p;
+  // launch shape per [kind][level][prec] (gmg::tslot), set by gmg_set_launch
+  // or gmg_autotune; every context starts with the default shapes
+  std::vector<gmg::Shape> shape =
+      std::vector<gmg::Shape>((size_t)GMG_K_COUNT * gmg::kMaxLevels * 2);
   gmg::Batch* batch = nullptr;       // non-null: a batched context (gmg_batch_setup)
   // per-kernel timing
   bool timing = false;
@@ -140,49 +161,50 @@ void batch_free(Batch* b);
 // ---- launchers (kernels.hip); every launcher returns the hipError_t of the launch
 enum class Stencil { SPMV = 0, RESIDUAL = 1, RESIDUAL_NORM = 2, RESIDUAL_NORM_DOWN = 3 };
 
-template <typename T>
-hipError_t launch_stencil(const Lvl<T>& L, Stencil mode, const T* x, const T* f, T* y,
-                          float* ydown, double* partials, int64_t* nblocks, hipStream_t s);
 
 template <typename T>
-hipError_t launch_line_solve(const Lvl<T>& L, const T* r, T* z, hipStream_t s);
+hipError_t launch_stencil(const Lvl<T>& L, Stencil mode, const T* x, const T* f, T* y,
+                          float* ydown, double* partials, int64_t* nblocks, hipStream_t s, Shape sh = {});
+
+template <typename T>
+hipError_t launch_line_solve(const Lvl<T>& L, const T* r, T* z, hipStream_t s, Shape sh = {});
 
 template <typename T>
 hipError_t launch_smooth(const Lvl<T>& L, const T* f, const T* uin, T* uout, T rho,
-                         hipStream_t s);
+                         hipStream_t s, Shape sh = {});
 
 template <typename T>
 hipError_t launch_restrict_smooth(const Lvl<T>& C, const Lvl<T>& F, const T* rf, T* fc, T* uc,
-                                  T rho, hipStream_t s);
+                                  T rho, hipStream_t s, Shape sh = {});
 
 // z = scale * M^-1 r (first smoothing step from a zero guess when scale = rho)
 template <typename T>
-hipError_t launch_line_solve_scaled(const Lvl<T>& L, const T* r, T* z, T scale, hipStream_t s);
+hipError_t launch_line_solve_scaled(const Lvl<T>& L, const T* r, T* z, T scale, hipStream_t s, Shape sh = {});
 
 // Smooth that also returns ||f - A u_in||^2 per workgroup (line_blocks partials)
 template <typename T>
 hipError_t launch_smooth_norm(const Lvl<T>& L, const T* f, const T* uin, T* uout, T rho,
-                              double* partials, int64_t* nblocks, hipStream_t s);
+                              double* partials, int64_t* nblocks, hipStream_t s, Shape sh = {});
 
 // fc = R (f - A u): residual of level F restricted to level C, r never stored
 template <typename T>
 hipError_t launch_resrestrict(const Lvl<T>& F, const Lvl<T>& C, const T* u, const T* f, T* fc,
-                              hipStream_t s);
+                              hipStream_t s, Shape sh = {});
 
 // uout = u + e, r32 = f - A uout, partial ||r||^2
 hipError_t launch_correct_residual(const Lvl<double>& L, const double* u, const float* e,
                                    const double* f, double* uout, float* r32, double* partials,
-                                   int64_t* nblocks, hipStream_t s);
+                                   int64_t* nblocks, hipStream_t s, Shape sh = {});
 
 template <typename T>
 hipError_t launch_prolongate(const Lvl<T>& C, const Lvl<T>& F, const T* uc, T* uf,
-                             hipStream_t s);
+                             hipStream_t s, Shape sh = {});
 
 hipError_t launch_cg_p1(const Lvl<double>& L, double* u, double* p, const double* z, double* q,
-                        const CgState* st, double* partials, int64_t* nblocks, hipStream_t s);
+                        const CgState* st, double* partials, int64_t* nblocks, hipStream_t s, Shape sh = {});
 hipError_t launch_cg_p2(const Lvl<double>& L, double* r, const double* q, double* z,
                         const CgState* st, int init, double* partials, int64_t* nblocks,
-                        hipStream_t s);
+                        hipStream_t s, Shape sh = {});
 // finalize kernels: reduce partials in a fixed order and update the CG state
 hipError_t launch_cg_fin1(CgState* st, const double* partials, int64_t nblocks, hipStream_t s);
 hipError_t launch_cg_fin2(CgState* st, const double* partials, int64_t nblocks, int init,
@@ -198,10 +220,10 @@ hipError_t launch_fcg_zq(const Lvl<double>& L, const TZ* z, const double* q, dou
 template <typename TZ>
 hipError_t launch_fcg_dir(const Lvl<double>& L, const TZ* z, double* p, double* q,
                           const double* r, const CgState* st, double* partials, int64_t* nblocks,
-                          hipStream_t s);
+                          hipStream_t s, Shape sh = {});
 hipError_t launch_fcg_update(const Lvl<double>& L, double* u, double* r, const double* p,
                              const double* q, float* rdown, const CgState* st, double* partials,
-                             int64_t* nblocks, hipStream_t s);
+                             int64_t* nblocks, hipStream_t s, Shape sh = {});
 // which: 0 beta, 1 alpha, 2 residual / convergence
 hipError_t launch_fcg_fin(int which, CgState* st, const double* partials, int64_t nblocks,
                           double* hist, hipStream_t s);

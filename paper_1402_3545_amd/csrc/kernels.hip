@@ -115,13 +115,37 @@ struct Geo {
   int k0, n;       // first layer and number of layers of the segment (uniform)
 };
 
+// Tile coordinates of logical workgroup b (all wave-uniform).  Tiles are
+// walked in groups of `group` tile columns: inside a group the tiles of one
+// tile row are adjacent and tile rows follow each other, so a tile's
+// east/west and north/south neighbours run within a few workgroups of it and
+// its halo rows are still in the XCD's L2.  group <= 0 or >= nti: row-major.
+// Segments of layers (kb) vary slowest.
+__device__ __forceinline__ void tile_coords(int b, int nti, int ntj, int group, int& ti, int& tj,
+                                            int& kb) {
+  const int per = nti * ntj;
+  kb = b / per;
+  int r = b - kb * per;
+  if (group <= 0 || group >= nti) {
+    tj = r / nti;
+    ti = r - tj * nti;
+    return;
+  }
+  const int gsize = group * ntj;
+  const int gi = r / gsize;
+  const int g0 = gi * group;
+  const int w = min(group, nti - g0);
+  r -= gi * gsize;
+  tj = r / w;
+  ti = g0 + (r - tj * w);
+}
+
 template <int SR>
-__device__ __forceinline__ Geo stencil_geo(int nx, int ny, int nz, int nti, int ntj, int b) {
+__device__ __forceinline__ Geo stencil_geo(int nx, int ny, int nz, int nti, int ntj, int group,
+                                           int b) {
   Geo g;
-  const int ti = b % nti;
-  const int r1 = b / nti;
-  const int tj = r1 % ntj;
-  const int kb = r1 / ntj;
+  int ti, tj, kb;
+  tile_coords(b, nti, ntj, group, ti, tj, kb);
   const int i = ti * 64 + (int)(threadIdx.x & 63);
   const int j = tj * SR + __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   g.row = j < ny;
@@ -314,9 +338,10 @@ __global__ __launch_bounds__(64 * SR) void k_stencil(Lvl<T> L, const T* __restri
                                                      const T* __restrict__ f, T* __restrict__ y,
                                                      float* __restrict__ ydown,
                                                      double* __restrict__ partials, int nti,
-                                                     int ntj) {
+                                                     int ntj, int group) {
   constexpr int CH = sizeof(T) == 8 ? 4 : 8;
-  const Geo g = stencil_geo<SR>(L.nx, L.ny, L.nz, nti, ntj, xcd_remap(blockIdx.x, gridDim.x));
+  const Geo g =
+      stencil_geo<SR>(L.nx, L.ny, L.nz, nti, ntj, group, xcd_remap(blockIdx.x, gridDim.x));
   __shared__ Prof<T> sp[KSEG];
   stage_prof(L, g.k0, sp);
   double nrm[1] = {0.0};
@@ -436,7 +461,7 @@ struct StepIn<T, LINE_CG> { T r, q; };
 // checkpoint and substitutes backwards.
 template <typename T, int HALF, int MODE>
 __device__ __forceinline__ void line_body(const Lvl<T>& L, const LineArgs<T>& a, int nti,
-                                          int b) {
+                                          int ntj, int group, int b) {
   constexpr int NR = 2 * HALF;
   constexpr bool kSmooth = (MODE == LINE_SMOOTH || MODE == LINE_SMOOTH_NORM);
   constexpr int G = HALF < 8 ? HALF : 8;                       // back-sweep segment
@@ -459,8 +484,8 @@ __device__ __forceinline__ void line_body(const Lvl<T>& L, const LineArgs<T>& a,
     s_dz[k] = real ? L.dz[k] : T(0);
   }
   __syncthreads();
-  const int ti = b % nti;
-  const int tj = b / nti;
+  int ti, tj, kb_unused;
+  tile_coords(b, nti, ntj, group, ti, tj, kb_unused);
   const int lane = threadIdx.x & 63;
   const int half = lane >> 5;
   const int i = ti * 32 + (lane & 31);
@@ -667,11 +692,12 @@ __device__ __forceinline__ void line_body(const Lvl<T>& L, const LineArgs<T>& a,
 }
 
 template <typename T, int HALF, int MODE>
-__global__ __launch_bounds__(NTHREADS) void k_line(Lvl<T> L, LineArgs<T> a, int nti, int ntj) {
+__global__ __launch_bounds__(NTHREADS) void k_line(Lvl<T> L, LineArgs<T> a, int nti, int ntj,
+                                                   int group) {
   if constexpr (MODE == LINE_CG) {
     if (a.st->done) return;  // uniform: the solve has already stopped
   }
-  line_body<T, HALF, MODE>(L, a, nti, xcd_remap(blockIdx.x, gridDim.x));
+  line_body<T, HALF, MODE>(L, a, nti, ntj, group, xcd_remap(blockIdx.x, gridDim.x));
 }
 
 // ---------------------------------------------------------------------------
@@ -743,13 +769,13 @@ struct ResRestrictPol {
 // residual is only needed restricted): f_c(I,J) = sum over the 2x2 children of
 // (f - A u).  One lane per coarse column; its four children are read as two
 // 2-vectors per layer.  The fine residual itself is never stored.
-template <typename T>
+template <typename T, int SR>
 __device__ __forceinline__ void resrestrict_body(const Lvl<T>& F, const Lvl<T>& C,
                                                  const T* __restrict__ u,
                                                  const T* __restrict__ f, T* __restrict__ fc,
-                                                 int nti, int ntj, int b) {
+                                                 int nti, int ntj, int group, int b) {
   constexpr int CH = sizeof(T) == 8 ? 1 : 2;
-  const Geo g = stencil_geo<SROWS>(C.nx, C.ny, C.nz, nti, ntj, b);
+  const Geo g = stencil_geo<SR>(C.nx, C.ny, C.nz, nti, ntj, group, b);
   __shared__ Prof<T> sp[KSEG];
   stage_prof(F, g.k0, sp);
   if (!(g.row && g.act)) return;
@@ -815,12 +841,13 @@ __device__ __forceinline__ void resrestrict_body(const Lvl<T>& F, const Lvl<T>& 
     run(std::false_type{});
 }
 
-template <typename T>
-__global__ __launch_bounds__(NTHREADS) void k_resrestrict(Lvl<T> F, Lvl<T> C,
-                                                          const T* __restrict__ u,
-                                                          const T* __restrict__ f,
-                                                          T* __restrict__ fc, int nti, int ntj) {
-  resrestrict_body<T>(F, C, u, f, fc, nti, ntj, xcd_remap(blockIdx.x, gridDim.x));
+template <typename T, int SR>
+__global__ __launch_bounds__(64 * SR) void k_resrestrict(Lvl<T> F, Lvl<T> C,
+                                                         const T* __restrict__ u,
+                                                         const T* __restrict__ f,
+                                                         T* __restrict__ fc, int nti, int ntj,
+                                                         int group) {
+  resrestrict_body<T, SR>(F, C, u, f, fc, nti, ntj, group, xcd_remap(blockIdx.x, gridDim.x));
 }
 
 // ---------------------------------------------------------------------------
@@ -876,11 +903,12 @@ struct CorrectPol {
   }
 };
 
+template <int SR>
 __device__ __forceinline__ void correct_residual_body(
     const Lvl<double>& L, const double* __restrict__ u, const float* __restrict__ e,
     const double* __restrict__ f, double* __restrict__ uout, float* __restrict__ r32,
-    double* __restrict__ partials, int nti, int ntj, int b) {
-  const Geo g = stencil_geo<SROWS>(L.nx, L.ny, L.nz, nti, ntj, b);
+    double* __restrict__ partials, int nti, int ntj, int group, int b) {
+  const Geo g = stencil_geo<SR>(L.nx, L.ny, L.nz, nti, ntj, group, b);
   __shared__ Prof<double> sp[KSEG];
   stage_prof(L, g.k0, sp);
   double nrm[1] = {0.0};
@@ -924,15 +952,16 @@ __device__ __forceinline__ void correct_residual_body(
     else
       run(std::false_type{});
   }
-  block_partials<1>(nrm, partials);
+  block_partials<1, SR>(nrm, partials);
 }
 
-__global__ __launch_bounds__(NTHREADS) void k_correct_residual(
+template <int SR>
+__global__ __launch_bounds__(64 * SR) void k_correct_residual(
     Lvl<double> L, const double* __restrict__ u, const float* __restrict__ e,
     const double* __restrict__ f, double* __restrict__ uout, float* __restrict__ r32,
-    double* __restrict__ partials, int nti, int ntj) {
-  correct_residual_body(L, u, e, f, uout, r32, partials, nti, ntj,
-                        xcd_remap(blockIdx.x, gridDim.x));
+    double* __restrict__ partials, int nti, int ntj, int group) {
+  correct_residual_body<SR>(L, u, e, f, uout, r32, partials, nti, ntj, group,
+                            xcd_remap(blockIdx.x, gridDim.x));
 }
 
 // ---------------------------------------------------------------------------
@@ -966,11 +995,11 @@ struct ProlongPol {
 // One lane per fine column (i, j); its coarse parent (I, J) = (i/2, j/2) and
 // the coarse neighbours on the child's side, I2 = I -+ 1, J2 = J -+ 1
 // (periodic), weighted 9/3/3/1 over 16.
-template <typename T>
+template <typename T, int SR>
 __device__ __forceinline__ void prolongate_body(const Lvl<T>& C, const Lvl<T>& F,
                                                 const T* __restrict__ uc, T* __restrict__ uf,
-                                                int nti, int ntj, int b) {
-  const Geo g = stencil_geo<SROWS>(F.nx, F.ny, F.nz, nti, ntj, b);
+                                                int nti, int ntj, int group, int b) {
+  const Geo g = stencil_geo<SR>(F.nx, F.ny, F.nz, nti, ntj, group, b);
   if (!(g.row && g.act)) return;
   const int I = g.ic >> 1, J = g.j >> 1;
   int I2 = I + ((g.ic & 1) ? 1 : -1);
@@ -1000,11 +1029,12 @@ __device__ __forceinline__ void prolongate_body(const Lvl<T>& C, const Lvl<T>& F
     run(std::false_type{});
 }
 
-template <typename T>
-__global__ __launch_bounds__(NTHREADS) void k_prolongate(Lvl<T> C, Lvl<T> F,
-                                                         const T* __restrict__ uc,
-                                                         T* __restrict__ uf, int nti, int ntj) {
-  prolongate_body<T>(C, F, uc, uf, nti, ntj, xcd_remap(blockIdx.x, gridDim.x));
+template <typename T, int SR>
+__global__ __launch_bounds__(64 * SR) void k_prolongate(Lvl<T> C, Lvl<T> F,
+                                                        const T* __restrict__ uc,
+                                                        T* __restrict__ uf, int nti, int ntj,
+                                                        int group) {
+  prolongate_body<T, SR>(C, F, uc, uf, nti, ntj, group, xcd_remap(blockIdx.x, gridDim.x));
 }
 
 // ---------------------------------------------------------------------------
@@ -1049,11 +1079,12 @@ __global__ __launch_bounds__(64 * SR) void k_cg_p1(Lvl<double> L, double* __rest
                                                    double* __restrict__ q,
                                                    const CgState* __restrict__ st,
                                                    double* __restrict__ partials, int nti,
-                                                   int ntj) {
+                                                   int ntj, int group) {
   if (st->done) return;  // uniform: the solve has already stopped
   constexpr int CH = 2;
   const double alpha = st->alpha, beta = st->beta;
-  const Geo g = stencil_geo<SR>(L.nx, L.ny, L.nz, nti, ntj, xcd_remap(blockIdx.x, gridDim.x));
+  const Geo g =
+      stencil_geo<SR>(L.nx, L.ny, L.nz, nti, ntj, group, xcd_remap(blockIdx.x, gridDim.x));
   __shared__ Prof<double> sp[KSEG];
   stage_prof(L, g.k0, sp);
   double pq[1] = {0.0};
@@ -1146,16 +1177,17 @@ struct FcgDirPol {
   }
 };
 
-template <typename TZ>
-__global__ __launch_bounds__(NTHREADS) void k_fcg_dir(Lvl<double> L, const TZ* __restrict__ z,
-                                                      double* __restrict__ p,
-                                                      double* __restrict__ q,
-                                                      const double* __restrict__ r,
-                                                      const CgState* __restrict__ st,
-                                                      double* __restrict__ partials, int nti,
-                                                      int ntj) {
+template <typename TZ, int SR>
+__global__ __launch_bounds__(64 * SR) void k_fcg_dir(Lvl<double> L, const TZ* __restrict__ z,
+                                                     double* __restrict__ p,
+                                                     double* __restrict__ q,
+                                                     const double* __restrict__ r,
+                                                     const CgState* __restrict__ st,
+                                                     double* __restrict__ partials, int nti,
+                                                     int ntj, int group) {
   const double beta = st->beta;
-  const Geo g = stencil_geo<SROWS>(L.nx, L.ny, L.nz, nti, ntj, xcd_remap(blockIdx.x, gridDim.x));
+  const Geo g =
+      stencil_geo<SR>(L.nx, L.ny, L.nz, nti, ntj, group, xcd_remap(blockIdx.x, gridDim.x));
   __shared__ Prof<double> sp[KSEG];
   stage_prof(L, g.k0, sp);
   double acc[2] = {0.0, 0.0};
@@ -1182,7 +1214,7 @@ __global__ __launch_bounds__(NTHREADS) void k_fcg_dir(Lvl<double> L, const TZ* _
     else
       run(std::false_type{});
   }
-  block_partials<2>(acc, partials);
+  block_partials<2, SR>(acc, partials);
 }
 
 template <bool FULL>
@@ -1215,16 +1247,18 @@ struct FcgUpdPol {
   }
 };
 
-__global__ __launch_bounds__(NTHREADS) void k_fcg_update(Lvl<double> L, double* __restrict__ u,
-                                                         double* __restrict__ r,
-                                                         const double* __restrict__ p,
-                                                         const double* __restrict__ q,
-                                                         float* __restrict__ rdown,
-                                                         const CgState* __restrict__ st,
-                                                         double* __restrict__ partials, int nti,
-                                                         int ntj) {
+template <int SR>
+__global__ __launch_bounds__(64 * SR) void k_fcg_update(Lvl<double> L, double* __restrict__ u,
+                                                        double* __restrict__ r,
+                                                        const double* __restrict__ p,
+                                                        const double* __restrict__ q,
+                                                        float* __restrict__ rdown,
+                                                        const CgState* __restrict__ st,
+                                                        double* __restrict__ partials, int nti,
+                                                        int ntj, int group) {
   const double alpha = st->alpha;
-  const Geo g = stencil_geo<SROWS>(L.nx, L.ny, L.nz, nti, ntj, xcd_remap(blockIdx.x, gridDim.x));
+  const Geo g =
+      stencil_geo<SR>(L.nx, L.ny, L.nz, nti, ntj, group, xcd_remap(blockIdx.x, gridDim.x));
   double acc[1] = {0.0};
   if (g.row && g.act) {
     const int64_t jst = (int64_t)L.nz * L.ldx;
@@ -1252,7 +1286,7 @@ __global__ __launch_bounds__(NTHREADS) void k_fcg_update(Lvl<double> L, double* 
     else
       run(std::false_type{});
   }
-  block_partials<1>(acc, partials);
+  block_partials<1, SR>(acc, partials);
 }
 
 // ---------------------------------------------------------------------------
@@ -1285,7 +1319,7 @@ __global__ __launch_bounds__(NTHREADS) void k_line_grouped(const GItem<float>* _
   a.b = it.b;
   a.o0 = it.o;
   a.rho = rho;
-  line_body<float, HALF, MODE>(it.L, a, it.nti, B - it.blk0);
+  line_body<float, HALF, MODE>(it.L, a, it.nti, it.ntj, 0, B - it.blk0);
 }
 
 __global__ __launch_bounds__(NTHREADS) void k_resrestrict_grouped(
@@ -1293,7 +1327,7 @@ __global__ __launch_bounds__(NTHREADS) void k_resrestrict_grouped(
   const int B = xcd_remap(blockIdx.x, gridDim.x);
   const GItem<float> it = items[find_item(items, nitems, B)];
   if (!active[it.pair]) return;
-  resrestrict_body<float>(it.L, it.X, it.a, it.b, it.o, it.nti, it.ntj, B - it.blk0);
+  resrestrict_body<float, SROWS>(it.L, it.X, it.a, it.b, it.o, it.nti, it.ntj, 0, B - it.blk0);
 }
 
 __global__ __launch_bounds__(NTHREADS) void k_prolongate_grouped(
@@ -1301,7 +1335,7 @@ __global__ __launch_bounds__(NTHREADS) void k_prolongate_grouped(
   const int B = xcd_remap(blockIdx.x, gridDim.x);
   const GItem<float> it = items[find_item(items, nitems, B)];
   if (!active[it.pair]) return;
-  prolongate_body<float>(it.X, it.L, it.a, it.o, it.nti, it.ntj, B - it.blk0);
+  prolongate_body<float, SROWS>(it.X, it.L, it.a, it.o, it.nti, it.ntj, 0, B - it.blk0);
 }
 
 __global__ __launch_bounds__(NTHREADS) void k_correct_residual_grouped(
@@ -1311,8 +1345,8 @@ __global__ __launch_bounds__(NTHREADS) void k_correct_residual_grouped(
   const GItemCR it = items[find_item(items, nitems, B)];
   if (!active[it.pair]) return;
   // partial of workgroup B of the item goes to slot B (the pair's segment)
-  correct_residual_body(it.L, it.u, it.e, it.f, it.uout, it.r32, partials - blockIdx.x + B,
-                        it.nti, it.ntj, B - it.blk0);
+  correct_residual_body<SROWS>(it.L, it.u, it.e, it.f, it.uout, it.r32,
+                               partials - blockIdx.x + B, it.nti, it.ntj, 0, B - it.blk0);
 }
 
 // ---------------------------------------------------------------------------
@@ -1532,20 +1566,25 @@ inline int grid_stride_blocks(int64_t n) {
 }
 
 template <typename T, int MODE>
-hipError_t line_dispatch(const Lvl<T>& L, const LineArgs<T>& a, hipStream_t s) {
+hipError_t line_dispatch(const Lvl<T>& L, const LineArgs<T>& a, hipStream_t s, int group) {
   const int nti = cdiv(L.nx, 32), ntj = cdiv(L.ny, LROWS);
   const dim3 grid(nti * ntj), block(NTHREADS);
   const int half = (L.nz + 1) / 2;
   if (half <= 4)
-    hipLaunchKernelGGL((k_line<T, 4, MODE>), grid, block, 0, s, L, a, nti, ntj);
+    hipLaunchKernelGGL((k_line<T, 4, MODE>), grid, block, 0, s, L, a, nti, ntj,
+                       group);
   else if (half <= 8)
-    hipLaunchKernelGGL((k_line<T, 8, MODE>), grid, block, 0, s, L, a, nti, ntj);
+    hipLaunchKernelGGL((k_line<T, 8, MODE>), grid, block, 0, s, L, a, nti, ntj,
+                       group);
   else if (half <= 16)
-    hipLaunchKernelGGL((k_line<T, 16, MODE>), grid, block, 0, s, L, a, nti, ntj);
+    hipLaunchKernelGGL((k_line<T, 16, MODE>), grid, block, 0, s, L, a, nti, ntj,
+                       group);
   else if (half <= 32)
-    hipLaunchKernelGGL((k_line<T, 32, MODE>), grid, block, 0, s, L, a, nti, ntj);
+    hipLaunchKernelGGL((k_line<T, 32, MODE>), grid, block, 0, s, L, a, nti, ntj,
+                       group);
   else if (half <= 64)
-    hipLaunchKernelGGL((k_line<T, 64, MODE>), grid, block, 0, s, L, a, nti, ntj);
+    hipLaunchKernelGGL((k_line<T, 64, MODE>), grid, block, 0, s, L, a, nti, ntj,
+                       group);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();
@@ -1614,78 +1653,98 @@ int64_t stencil_blocks(int nx, int ny, int nz) {
 
 int64_t line_blocks(int nx, int ny) { return (int64_t)cdiv(nx, 32) * cdiv(ny, LROWS); }
 
-template <typename T>
-hipError_t launch_stencil(const Lvl<T>& L, Stencil mode, const T* x, const T* f, T* y,
-                          float* ydown, double* partials, int64_t* nblocks, hipStream_t s) {
-  constexpr int SR = SROWS;
-  const int nti = cdiv(L.nx, 64), ntj = cdiv(L.ny, SR), nkb = cdiv(L.nz, KSEG);
-  const dim3 grid(nti * ntj * nkb), block(64 * SR);
-  if (nblocks) *nblocks = (int64_t)nti * ntj * nkb;
-  switch (mode) {
-    case Stencil::SPMV:
-      hipLaunchKernelGGL((k_stencil<T, 0, SR>), grid, block, 0, s, L, x, f, y, ydown, partials,
-                         nti, ntj);
+// Instantiate f with the compile-time rows of a stencil launch shape.
+template <typename F>
+hipError_t with_rows(int rows, F&& f) {
+  switch (rows) {
+    case 8:
+      f(std::integral_constant<int, 8>{});
       break;
-    case Stencil::RESIDUAL:
-      hipLaunchKernelGGL((k_stencil<T, 1, SR>), grid, block, 0, s, L, x, f, y, ydown, partials,
-                         nti, ntj);
+    case 16:
+      f(std::integral_constant<int, 16>{});
       break;
-    case Stencil::RESIDUAL_NORM:
-      hipLaunchKernelGGL((k_stencil<T, 2, SR>), grid, block, 0, s, L, x, f, y, ydown, partials,
-                         nti, ntj);
-      break;
-    case Stencil::RESIDUAL_NORM_DOWN:
-      hipLaunchKernelGGL((k_stencil<T, 3, SR>), grid, block, 0, s, L, x, f, y, ydown, partials,
-                         nti, ntj);
+    default:
+      f(std::integral_constant<int, 4>{});
       break;
   }
   return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_line_solve(const Lvl<T>& L, const T* r, T* z, hipStream_t s) {
+hipError_t launch_stencil(const Lvl<T>& L, Stencil mode, const T* x, const T* f, T* y,
+                          float* ydown, double* partials, int64_t* nblocks, hipStream_t s,
+                          Shape sh) {
+  return with_rows(sh.rows, [&](auto R) {
+    constexpr int SR = decltype(R)::value;
+    const int nti = cdiv(L.nx, 64), ntj = cdiv(L.ny, SR), nkb = cdiv(L.nz, KSEG);
+    const dim3 grid(nti * ntj * nkb), block(64 * SR);
+    if (nblocks) *nblocks = (int64_t)nti * ntj * nkb;
+    switch (mode) {
+      case Stencil::SPMV:
+        hipLaunchKernelGGL((k_stencil<T, 0, SR>), grid, block, 0, s, L, x, f, y, ydown,
+                           partials, nti, ntj, sh.group);
+        break;
+      case Stencil::RESIDUAL:
+        hipLaunchKernelGGL((k_stencil<T, 1, SR>), grid, block, 0, s, L, x, f, y, ydown,
+                           partials, nti, ntj, sh.group);
+        break;
+      case Stencil::RESIDUAL_NORM:
+        hipLaunchKernelGGL((k_stencil<T, 2, SR>), grid, block, 0, s, L, x, f, y, ydown,
+                           partials, nti, ntj, sh.group);
+        break;
+      case Stencil::RESIDUAL_NORM_DOWN:
+        hipLaunchKernelGGL((k_stencil<T, 3, SR>), grid, block, 0, s, L, x, f, y, ydown,
+                           partials, nti, ntj, sh.group);
+        break;
+    }
+  });
+}
+
+template <typename T>
+hipError_t launch_line_solve(const Lvl<T>& L, const T* r, T* z, hipStream_t s, Shape sh) {
   LineArgs<T> a{};
   a.a = r;
   a.o0 = z;
   a.rho = T(1);
-  return line_dispatch<T, LINE_SOLVE>(L, a, s);
+  return line_dispatch<T, LINE_SOLVE>(L, a, s, sh.group);
 }
 
 template <typename T>
 hipError_t launch_smooth(const Lvl<T>& L, const T* f, const T* uin, T* uout, T rho,
-                         hipStream_t s) {
+                         hipStream_t s, Shape sh) {
   LineArgs<T> a{};
   a.a = uin;
   a.b = f;
   a.o0 = uout;
   a.rho = rho;
-  return line_dispatch<T, LINE_SMOOTH>(L, a, s);
+  return line_dispatch<T, LINE_SMOOTH>(L, a, s, sh.group);
 }
 
 template <typename T>
 hipError_t launch_restrict_smooth(const Lvl<T>& C, const Lvl<T>& F, const T* rf, T* fc, T* uc,
-                                  T rho, hipStream_t s) {
+                                  T rho, hipStream_t s, Shape sh) {
   LineArgs<T> a{};
   a.a = rf;
   a.o0 = uc;
   a.o1 = fc;
   a.rho = rho;
   a.F = F;
-  return line_dispatch<T, LINE_RESTRICT_SMOOTH>(C, a, s);
+  return line_dispatch<T, LINE_RESTRICT_SMOOTH>(C, a, s, sh.group);
 }
 
 template <typename T>
-hipError_t launch_line_solve_scaled(const Lvl<T>& L, const T* r, T* z, T scale, hipStream_t s) {
+hipError_t launch_line_solve_scaled(const Lvl<T>& L, const T* r, T* z, T scale, hipStream_t s,
+                                    Shape sh) {
   LineArgs<T> a{};
   a.a = r;
   a.o0 = z;
   a.rho = scale;
-  return line_dispatch<T, LINE_SOLVE>(L, a, s);
+  return line_dispatch<T, LINE_SOLVE>(L, a, s, sh.group);
 }
 
 template <typename T>
 hipError_t launch_smooth_norm(const Lvl<T>& L, const T* f, const T* uin, T* uout, T rho,
-                              double* partials, int64_t* nblocks, hipStream_t s) {
+                              double* partials, int64_t* nblocks, hipStream_t s, Shape sh) {
   LineArgs<T> a{};
   a.a = uin;
   a.b = f;
@@ -1693,50 +1752,58 @@ hipError_t launch_smooth_norm(const Lvl<T>& L, const T* f, const T* uin, T* uout
   a.rho = rho;
   a.partials = partials;
   *nblocks = line_blocks(L.nx, L.ny);
-  return line_dispatch<T, LINE_SMOOTH_NORM>(L, a, s);
+  return line_dispatch<T, LINE_SMOOTH_NORM>(L, a, s, sh.group);
 }
 
 template <typename T>
 hipError_t launch_resrestrict(const Lvl<T>& F, const Lvl<T>& C, const T* u, const T* f, T* fc,
-                              hipStream_t s) {
-  const int nti = cdiv(C.nx, 64), ntj = cdiv(C.ny, SROWS), nkb = cdiv(C.nz, KSEG);
-  hipLaunchKernelGGL((k_resrestrict<T>), dim3(nti * ntj * nkb), dim3(NTHREADS), 0, s, F, C, u, f,
-                     fc, nti, ntj);
-  return hipGetLastError();
+                              hipStream_t s, Shape sh) {
+  return with_rows(sh.rows, [&](auto R) {
+    constexpr int SR = decltype(R)::value;
+    const int nti = cdiv(C.nx, 64), ntj = cdiv(C.ny, SR), nkb = cdiv(C.nz, KSEG);
+    hipLaunchKernelGGL((k_resrestrict<T, SR>), dim3(nti * ntj * nkb), dim3(64 * SR), 0, s, F, C,
+                       u, f, fc, nti, ntj, sh.group);
+  });
 }
 
 hipError_t launch_correct_residual(const Lvl<double>& L, const double* u, const float* e,
                                    const double* f, double* uout, float* r32, double* partials,
-                                   int64_t* nblocks, hipStream_t s) {
-  const int nti = cdiv(L.nx, 64), ntj = cdiv(L.ny, SROWS), nkb = cdiv(L.nz, KSEG);
-  *nblocks = (int64_t)nti * ntj * nkb;
-  hipLaunchKernelGGL(k_correct_residual, dim3(nti * ntj * nkb), dim3(NTHREADS), 0, s, L, u, e, f,
-                     uout, r32, partials, nti, ntj);
-  return hipGetLastError();
+                                   int64_t* nblocks, hipStream_t s, Shape sh) {
+  return with_rows(sh.rows, [&](auto R) {
+    constexpr int SR = decltype(R)::value;
+    const int nti = cdiv(L.nx, 64), ntj = cdiv(L.ny, SR), nkb = cdiv(L.nz, KSEG);
+    *nblocks = (int64_t)nti * ntj * nkb;
+    hipLaunchKernelGGL(k_correct_residual<SR>, dim3(nti * ntj * nkb), dim3(64 * SR), 0, s, L, u,
+                       e, f, uout, r32, partials, nti, ntj, sh.group);
+  });
 }
 
 template <typename T>
 hipError_t launch_prolongate(const Lvl<T>& C, const Lvl<T>& F, const T* uc, T* uf,
-                             hipStream_t s) {
-  const int nti = cdiv(F.nx, 64), ntj = cdiv(F.ny, SROWS), nkb = cdiv(F.nz, KSEG);
-  hipLaunchKernelGGL((k_prolongate<T>), dim3(nti * ntj * nkb), dim3(NTHREADS), 0, s, C, F, uc,
-                     uf, nti, ntj);
-  return hipGetLastError();
+                             hipStream_t s, Shape sh) {
+  return with_rows(sh.rows, [&](auto R) {
+    constexpr int SR = decltype(R)::value;
+    const int nti = cdiv(F.nx, 64), ntj = cdiv(F.ny, SR), nkb = cdiv(F.nz, KSEG);
+    hipLaunchKernelGGL((k_prolongate<T, SR>), dim3(nti * ntj * nkb), dim3(64 * SR), 0, s, C, F,
+                       uc, uf, nti, ntj, sh.group);
+  });
 }
 
 hipError_t launch_cg_p1(const Lvl<double>& L, double* u, double* p, const double* z, double* q,
-                        const CgState* st, double* partials, int64_t* nblocks, hipStream_t s) {
-  constexpr int SR = SROWS;
-  const int nti = cdiv(L.nx, 64), ntj = cdiv(L.ny, SR), nkb = cdiv(L.nz, KSEG);
-  *nblocks = (int64_t)nti * ntj * nkb;
-  hipLaunchKernelGGL(k_cg_p1<SR>, dim3(nti * ntj * nkb), dim3(64 * SR), 0, s, L, u, p, z, q, st,
-                     partials, nti, ntj);
-  return hipGetLastError();
+                        const CgState* st, double* partials, int64_t* nblocks, hipStream_t s,
+                        Shape sh) {
+  return with_rows(sh.rows, [&](auto R) {
+    constexpr int SR = decltype(R)::value;
+    const int nti = cdiv(L.nx, 64), ntj = cdiv(L.ny, SR), nkb = cdiv(L.nz, KSEG);
+    *nblocks = (int64_t)nti * ntj * nkb;
+    hipLaunchKernelGGL(k_cg_p1<SR>, dim3(nti * ntj * nkb), dim3(64 * SR), 0, s, L, u, p, z, q, st,
+                       partials, nti, ntj, sh.group);
+  });
 }
 
 hipError_t launch_cg_p2(const Lvl<double>& L, double* r, const double* q, double* z,
                         const CgState* st, int init, double* partials, int64_t* nblocks,
-                        hipStream_t s) {
+                        hipStream_t s, Shape sh) {
   LineArgs<double> a{};
   a.a = q;
   a.rw = r;
@@ -1745,7 +1812,7 @@ hipError_t launch_cg_p2(const Lvl<double>& L, double* r, const double* q, double
   a.init = init;
   a.partials = partials;
   *nblocks = line_blocks(L.nx, L.ny);
-  return line_dispatch<double, LINE_CG>(L, a, s);
+  return line_dispatch<double, LINE_CG>(L, a, s, sh.group);
 }
 
 template <typename TZ>
@@ -1761,22 +1828,26 @@ hipError_t launch_fcg_zq(const Lvl<double>& L, const TZ* z, const double* q, dou
 template <typename TZ>
 hipError_t launch_fcg_dir(const Lvl<double>& L, const TZ* z, double* p, double* q,
                           const double* r, const CgState* st, double* partials, int64_t* nblocks,
-                          hipStream_t s) {
-  const int nti = cdiv(L.nx, 64), ntj = cdiv(L.ny, SROWS), nkb = cdiv(L.nz, KSEG);
-  *nblocks = (int64_t)nti * ntj * nkb;
-  hipLaunchKernelGGL((k_fcg_dir<TZ>), dim3(nti * ntj * nkb), dim3(NTHREADS), 0, s, L, z, p, q,
-                     r, st, partials, nti, ntj);
-  return hipGetLastError();
+                          hipStream_t s, Shape sh) {
+  return with_rows(sh.rows, [&](auto R) {
+    constexpr int SR = decltype(R)::value;
+    const int nti = cdiv(L.nx, 64), ntj = cdiv(L.ny, SR), nkb = cdiv(L.nz, KSEG);
+    *nblocks = (int64_t)nti * ntj * nkb;
+    hipLaunchKernelGGL((k_fcg_dir<TZ, SR>), dim3(nti * ntj * nkb), dim3(64 * SR), 0, s, L, z, p,
+                       q, r, st, partials, nti, ntj, sh.group);
+  });
 }
 
 hipError_t launch_fcg_update(const Lvl<double>& L, double* u, double* r, const double* p,
                              const double* q, float* rdown, const CgState* st, double* partials,
-                             int64_t* nblocks, hipStream_t s) {
-  const int nti = cdiv(L.nx, 64), ntj = cdiv(L.ny, SROWS), nkb = cdiv(L.nz, KSEG);
-  *nblocks = (int64_t)nti * ntj * nkb;
-  hipLaunchKernelGGL(k_fcg_update, dim3(nti * ntj * nkb), dim3(NTHREADS), 0, s, L, u, r, p, q,
-                     rdown, st, partials, nti, ntj);
-  return hipGetLastError();
+                             int64_t* nblocks, hipStream_t s, Shape sh) {
+  return with_rows(sh.rows, [&](auto R) {
+    constexpr int SR = decltype(R)::value;
+    const int nti = cdiv(L.nx, 64), ntj = cdiv(L.ny, SR), nkb = cdiv(L.nz, KSEG);
+    *nblocks = (int64_t)nti * ntj * nkb;
+    hipLaunchKernelGGL(k_fcg_update<SR>, dim3(nti * ntj * nkb), dim3(64 * SR), 0, s, L, u, r, p,
+                       q, rdown, st, partials, nti, ntj, sh.group);
+  });
 }
 
 hipError_t launch_fcg_fin(int which, CgState* st, const double* partials, int64_t nblocks,
@@ -1797,10 +1868,10 @@ template hipError_t launch_fcg_zq<float>(const Lvl<double>&, const float*, const
                                          double*, int64_t*, hipStream_t);
 template hipError_t launch_fcg_dir<double>(const Lvl<double>&, const double*, double*, double*,
                                            const double*, const CgState*, double*, int64_t*,
-                                           hipStream_t);
+                                           hipStream_t, Shape);
 template hipError_t launch_fcg_dir<float>(const Lvl<double>&, const float*, double*, double*,
                                           const double*, const CgState*, double*, int64_t*,
-                                          hipStream_t);
+                                          hipStream_t, Shape);
 
 hipError_t launch_cg_fin1(CgState* st, const double* partials, int64_t nblocks, hipStream_t s) {
   hipLaunchKernelGGL(k_cg_fin1, dim3(1), dim3(NTHREADS), 0, s, st, partials, nblocks);
@@ -1842,19 +1913,21 @@ hipError_t launch_add_f32_to_f64(double* u, const float* e, int64_t n, hipStream
 
 #define GMG_INSTANTIATE(T)                                                                    \
   template hipError_t launch_stencil<T>(const Lvl<T>&, Stencil, const T*, const T*, T*,       \
-                                        float*, double*, int64_t*, hipStream_t);              \
-  template hipError_t launch_line_solve<T>(const Lvl<T>&, const T*, T*, hipStream_t);         \
-  template hipError_t launch_smooth<T>(const Lvl<T>&, const T*, const T*, T*, T, hipStream_t); \
+                                        float*, double*, int64_t*, hipStream_t, Shape);       \
+  template hipError_t launch_line_solve<T>(const Lvl<T>&, const T*, T*, hipStream_t, Shape);  \
+  template hipError_t launch_smooth<T>(const Lvl<T>&, const T*, const T*, T*, T, hipStream_t, \
+                                       Shape);                                                \
   template hipError_t launch_restrict_smooth<T>(const Lvl<T>&, const Lvl<T>&, const T*, T*,   \
-                                                T*, T, hipStream_t);                          \
+                                                T*, T, hipStream_t, Shape);                   \
   template hipError_t launch_prolongate<T>(const Lvl<T>&, const Lvl<T>&, const T*, T*,        \
-                                           hipStream_t);                                      \
+                                           hipStream_t, Shape);                               \
   template hipError_t launch_fill<T>(T*, int64_t, T, hipStream_t);                            \
-  template hipError_t launch_line_solve_scaled<T>(const Lvl<T>&, const T*, T*, T, hipStream_t); \
+  template hipError_t launch_line_solve_scaled<T>(const Lvl<T>&, const T*, T*, T, hipStream_t, \
+                                                  Shape);                                     \
   template hipError_t launch_smooth_norm<T>(const Lvl<T>&, const T*, const T*, T*, T, double*, \
-                                            int64_t*, hipStream_t);                           \
+                                            int64_t*, hipStream_t, Shape);                    \
   template hipError_t launch_resrestrict<T>(const Lvl<T>&, const Lvl<T>&, const T*, const T*, \
-                                            T*, hipStream_t);
+                                            T*, hipStream_t, Shape);
 
 GMG_INSTANTIATE(double)
 GMG_INSTANTIATE(float)

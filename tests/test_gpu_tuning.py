@@ -1,0 +1,101 @@
+"""Launch shapes and the autotuner: every shape computes the same values.
+
+The stencil and line kernels compute each output element with the same
+arithmetic whatever the workgroup shape and tile order, so their outputs must
+be bitwise identical across shapes; only FP64 reductions (norms, dot products)
+may differ, in their summation order.  After autotuning, the solvers still
+match the oracle."""
+
+import numpy as np
+import pytest
+
+import workloads as W
+from tests.gpu_util import problem
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+SHAPES = [(4, 0), (8, 0), (16, 0), (4, 1), (8, 2), (16, 4), (4, 8)]
+
+
+@pytest.fixture(autouse=True, scope="module")
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("needs a GPU")
+
+
+def _set_all(G, ctx, rows, group):
+    for k in G.TUNED_KERNELS:
+        for lvl in range(ctx.nlevels):
+            for prec in (G.GMG_F64, G.GMG_F32):
+                G.gmg_set_launch(ctx, k, lvl, prec, rows, group)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("grid", [(96, 40, 37, 3), (256, 24, 64, 2)])
+def test_kernels_bitwise_identical_across_shapes(grid, prec):
+    import paper_1402_3545_amd as G
+    nx, ny, nz, L = grid
+    ctx, _, _ = problem(nx, ny, nz, nlevels=L, seed=21)
+    dt = torch.float64 if prec == 0 else torch.float32
+    n = nx * ny * nz
+    x = ctx.to_device(W.uniform_pm1(31, 1, n), dtype=dt)
+    f = ctx.to_device(W.uniform_pm1(31, 2, n), dtype=dt)
+    ref = None
+    for rows, group in SHAPES:
+        _set_all(G, ctx, rows, group)
+        y, r, u = ctx.empty(dtype=dt), ctx.empty(dtype=dt), x.clone()
+        G.spmv(ctx, 0, x, y)
+        nrm = G.gmg_residual(ctx, 0, f, x, r, norm=True)
+        G.line_smooth(ctx, 0, f, u, nsweeps=2)
+        uc = ctx.to_device(W.uniform_pm1(32, 1, (nx // 2) * (ny // 2) * nz), 1, dtype=dt)
+        uf = x.clone()
+        G.gmg_prolongate(ctx, 1, uc, uf)
+        out = [t.cpu() for t in (y, r, u, uf)]
+        if ref is None:
+            ref, ref_nrm = out, nrm
+            continue
+        for a, b in zip(out, ref):
+            assert torch.equal(a, b), (rows, group)
+        assert nrm == pytest.approx(ref_nrm, rel=1e-13 if prec == 0 else 1e-12)
+
+
+@pytest.mark.parametrize("prec_precond", [0, 1])
+def test_autotune_then_solve_matches_oracle(prec_precond):
+    import paper_1402_3545_amd as G
+    w = W.SMALL
+    ctx, orc, _ = problem(w.nx, w.ny, w.nz, nlevels=w.nlevels, kv=w.kv, seed=w.seed,
+                          kh_model=w.kh_model, prec_precond=prec_precond)
+    f = w.rhs()
+    fd = ctx.to_device(f)
+    ud0 = ctx.empty()
+    it0, rel0, _, st0 = G.gmg_solve(ctx, fd, ud0, rtol=1e-10, maxit=60)
+    G.gmg_autotune(ctx, reps=2)
+    table = G.launch_table(ctx)
+    assert all(r in (4, 8, 16) and 0 <= g <= 8 for r, g in table.values())
+    ud = ctx.empty()
+    it, rel, _, st = G.gmg_solve(ctx, fd, ud, rtol=1e-10, maxit=60)
+    assert st == st0 == 0 and it == it0
+    assert rel == pytest.approx(rel0, rel=1e-6)
+    u = ctx.from_device(ud)
+    true_rel = orc.residual_norm2_rows(f, u) ** 0.5 / np.linalg.norm(f)
+    assert true_rel < 1e-10
+    # the line-preconditioned CG after tuning
+    ud.zero_()
+    itc, relc, _, stc = G.pcg_solve(ctx, fd, ud, rtol=1e-8, maxit=500)
+    assert stc == 0
+    true_rel = orc.residual_norm2_rows(f, ctx.from_device(ud)) ** 0.5 / np.linalg.norm(f)
+    assert true_rel < 1e-8
+
+
+def test_launch_shape_validation():
+    import paper_1402_3545_amd as G
+    ctx, _, _ = problem(16, 16, 8, nlevels=2)
+    G.gmg_set_launch(ctx, "spmv", 1, G.GMG_F32, 16, 3)
+    assert G.gmg_get_launch(ctx, "spmv", 1, G.GMG_F32) == (16, 3)
+    for bad in [("spmv", 2, 0, 4, 0), ("spmv", 0, 2, 4, 0), ("spmv", 0, 0, 5, 0),
+                ("spmv", 0, 0, 4, -1), ("spmv", 0, 0, 4, 5000), (99, 0, 0, 4, 0)]:
+        with pytest.raises(G.GmgError):
+            G.gmg_set_launch(ctx, *bad)
+    with pytest.raises(G.GmgError):
+        G.gmg_autotune(ctx, reps=0)

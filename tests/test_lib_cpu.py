@@ -75,4 +75,7 @@ def test_null_context_is_rejected():
     import paper_1402_3545_amd as G
     assert G._lib.spmv(None, 0, 0, None, None, None) == G.GMG_EINVAL
     assert G._lib.gmg_vcycle(None, None, None, None) == G.GMG_EINVAL
+    assert G._lib.gmg_set_launch(None, 0, 0, 0, 4, 0) == G.GMG_EINVAL
+    assert G._lib.gmg_get_launch(None, 0, 0, 0, None, None) == G.GMG_EINVAL
+    assert G._lib.gmg_autotune(None, 3, None) == G.GMG_EINVAL
     assert G._lib.gmg_destroy(None) == G.GMG_OK
