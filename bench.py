@@ -60,7 +60,19 @@ SOLVES = ("mg_f64", "pcg_f64", "mg_mixed", "fcg_mixed")
 # (FETCH_SIZE, then WRITE_SIZE; KiB per dispatch averaged over the kernel's
 # dispatches) scaled by what the same counters read for a plain copy of known
 # size.  Reported only while the kernel source hashes to the recorded value.
-MEASURED_TRAFFIC = {}
+MEASURED_TRAFFIC = {
+    # k_cg_p1, 64x4 workgroups, tile groups of 8 (the stored launch shape);
+    # profiles/cg_p1_1024x1024x128_pmc.md.  Plain-copy calibration: 2 GiB read
+    # + 2 GiB written read FETCH_SIZE 898800.3 KiB, WRITE_SIZE 2097216.8 KiB.
+    ("cg_spmv", 0, "f64"): {
+        "fetch_kib": 2470665.705,
+        "write_kib": 3146270.480,
+        "copy_fetch_scale": 2097152.0 / 898800.3125,
+        "copy_write_scale": 2097152.0 / 2097216.7679,
+        "source_sha256": "32ada5f3ce93084bbca23f46999556743b27082df3319f5bb9d729866e3660f8",
+        "shape": [4, 8],
+    },
+}
 KERNEL_SOURCE = os.path.join(ROOT, "paper_1402_3545_amd", "csrc", "kernels.hip")
 COPY_PROBE_BYTES = 2 << 30   # per direction
 
@@ -87,9 +99,11 @@ def source_sha256():
         return hashlib.sha256(fh.read()).hexdigest()
 
 
-def measured_traffic(key):
+def measured_traffic(key, shape):
+    """Counter-derived bytes per launch, or None when the kernel source or its
+    launch shape differ from those the counters were taken with."""
     rec = MEASURED_TRAFFIC.get(key)
-    if rec is None or rec["source_sha256"] != source_sha256():
+    if rec is None or rec["source_sha256"] != source_sha256() or list(shape) != rec["shape"]:
         return None
     return (rec["fetch_kib"] * 1024.0 * rec["copy_fetch_scale"] +
             rec["write_kib"] * 1024.0 * rec["copy_write_scale"])
@@ -272,7 +286,8 @@ def main():
 
     copy_gbs = copy_probe(torch)
     log(f"[bench] plain-copy ceiling {copy_gbs:.0f} GB/s")
-    traffic = measured_traffic(dom)
+    prec_id = 0 if dom[2] == "f64" else 1
+    traffic = measured_traffic(dom, G.gmg_get_launch(ctx64, dom[0], dom[1], prec_id))
 
     base = None
     if not args.no_cpu_baseline:
