@@ -61,16 +61,16 @@ SOLVES = ("mg_f64", "pcg_f64", "mg_mixed", "fcg_mixed")
 # dispatches) scaled by what the same counters read for a plain copy of known
 # size.  Reported only while the kernel source hashes to the recorded value.
 MEASURED_TRAFFIC = {
-    # k_cg_p1, 64x4 workgroups, tile groups of 8 (the stored launch shape);
+    # k_cg_p1, 64x16 workgroups, tile groups of 8 (the stored launch shape);
     # profiles/cg_p1_1024x1024x128_pmc.md.  Plain-copy calibration: 2 GiB read
-    # + 2 GiB written read FETCH_SIZE 898800.3 KiB, WRITE_SIZE 2097216.8 KiB.
+    # + 2 GiB written read FETCH_SIZE 898803.8 KiB, WRITE_SIZE 2097248.2 KiB.
     ("cg_spmv", 0, "f64"): {
-        "fetch_kib": 2470665.705,
-        "write_kib": 3146270.480,
-        "copy_fetch_scale": 2097152.0 / 898800.3125,
-        "copy_write_scale": 2097152.0 / 2097216.7679,
-        "source_sha256": "32ada5f3ce93084bbca23f46999556743b27082df3319f5bb9d729866e3660f8",
-        "shape": [4, 8],
+        "fetch_kib": 2306866.651,
+        "write_kib": 3145864.543,
+        "copy_fetch_scale": 2097152.0 / 898803.7768,
+        "copy_write_scale": 2097152.0 / 2097248.2143,
+        "source_sha256": "1f0c3685274a91b40ff63cc8605faff23e9323a9cf90ebe4104d8432a9732394",
+        "shape": [16, 8],
     },
 }
 KERNEL_SOURCE = os.path.join(ROOT, "paper_1402_3545_amd", "csrc", "kernels.hip")

@@ -205,14 +205,25 @@ __device__ __forceinline__ char* roww(T* f, int j, int64_t jstride) {
 }
 
 // Load/store through a wave-uniform base and a 32-bit per-lane byte offset
-// (the saddr form of the global memory instructions).
+// (the saddr form of the global memory instructions).  Stores are
+// non-temporal: every output is written once and read by a later kernel, so
+// it should not displace the halo rows the L2 is holding for neighbouring
+// tiles.  ldn is the non-temporal load for fields a kernel reads exactly once
+// (no halo); fields read with horizontal neighbours use ldo.
 template <typename T>
 __device__ __forceinline__ T ldo(const char* base, uint32_t off) {
   return *reinterpret_cast<const T*>(base + off);
 }
 template <typename T>
+__device__ __forceinline__ T ldn(const char* base, uint32_t off) {
+  return __builtin_nontemporal_load(reinterpret_cast<const T*>(base + off));
+}
+template <typename T>
 __device__ __forceinline__ void sto(char* base, uint32_t off, T v) {
-  *reinterpret_cast<T*>(base + off) = v;
+  if constexpr (std::is_arithmetic_v<T>)
+    __builtin_nontemporal_store(v, reinterpret_cast<T*>(base + off));
+  else
+    *reinterpret_cast<T*>(base + off) = v;
 }
 
 // The layer walk shared by the stencil kernels: P supplies the per-layer
@@ -316,7 +327,7 @@ struct StencilPol {
     const uint32_t ok = layer_off<FULL>(k, op.nz, op.kb);
     const uint32_t okp = (uint32_t)min(k + 1, op.nz - 1) * op.kb;
     op.load(ok, okp, v.xp, v.xe, v.xw, v.xn, v.xs);
-    if constexpr (MODE != (int)Stencil::SPMV) v.f = ldo<T>(rf, op.oc + ok);
+    if constexpr (MODE != (int)Stencil::SPMV) v.f = ldn<T>(rf, op.oc + ok);
   }
   __device__ __forceinline__ void step(int s, const In& v) {
     const uint32_t o = op.oc + layer_off<FULL>(op.k0 + s, op.nz, op.kb);
@@ -543,21 +554,21 @@ __device__ __forceinline__ void line_body(const Lvl<T>& L, const LineArgs<T>& a,
   auto load_step = [&](int k, StepIn<T, MODE>& v) {
     const uint32_t o = off(k, ic);
     if constexpr (MODE == LINE_SOLVE) {
-      v.r = ldo<T>(rA, o);
+      v.r = ldn<T>(rA, o);
     } else if constexpr (kSmooth) {
       v.un = ldo<T>(rA, (uint32_t)ic * ES + (uint32_t)min(max(k + dir, 0), nz - 1) * kbytes);
       v.ue = ldo<T>(rA, off(k, ie));
       v.uw = ldo<T>(rA, off(k, iw));
       v.unn = ldo<T>(rAn, o);
       v.us = ldo<T>(rAs, o);
-      v.f = ldo<T>(rB, o);
+      v.f = ldn<T>(rB, o);
     } else if constexpr (MODE == LINE_RESTRICT_SMOOTH) {
       const uint32_t fo = (uint32_t)(2 * ic) * ES + kcl(k) * fkbytes;
       v.lo = ldo<V2>(rF0, fo);
       v.hi = ldo<V2>(rF1, fo);
     } else {
-      v.r = ldo<T>(rW, o);
-      v.q = ldo<T>(rA, o);
+      v.r = ldn<T>(rW, o);
+      v.q = ldn<T>(rA, o);
     }
   };
 
@@ -984,7 +995,7 @@ struct ProlongPol {
     v.b = ldo<T>(rc0, oI2 + okc);
     v.c = ldo<T>(rc1, oI + okc);
     v.d = ldo<T>(rc1, oI2 + okc);
-    v.u = ldo<T>(rf, of + layer_off<FULL>(k, nz, fkb));
+    v.u = ldn<T>(rf, of + layer_off<FULL>(k, nz, fkb));
   }
   __device__ __forceinline__ void step(int s, const In& v) {
     const T p = T(9) * v.a + T(3) * v.b + T(3) * v.c + v.d;
@@ -1055,9 +1066,9 @@ struct CgP1Pol {
     const uint32_t ok = layer_off<FULL>(k, op.nz, op.kb);
     const uint32_t okp = (uint32_t)min(k + 1, op.nz - 1) * op.kb;
     op.load(ok, okp, v.xp, v.xe, v.xw, v.xn, v.xs);
-    v.p = ldo<double>(rp, op.oc + ok);
-    v.q = ldo<double>(rq, op.oc + ok);
-    v.u = ldo<double>(ru, op.oc + ok);
+    v.p = ldn<double>(rp, op.oc + ok);
+    v.q = ldn<double>(rq, op.oc + ok);
+    v.u = ldn<double>(ru, op.oc + ok);
   }
   __device__ __forceinline__ void step(int s, const In& v) {
     const uint32_t o = op.oc + layer_off<FULL>(op.k0 + s, op.nz, op.kb);
@@ -1160,9 +1171,9 @@ struct FcgDirPol {
     op.load(layer_off<FULL>(k, op.nz, op.kb), (uint32_t)min(k + 1, op.nz - 1) * op.kb, v.xp,
             v.xe, v.xw, v.xn, v.xs);
     const uint32_t o = oc + layer_off<FULL>(k, op.nz, kb);
-    v.p = ldo<double>(rp, o);
-    v.q = ldo<double>(rq, o);
-    v.r = ldo<double>(rr, o);
+    v.p = ldn<double>(rp, o);
+    v.q = ldn<double>(rq, o);
+    v.r = ldn<double>(rr, o);
   }
   __device__ __forceinline__ void step(int s, const In& v) {
     const uint32_t o = oc + layer_off<FULL>(op.k0 + s, op.nz, kb);
@@ -1231,10 +1242,10 @@ struct FcgUpdPol {
 
   __device__ __forceinline__ void load(int s, In& v) {
     const uint32_t o = oc + layer_off<FULL>(k0 + s, nz, kb);
-    v.u = ldo<double>(ru, o);
-    v.r = ldo<double>(rr, o);
-    v.p = ldo<double>(rp, o);
-    v.q = ldo<double>(rq, o);
+    v.u = ldn<double>(ru, o);
+    v.r = ldn<double>(rr, o);
+    v.p = ldn<double>(rp, o);
+    v.q = ldn<double>(rq, o);
   }
   __device__ __forceinline__ void step(int s, const In& v) {
     const int kc = FULL ? k0 + s : min(k0 + s, nz - 1);
