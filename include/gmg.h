@@ -202,6 +202,37 @@ int gmg_timing_enable(gmg_ctx *c, int enable);
 int gmg_timing_read(gmg_ctx *c, int kernel, int level, int prec, int64_t *count,
                     double *total_ms);
 
+/* Layout conversion of one field on the device between the canonical
+ * z-contiguous order (j*nx + i)*nz + k -- the order of the caller's host data
+ * and of the synthetic inputs -- and the x-contiguous order of
+ * gmg_field_layout (Sec. 3.1 stores fields x-contiguous; Sec. 5.1 reports
+ * the host transfer and this transpose as part of the total solution time).
+ * level selects the grid, prec the element type (GMG_F64 / GMG_F32); src and
+ * dst are distinct device arrays of nx*ny*nz (z-contiguous) and `elems` of
+ * gmg_field_layout (x-contiguous) elements, owned by the caller; padding
+ * columns of the x-contiguous field are not written.  Asynchronous on
+ * `stream`.  GMG_EINVAL for a bad level or precision, NULL or unaligned
+ * pointers, src == dst. */
+int gmg_transpose_in(gmg_ctx *c, int level, int prec, const void *src_z, void *dst_x,
+                     void *stream);
+int gmg_transpose_out(gmg_ctx *c, int level, int prec, const void *src_x, void *dst_z,
+                      void *stream);
+
+/* A whole solve from host memory (Sec. 5.1 "total solution time"): copies
+ * f_host and the initial guess u_host (both FP64, z-contiguous order,
+ * nx*ny*nz values, caller-owned pageable or pinned host memory) to the
+ * device, converts their layout, runs gmg_solve (method 0: multigrid, or
+ * refinement with FP32 cycles when the context's preconditioner is FP32) or
+ * pcg_solve (method 1: line preconditioner, 2: V-cycle preconditioner,
+ * flexible CG), converts u back and copies it into u_host.  The context
+ * allocates three level-0 FP64 device fields on first use and keeps them
+ * until gmg_destroy.  timings_ms (may be NULL) receives 5 values: host to
+ * device copies, layout conversion in, solve, layout conversion out, device
+ * to host copy.  Synchronises `stream`.  Returns the solve's status
+ * (GMG_ENOCONV still copies the last iterate out). */
+int gmg_solve_host(gmg_ctx *c, int method, const double *f_host, double *u_host, double rtol,
+                   int maxit, int *iters, double *relres, double *timings_ms, void *stream);
+
 /* Launch shapes and the autotuner.  Sec. 5.1 fixes one thread-block layout
  * for every kernel; here each kernel kind (gmg_kernel), level and precision
  * has its own shape, which only changes how the work is cut into workgroups:

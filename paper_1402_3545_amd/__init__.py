@@ -27,7 +27,8 @@ EXPORTS = ("gmg_default_params", "gmg_setup", "gmg_destroy", "gmg_field_layout",
            "line_solve", "line_smooth", "gmg_residual", "gmg_restrict_smooth", "gmg_prolongate",
            "gmg_vcycle", "gmg_solve", "pcg_solve", "gmg_batch_setup", "gmg_batch_layout",
            "gmg_batch_solve", "gmg_timing_enable", "gmg_timing_read", "gmg_set_launch",
-           "gmg_get_launch", "gmg_autotune", "gmg_last_error")
+           "gmg_get_launch", "gmg_autotune", "gmg_transpose_in", "gmg_transpose_out",
+           "gmg_solve_host", "gmg_last_error")
 
 # kernel ids of the timing facility (gmg_kernel in include/gmg.h)
 KERNELS = ("spmv", "residual", "line_solve", "smooth", "restrict_smooth", "prolongate",
@@ -94,6 +95,9 @@ def _load():
         "gmg_set_launch": (i32, [vp, i32, i32, i32, i32, i32]),
         "gmg_get_launch": (i32, [vp, i32, i32, i32, intp, intp]),
         "gmg_autotune": (i32, [vp, i32, vp]),
+        "gmg_transpose_in": (i32, [vp, i32, i32, vp, vp, vp]),
+        "gmg_transpose_out": (i32, [vp, i32, i32, vp, vp, vp]),
+        "gmg_solve_host": (i32, [vp, i32, vp, vp, dbl, i32, intp, dblp, dblp, vp]),
         "gmg_last_error": (C.c_char_p, []),
     }
     for name, (res, args) in sig.items():
@@ -483,3 +487,48 @@ def tuned(ctx, reps=3, path=LAUNCH_TABLE, stream=None):
         return store[key], True
     gmg_autotune(ctx, reps, stream)
     return launch_table(ctx), False
+
+
+# ---------------------------------------------------------------------------
+# Layout conversion and host-memory solves
+# ---------------------------------------------------------------------------
+def _prec_of(t):
+    import torch
+    return GMG_F64 if t.dtype == torch.float64 else GMG_F32
+
+
+def gmg_transpose_in(ctx, level, src_z, dst_x, stream=None):
+    """Device z-contiguous (j*nx+i)*nz+k -> x-contiguous field (same dtype)."""
+    _check(_lib.gmg_transpose_in(ctx.handle, int(level), _prec_of(src_z), src_z.data_ptr(),
+                                 dst_x.data_ptr(), _stream(stream)))
+
+
+def gmg_transpose_out(ctx, level, src_x, dst_z, stream=None):
+    """Device x-contiguous field -> z-contiguous (j*nx+i)*nz+k (same dtype)."""
+    _check(_lib.gmg_transpose_out(ctx.handle, int(level), _prec_of(src_x), src_x.data_ptr(),
+                                  dst_z.data_ptr(), _stream(stream)))
+
+
+HOST_METHODS = {"mg": 0, "pcg": 1, "fcg": 2}
+
+
+def gmg_solve_host(ctx, f, u, method="mg", rtol=1e-8, maxit=100, stream=None, check=True):
+    """Solve from host arrays in canonical z-contiguous order (FP64, C order);
+    u is the initial guess and is overwritten with the solution.  Returns
+    (iters, relres, timings_ms dict, status)."""
+    f = np.ascontiguousarray(f, dtype=np.float64)
+    if not (isinstance(u, np.ndarray) and u.dtype == np.float64 and u.flags.c_contiguous):
+        raise ValueError("u must be a C-contiguous float64 numpy array (it is overwritten)")
+    n = ctx.nx * ctx.ny * ctx.nz
+    if f.size != n or u.size != n:
+        raise ValueError(f"f and u need {n} values")
+    it, rel = C.c_int(), C.c_double()
+    tm = (C.c_double * 5)()
+    m = HOST_METHODS[method] if isinstance(method, str) else int(method)
+    st = _lib.gmg_solve_host(ctx.handle, m, f.ctypes.data_as(C.c_void_p),
+                             u.ctypes.data_as(C.c_void_p), float(rtol), int(maxit), C.byref(it),
+                             C.byref(rel), tm, _stream(stream))
+    if check and st != GMG_ENOCONV:
+        _check(st)
+    names = ("copy_in", "layout_in", "solve", "layout_out", "copy_out")
+    return it.value, rel.value, dict(zip(names, list(tm))), st

@@ -155,6 +155,7 @@ int gmg_destroy(gmg_ctx* c) {
   dfree(c->dz64); dfree(c->dz32);
   dfree(c->vr); dfree(c->vz); dfree(c->vp); dfree(c->vq); dfree(c->vt);
   dfree(c->er32); dfree(c->eu32);
+  dfree(c->hz); dfree(c->hf); dfree(c->hu);
   dfree(c->partials);
   dfree(c->state);
   dfree(c->dhist);
@@ -816,6 +817,106 @@ int gmg_timing_read(gmg_ctx* c, int kernel, int level, int prec, int64_t* count,
   if (count) *count = n;
   if (total_ms) *total_ms = ms;
   return GMG_OK;
+}
+
+int gmg_transpose_in(gmg_ctx* c, int level, int prec, const void* src_z, void* dst_x,
+                     void* stream) {
+  if (!level_ok(c, level)) return fail(GMG_EINVAL, "bad context or level %d", level);
+  int st;
+  if ((st = check_prec(prec)) || (st = check_ptrs({src_z, dst_x}))) return st;
+  if (src_z == dst_x) return fail(GMG_EINVAL, "transpose: src and dst must differ");
+  const LevelBuf& B = c->lev[level];
+  hipStream_t s = as_stream(stream);
+  HIP_TRY(prec == GMG_F64
+              ? gmg::launch_transpose<double>((const double*)src_z, (double*)dst_x, B.nx, B.ny,
+                                              B.nz, B.ldx, true, s)
+              : gmg::launch_transpose<float>((const float*)src_z, (float*)dst_x, B.nx, B.ny,
+                                             B.nz, B.ldx, true, s));
+  return GMG_OK;
+}
+
+int gmg_transpose_out(gmg_ctx* c, int level, int prec, const void* src_x, void* dst_z,
+                      void* stream) {
+  if (!level_ok(c, level)) return fail(GMG_EINVAL, "bad context or level %d", level);
+  int st;
+  if ((st = check_prec(prec)) || (st = check_ptrs({src_x, dst_z}))) return st;
+  if (src_x == dst_z) return fail(GMG_EINVAL, "transpose: src and dst must differ");
+  const LevelBuf& B = c->lev[level];
+  hipStream_t s = as_stream(stream);
+  HIP_TRY(prec == GMG_F64
+              ? gmg::launch_transpose<double>((const double*)src_x, (double*)dst_z, B.nx, B.ny,
+                                              B.nz, B.ldx, false, s)
+              : gmg::launch_transpose<float>((const float*)src_x, (float*)dst_z, B.nx, B.ny,
+                                             B.nz, B.ldx, false, s));
+  return GMG_OK;
+}
+
+int gmg_solve_host(gmg_ctx* c, int method, const double* f_host, double* u_host, double rtol,
+                   int maxit, int* iters, double* relres, double* timings_ms, void* stream) {
+  if (!c || c->batch) return fail(GMG_EINVAL, "context is NULL or batched");
+  if (!f_host || !u_host) return fail(GMG_EINVAL, "NULL host array");
+  if (method < 0 || method > 2) return fail(GMG_EINVAL, "method must be 0, 1 or 2");
+  const LevelBuf& B = c->lev[0];
+  const size_t ncan = (size_t)B.nx * B.ny * B.nz;
+  const size_t bytes = ncan * sizeof(double);
+  if (!c->hz) {
+    hipError_t e;
+    if ((e = dmalloc(&c->hz, (int64_t)ncan)) || (e = dmalloc(&c->hf, B.elems)) ||
+        (e = dmalloc(&c->hu, B.elems))) {
+      dfree(c->hz); dfree(c->hf); dfree(c->hu);
+      c->hz = c->hf = c->hu = nullptr;
+      return fail(GMG_ENOMEM, "host-solve buffers: %s", hipGetErrorString(e));
+    }
+  }
+  hipStream_t s = as_stream(stream);
+  // events between the steps: copy f in | layout f | copy u in | layout u |
+  // solve | layout u out | copy u out
+  hipEvent_t ev[8] = {};
+  for (hipEvent_t& e : ev) HIP_TRY(hipEventCreate(&e));
+  auto done = [&](int code) {
+    for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+    return code;
+  };
+  auto step = [&](hipError_t e, const char* what) {
+    return e == hipSuccess ? GMG_OK : hip_fail(e, what);
+  };
+  int st;
+  if ((st = step(hipEventRecord(ev[0], s), "event")) ||
+      (st = step(hipMemcpyAsync(c->hz, f_host, bytes, hipMemcpyHostToDevice, s), "copy f in")) ||
+      (st = step(hipEventRecord(ev[1], s), "event")) ||
+      (st = step(gmg::launch_transpose<double>(c->hz, c->hf, B.nx, B.ny, B.nz, B.ldx, true, s),
+                 "layout f in")) ||
+      (st = step(hipEventRecord(ev[2], s), "event")) ||
+      (st = step(hipMemcpyAsync(c->hz, u_host, bytes, hipMemcpyHostToDevice, s), "copy u in")) ||
+      (st = step(hipEventRecord(ev[3], s), "event")) ||
+      (st = step(gmg::launch_transpose<double>(c->hz, c->hu, B.nx, B.ny, B.nz, B.ldx, true, s),
+                 "layout u in")) ||
+      (st = step(hipEventRecord(ev[4], s), "event")))
+    return done(st);
+  const int solve_st =
+      method == 0 ? gmg_solve(c, c->hf, c->hu, rtol, maxit, iters, relres, nullptr, stream)
+                  : pcg_solve(c, c->hf, c->hu, rtol, maxit, method == 2 ? 1 : 0, iters, relres,
+                              nullptr, stream);
+  if (solve_st != GMG_OK && solve_st != GMG_ENOCONV) return done(solve_st);
+  if ((st = step(hipEventRecord(ev[5], s), "event")) ||
+      (st = step(gmg::launch_transpose<double>(c->hu, c->hz, B.nx, B.ny, B.nz, B.ldx, false, s),
+                 "layout u out")) ||
+      (st = step(hipEventRecord(ev[6], s), "event")) ||
+      (st = step(hipMemcpyAsync(u_host, c->hz, bytes, hipMemcpyDeviceToHost, s), "copy u out")) ||
+      (st = step(hipEventRecord(ev[7], s), "event")) ||
+      (st = step(hipStreamSynchronize(s), "sync")))
+    return done(st);
+  if (timings_ms) {
+    float ms[7] = {};
+    for (int q = 0; q < 7; ++q)
+      if ((st = step(hipEventElapsedTime(&ms[q], ev[q], ev[q + 1]), "elapsed"))) return done(st);
+    timings_ms[0] = (double)ms[0] + ms[2];  // host -> device copies
+    timings_ms[1] = (double)ms[1] + ms[3];  // layout conversions in
+    timings_ms[2] = ms[4];                  // solve
+    timings_ms[3] = ms[5];                  // layout conversion out
+    timings_ms[4] = ms[6];                  // device -> host copy
+  }
+  return done(solve_st);
 }
 
 int gmg_set_launch(gmg_ctx* c, int kernel, int level, int prec, int rows, int group) {

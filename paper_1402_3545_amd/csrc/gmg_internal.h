@@ -146,6 +146,9 @@ struct gmg_ctx {
   double* dhist = nullptr;           // device history buffer
   int dhist_len = 0;
   double* hscal = nullptr;           // pinned host scalars
+  // gmg_solve_host: z-contiguous staging and x-contiguous f, u (FP64, level
+  // 0), allocated on first use
+  double *hz = nullptr, *hf = nullptr, *hu = nullptr;
 };
 
 namespace gmg {
@@ -230,6 +233,10 @@ hipError_t launch_fcg_fin(int which, CgState* st, const double* partials, int64_
 
 template <typename T>
 hipError_t launch_fill(T* p, int64_t n, T v, hipStream_t s);
+// canonical z-contiguous (j*nx+i)*nz+k <-> x-contiguous (j*nz+k)*ldx+i
+template <typename T>
+hipError_t launch_transpose(const T* src, T* dst, int nx, int ny, int nz, int64_t ldx,
+                            bool to_x, hipStream_t s);
 hipError_t launch_add_f32_to_f64(double* u, const float* e, int64_t n, hipStream_t s);
 
 // grouped launches (batched solves)
