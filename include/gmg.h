@@ -239,8 +239,11 @@ int gmg_solve_host(gmg_ctx *c, int method, const double *f_host, double *u_host,
  *   rows  - grid rows per workgroup of the stencil kernels (SpMV, residual,
  *           fused residual+restriction, prolongation, CG direction kernel,
  *           refinement update, flexible-CG kernels): 4, 8 or 16 wavefronts
- *           of 64 columns.  Line kernels always use 4 wavefronts of 32
- *           columns; their rows value is stored but not used.
+ *           of 64 columns.  Line kernels use 4 wavefronts of 32 columns (the
+ *           twisted elimination, rows = 4); the line solve and the smoother
+ *           (GMG_K_LINE_SOLVE, GMG_K_SMOOTH) also take rows = 1: one
+ *           wavefront per column, solved by parallel cyclic reduction
+ *           (n_z <= 128), for levels with too few columns to fill the GPU.
  *   group - tile columns per dispatch group: tiles are walked group by group
  *           and tile rows follow each other inside a group, so that a tile's
  *           neighbours run close in time and share an XCD's L2; 0 walks the
@@ -249,9 +252,10 @@ int gmg_solve_host(gmg_ctx *c, int method, const double *f_host, double *u_host,
  * the FP64 reductions (norms and dot products).
  * gmg_set_launch / gmg_get_launch: one entry of the context's table;
  * GMG_EINVAL for a bad kernel id, level or precision, rows not in {4, 8, 16}
- * or group outside [0, 4096], and for batched contexts.
+ * (or 1 for the line solve and smoother), group outside [0, 4096], and for
+ * batched contexts.
  * gmg_autotune: for every level and for the precisions the context's solvers
- * use, runs each candidate shape (rows 4/8/16, group 0/1/2/4/8) of each kernel
+ * use, runs each candidate shape (rows 4/8/16 or 4/1, group 0/1/2/4/8) of each kernel
  * kind `reps` times on the context's own work buffers (their contents are
  * overwritten; caller memory is not touched), times it with HIP events on
  * `stream` and keeps the fastest.  Synchronises `stream`.  reps in [1, 1000]. */

@@ -620,24 +620,34 @@ int fcg_impl(gmg_ctx* c, const double* f, double* u, double rtol, int maxit, int
 }
 
 // ---- autotuner --------------------------------------------------------------
-// Candidate launch shapes: rows per workgroup (stencil kernels only) and tile
-// columns per dispatch group (0 = row-major).
-constexpr int kTuneRows[] = {4, 8, 16};
+// Candidate launch shapes: rows per workgroup and tile columns per dispatch
+// group (0 = row-major).  Stencil kernels: 4, 8 or 16 rows; line kernels: the
+// twisted elimination (4) and, for the line solve and the smoother, one
+// wavefront per column by cyclic reduction (1, tile order irrelevant).
+constexpr int kStencilRows[] = {4, 8, 16};
+constexpr int kLineRows[] = {4};
+constexpr int kLinePcrRows[] = {4, 1};
 constexpr int kTuneGroups[] = {0, 1, 2, 4, 8};
+
+enum class Cand { STENCIL, LINE, LINE_PCR };
 
 // Time `reps` launches of every candidate shape of one kernel kind and store
 // the fastest in the context's table.  `nti` is the kernel's tile count across
 // (groups at or above it are row-major again and are skipped).
 template <typename F>
-int tune_kind(gmg_ctx* c, int kind, int level, int prec, bool stencil, int nti, int reps,
+int tune_kind(gmg_ctx* c, int kind, int level, int prec, Cand cand, int nti, int reps,
               hipStream_t s, hipEvent_t ea, hipEvent_t eb, F&& launch) {
   gmg::Shape best{};
   float best_ms = 0.0f;
   bool have = false;
-  for (int rows : kTuneRows) {
-    if (!stencil && rows != 4) continue;
+  const int* rows_c = cand == Cand::STENCIL ? kStencilRows
+                      : cand == Cand::LINE  ? kLineRows
+                                            : kLinePcrRows;
+  const int nrows = cand == Cand::STENCIL ? 3 : cand == Cand::LINE ? 1 : 2;
+  for (int q0 = 0; q0 < nrows; ++q0) {
+    const int rows = rows_c[q0];
     for (int group : kTuneGroups) {
-      if (group >= nti) continue;
+      if (group >= nti || (rows == 1 && group != 0)) continue;
       const gmg::Shape sh{rows, group};
       HIP_TRY(launch(sh));  // warm-up
       HIP_TRY(hipEventRecord(ea, s));
@@ -686,21 +696,21 @@ int tune_levels(gmg_ctx* c, int reps, hipStream_t s, hipEvent_t ea, hipEvent_t e
     const int nts = (int)gmg::stencil_tiles_x(V.nx), ntl = (int)gmg::line_tiles_x(V.nx);
     int64_t nb = 0;
     int st;
-    if ((st = tune_kind(c, GMG_K_SPMV, d, P, true, nts, reps, s, ea, eb, [&](Shape sh) {
+    if ((st = tune_kind(c, GMG_K_SPMV, d, P, Cand::STENCIL, nts, reps, s, ea, eb, [&](Shape sh) {
            return gmg::launch_stencil<T>(V, Stencil::SPMV, x0, nullptr, x1, nullptr, nullptr,
                                          nullptr, s, sh);
          })))
       return st;
-    if ((st = tune_kind(c, GMG_K_RESIDUAL, d, P, true, nts, reps, s, ea, eb, [&](Shape sh) {
+    if ((st = tune_kind(c, GMG_K_RESIDUAL, d, P, Cand::STENCIL, nts, reps, s, ea, eb, [&](Shape sh) {
            return gmg::launch_stencil<T>(V, Stencil::RESIDUAL_NORM, x0, x2, x1, nullptr,
                                          c->partials, &nb, s, sh);
          })))
       return st;
-    if ((st = tune_kind(c, GMG_K_LINE_SOLVE, d, P, false, ntl, reps, s, ea, eb, [&](Shape sh) {
+    if ((st = tune_kind(c, GMG_K_LINE_SOLVE, d, P, Cand::LINE_PCR, ntl, reps, s, ea, eb, [&](Shape sh) {
            return gmg::launch_line_solve_scaled<T>(V, x2, x1, rho, s, sh);
          })))
       return st;
-    if ((st = tune_kind(c, GMG_K_SMOOTH, d, P, false, ntl, reps, s, ea, eb, [&](Shape sh) {
+    if ((st = tune_kind(c, GMG_K_SMOOTH, d, P, Cand::LINE_PCR, ntl, reps, s, ea, eb, [&](Shape sh) {
            return gmg::launch_smooth<T>(V, x2, x0, x1, rho, s, sh);
          })))
       return st;
@@ -708,13 +718,13 @@ int tune_levels(gmg_ctx* c, int reps, hipStream_t s, hipEvent_t ea, hipEvent_t e
       const Lvl<T> C = gmg::view<T>(c, d + 1);
       T* fc = static_cast<T*>(c->lev[d + 1].f);
       T* uc = static_cast<T*>(c->lev[d + 1].u);
-      if ((st = tune_kind(c, GMG_K_RESIDUAL_RESTRICT, d, P, true,
+      if ((st = tune_kind(c, GMG_K_RESIDUAL_RESTRICT, d, P, Cand::STENCIL,
                           (int)gmg::stencil_tiles_x(C.nx), reps, s, ea, eb, [&](Shape sh) {
                             return gmg::launch_resrestrict<T>(V, C, x0, x2, fc, s, sh);
                           })))
         return st;
       // prolongation from level d+1 onto level d, kept under the coarse level
-      if ((st = tune_kind(c, GMG_K_PROLONGATE, d + 1, P, true, nts, reps, s, ea, eb,
+      if ((st = tune_kind(c, GMG_K_PROLONGATE, d + 1, P, Cand::STENCIL, nts, reps, s, ea, eb,
                           [&](Shape sh) {
                             return gmg::launch_prolongate<T>(C, V, uc, x1, s, sh);
                           })))
@@ -740,33 +750,33 @@ int tune_solver(gmg_ctx* c, int reps, hipStream_t s, hipEvent_t ea, hipEvent_t e
   HIP_TRY(hipMemcpyAsync(c->state, &idle, sizeof(idle), hipMemcpyHostToDevice, s));
   int64_t nb = 0;
   int st;
-  if ((st = tune_kind(c, GMG_K_CG_SPMV, 0, GMG_F64, true, nts, reps, s, ea, eb, [&](Shape sh) {
+  if ((st = tune_kind(c, GMG_K_CG_SPMV, 0, GMG_F64, Cand::STENCIL, nts, reps, s, ea, eb, [&](Shape sh) {
          return gmg::launch_cg_p1(V, c->vt, c->vp, c->vz, c->vq, c->state, c->partials, &nb, s,
                                   sh);
        })))
     return st;
-  if ((st = tune_kind(c, GMG_K_CG_TRIDIAG, 0, GMG_F64, false, ntl, reps, s, ea, eb,
+  if ((st = tune_kind(c, GMG_K_CG_TRIDIAG, 0, GMG_F64, Cand::LINE, ntl, reps, s, ea, eb,
                       [&](Shape sh) {
                         return gmg::launch_cg_p2(V, c->vr, c->vq, c->vz, c->state, 0,
                                                  c->partials, &nb, s, sh);
                       })))
     return st;
   if (mixed) {
-    if ((st = tune_kind(c, GMG_K_RESIDUAL, 0, GMG_F64, true, nts, reps, s, ea, eb,
+    if ((st = tune_kind(c, GMG_K_RESIDUAL, 0, GMG_F64, Cand::STENCIL, nts, reps, s, ea, eb,
                         [&](Shape sh) {
                           return gmg::launch_stencil<double>(V, Stencil::RESIDUAL_NORM_DOWN,
                                                              c->vt, c->vr, c->vz, c->er32,
                                                              c->partials, &nb, s, sh);
                         })))
       return st;
-    if ((st = tune_kind(c, GMG_K_CORRECT, 0, GMG_F64, true, nts, reps, s, ea, eb,
+    if ((st = tune_kind(c, GMG_K_CORRECT, 0, GMG_F64, Cand::STENCIL, nts, reps, s, ea, eb,
                         [&](Shape sh) {
                           return gmg::launch_correct_residual(V, c->vt, c->eu32, c->vr, c->vz,
                                                               c->er32, c->partials, &nb, s, sh);
                         })))
       return st;
   }
-  if ((st = tune_kind(c, GMG_K_FCG, 0, GMG_F64, true, nts, reps, s, ea, eb, [&](Shape sh) {
+  if ((st = tune_kind(c, GMG_K_FCG, 0, GMG_F64, Cand::STENCIL, nts, reps, s, ea, eb, [&](Shape sh) {
          hipError_t e = mixed ? gmg::launch_fcg_dir<float>(V, c->eu32, c->vp, c->vq, c->vr,
                                                             c->state, c->partials, &nb, s, sh)
                               : gmg::launch_fcg_dir<double>(V, c->vz, c->vp, c->vq, c->vr,
@@ -925,8 +935,10 @@ int gmg_set_launch(gmg_ctx* c, int kernel, int level, int prec, int rows, int gr
   if (level < 0 || level >= c->nlevels) return fail(GMG_EINVAL, "bad level %d", level);
   int st;
   if ((st = check_prec(prec))) return st;
-  if (rows != 4 && rows != 8 && rows != 16)
-    return fail(GMG_EINVAL, "rows must be 4, 8 or 16 (got %d)", rows);
+  const bool pcr_ok = kernel == GMG_K_LINE_SOLVE || kernel == GMG_K_SMOOTH;
+  if (!(rows == 4 || rows == 8 || rows == 16 || (rows == 1 && pcr_ok)))
+    return fail(GMG_EINVAL, "rows must be 4, 8 or 16 (1 for the line solve and smoother), got %d",
+                rows);
   if (group < 0 || group > 4096) return fail(GMG_EINVAL, "group must be in [0, 4096]");
   c->shape[gmg::tslot(kernel, level, prec)] = gmg::Shape{rows, group};
   return GMG_OK;

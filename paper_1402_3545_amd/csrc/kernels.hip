@@ -712,6 +712,130 @@ __global__ __launch_bounds__(NTHREADS) void k_line(Lvl<T> L, LineArgs<T> a, int 
 }
 
 // ---------------------------------------------------------------------------
+// Line solve and smoother by parallel cyclic reduction, one wavefront per
+// column, for levels with too few columns to fill the GPU (horizontal-only
+// coarsening keeps n_z on every level, so the coarse levels have long columns
+// but few of them).  Lane l holds rows 2l and 2l+1 of the column, padded to
+// 128 rows with identity rows; each reduction step at distance d eliminates
+// the couplings to rows i -+ d with the equations of those rows, so after
+// seven steps (d = 1, 2, ..., 64) every equation stands alone and x = y / b.
+// All loads of a lane are issued at once: one memory round trip instead of
+// the 2 x 64 dependent steps of the twisted elimination.  The arithmetic is
+// Gaussian elimination in the cyclic-reduction order, stable for these
+// diagonally dominant columns.
+// ---------------------------------------------------------------------------
+template <typename T>
+struct PcrRow {
+  T a, b, c, y;
+};
+
+template <typename T>
+__device__ __forceinline__ PcrRow<T> pcr_fetch(const PcrRow<T>& r, int src, bool valid) {
+  PcrRow<T> o;
+  o.a = __shfl(r.a, src);
+  o.b = __shfl(r.b, src);
+  o.c = __shfl(r.c, src);
+  o.y = __shfl(r.y, src);
+  if (!valid) o = PcrRow<T>{T(0), T(1), T(0), T(0)};
+  return o;
+}
+
+template <typename T>
+__device__ __forceinline__ PcrRow<T> pcr_step(const PcrRow<T>& r, const PcrRow<T>& m,
+                                             const PcrRow<T>& p) {
+  const T k1 = r.a * rcp_nr(m.b), k2 = r.c * rcp_nr(p.b);
+  PcrRow<T> o;
+  o.a = -k1 * m.a;
+  o.c = -k2 * p.c;
+  o.b = r.b - k1 * m.c - k2 * p.a;
+  o.y = r.y - k1 * m.y - k2 * p.y;
+  return o;
+}
+
+template <typename T, int MODE>  // LINE_SOLVE or LINE_SMOOTH
+__global__ __launch_bounds__(NTHREADS) void k_line_pcr(Lvl<T> L, LineArgs<T> a, int ncols) {
+  constexpr int NR = 128;
+  __shared__ T s_sub[NR], s_sup[NR], s_dg[NR], s_dz[NR];
+  const int nz = L.nz;
+  for (int k = threadIdx.x; k < NR; k += blockDim.x) {
+    const bool real = k < nz;
+    s_sub[k] = real ? L.sub[k] : T(0);
+    s_sup[k] = real ? L.sup[k] : T(0);
+    s_dg[k] = real ? L.dg[k] : T(1);
+    s_dz[k] = real ? L.dz[k] : T(0);
+  }
+  __syncthreads();
+  const int col = blockIdx.x * (NTHREADS / 64) + __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  if (col >= ncols) return;  // wave-uniform; no barrier follows
+  const int i = col % L.nx, j = col / L.nx;
+  const int lane = threadIdx.x & 63;
+  const Col<T> c = load_col(L, i, j);
+  const int64_t ldx = L.ldx;
+  const T wmu = (T(1) - a.rho) / a.rho;  // smoother: weight of M u
+  PcrRow<T> row[2];
+  int kr[2];
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int k = 2 * lane + h;
+    kr[h] = k;
+    const bool real = k < nz;
+    const int kc = min(k, nz - 1);
+    const int64_t o = c.base + (int64_t)kc * ldx;
+    PcrRow<T>& r = row[h];
+    r.a = s_sub[k];
+    r.c = s_sup[k];
+    r.b = s_dg[k] + s_dz[k] * c.S;
+    if constexpr (MODE == LINE_SOLVE) {
+      r.y = real ? __builtin_nontemporal_load(a.a + o) : T(0);
+    } else {
+      const T* u = a.a;
+      const T um = kc > 0 ? u[o - ldx] : T(0);
+      const T up = kc + 1 < nz ? u[o + ldx] : T(0);
+      const T uc = u[o];
+      const T h4 = c.ce * u[o + c.oe] + c.cw * u[o + c.ow] + c.cn * u[o + c.on] +
+                   c.cs * u[o + c.os];
+      const T mu = r.b * uc + r.a * um + r.c * up;
+      const T g = __builtin_nontemporal_load(a.b + o) + s_dz[k] * h4;
+      r.y = real ? g + wmu * mu : T(0);
+    }
+    if (!real) r = PcrRow<T>{T(0), T(1), T(0), T(0)};
+  }
+  // d = 1: row 2l couples to 2l-1 (lane l-1, second row) and 2l+1 (own
+  // second row); row 2l+1 to 2l (own first row) and 2l+2 (lane l+1, first row)
+  {
+    const PcrRow<T> m0 = pcr_fetch(row[1], lane - 1 < 0 ? 0 : lane - 1, lane > 0);
+    const PcrRow<T> p1 = pcr_fetch(row[0], lane + 1 > 63 ? 63 : lane + 1, lane < 63);
+    const PcrRow<T> r0 = pcr_step(row[0], m0, row[1]);
+    const PcrRow<T> r1 = pcr_step(row[1], row[0], p1);
+    row[0] = r0;
+    row[1] = r1;
+  }
+  // d = 2e: rows 2l -+ 2e live in lanes l -+ e, same slot
+#pragma unroll
+  for (int e = 1; e < 64; e <<= 1) {
+    const int lm = lane - e, lp = lane + e;
+    const bool vm = lm >= 0, vp = lp < 64;
+    const int sm = vm ? lm : lane, sp = vp ? lp : lane;
+    PcrRow<T> nw[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const PcrRow<T> m = pcr_fetch(row[h], sm, vm);
+      const PcrRow<T> p = pcr_fetch(row[h], sp, vp);
+      nw[h] = pcr_step(row[h], m, p);
+    }
+    row[0] = nw[0];
+    row[1] = nw[1];
+  }
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    if (kr[h] < nz) {
+      const T x = row[h].y / row[h].b;
+      __builtin_nontemporal_store(a.rho * x, a.o0 + c.base + (int64_t)kr[h] * ldx);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Residual fused with the restriction: f_c(I,J,k) = sum over the four fine
 // children (2I+a, 2J+b) of (f - A u).  One thread per coarse column; the fine
 // residual itself is never stored.  A wavefront covers 64 coarse = 128 fine
@@ -1577,7 +1701,17 @@ inline int grid_stride_blocks(int64_t n) {
 }
 
 template <typename T, int MODE>
-hipError_t line_dispatch(const Lvl<T>& L, const LineArgs<T>& a, hipStream_t s, int group) {
+hipError_t line_dispatch(const Lvl<T>& L, const LineArgs<T>& a, hipStream_t s, int group,
+                         int rows = 4) {
+  if constexpr (MODE == LINE_SOLVE || MODE == LINE_SMOOTH) {
+    // one wavefront per column (parallel cyclic reduction) when asked for
+    if (rows == 1 && L.nz <= 128) {
+      const int ncols = L.nx * L.ny;
+      hipLaunchKernelGGL((k_line_pcr<T, MODE>), dim3(cdiv(ncols, NTHREADS / 64)),
+                         dim3(NTHREADS), 0, s, L, a, ncols);
+      return hipGetLastError();
+    }
+  }
   const int nti = cdiv(L.nx, 32), ntj = cdiv(L.ny, LROWS);
   const dim3 grid(nti * ntj), block(NTHREADS);
   const int half = (L.nz + 1) / 2;
@@ -1717,7 +1851,7 @@ hipError_t launch_line_solve(const Lvl<T>& L, const T* r, T* z, hipStream_t s, S
   a.a = r;
   a.o0 = z;
   a.rho = T(1);
-  return line_dispatch<T, LINE_SOLVE>(L, a, s, sh.group);
+  return line_dispatch<T, LINE_SOLVE>(L, a, s, sh.group, sh.rows);
 }
 
 template <typename T>
@@ -1728,7 +1862,7 @@ hipError_t launch_smooth(const Lvl<T>& L, const T* f, const T* uin, T* uout, T r
   a.b = f;
   a.o0 = uout;
   a.rho = rho;
-  return line_dispatch<T, LINE_SMOOTH>(L, a, s, sh.group);
+  return line_dispatch<T, LINE_SMOOTH>(L, a, s, sh.group, sh.rows);
 }
 
 template <typename T>
@@ -1750,7 +1884,7 @@ hipError_t launch_line_solve_scaled(const Lvl<T>& L, const T* r, T* z, T scale, 
   a.a = r;
   a.o0 = z;
   a.rho = scale;
-  return line_dispatch<T, LINE_SOLVE>(L, a, s, sh.group);
+  return line_dispatch<T, LINE_SOLVE>(L, a, s, sh.group, sh.rows);
 }
 
 template <typename T>

@@ -195,3 +195,32 @@ def test_invalid_arguments_raise():
         G.gmg_restrict_smooth(ctx, 0, x, x, x)    # level 0 is not coarse
     with pytest.raises(G.GmgError):
         G.gmg_solve(ctx, x, x)                    # f and u overlap
+
+
+def _pcr_everywhere(G, ctx):
+    for lvl in range(ctx.nlevels):
+        for prec in (G.GMG_F64, G.GMG_F32):
+            G.gmg_set_launch(ctx, "line_solve", lvl, prec, 1, 0)
+            G.gmg_set_launch(ctx, "smooth", lvl, prec, 1, 0)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("shape", SHAPES)
+def test_line_kernels_by_cyclic_reduction(shape, prec):
+    """One wavefront per column, parallel cyclic reduction (the coarse-level
+    launch shape): same bars against the oracle as the twisted elimination."""
+    import paper_1402_3545_amd as G
+    nx, ny, nz = shape
+    ctx, orc, _ = problem(nx, ny, nz, kv=1e4, seed=6)
+    _pcr_everywhere(G, ctx)
+    r, f = _inputs(nx * ny * nz, 13, prec)
+    rd = ctx.to_device(r, dtype=_dtype(prec))
+    zd = ctx.empty(dtype=_dtype(prec))
+    G.line_solve(ctx, 0, rd, zd)
+    ref = orc.line_solve(r)
+    bar = F64 if prec == 0 else f32_line_bar(nz)
+    assert max_rel(ctx.from_device(zd), ref, np.abs(ref).max()) < bar
+    ud, fd = ctx.to_device(r, dtype=_dtype(prec)), ctx.to_device(f, dtype=_dtype(prec))
+    G.line_smooth(ctx, 0, fd, ud, nsweeps=2)
+    sref = orc.smooth(f, orc.smooth(f, r))
+    assert max_rel(ctx.from_device(ud), sref, np.abs(sref).max()) < 2 * bar

@@ -171,3 +171,21 @@ def test_flexible_cg_with_multigrid_preconditioner(prec_precond):
     assert true_rel == pytest.approx(rel, rel=1e-6)
     u_ref, _, _, _ = orc.mg_solve(f, rtol=1e-12, maxit=100)
     assert np.linalg.norm(u - u_ref) / np.linalg.norm(u_ref) < 1e-6
+
+
+def test_mg_with_cyclic_reduction_on_coarse_levels():
+    """The V-cycle with the coarse-level line kernels switched to one
+    wavefront per column follows the oracle's history."""
+    import paper_1402_3545_amd as G
+    w = W.SMALL
+    ctx, orc, _ = problem(w.nx, w.ny, w.nz, nlevels=w.nlevels, kv=w.kv, seed=w.seed,
+                          kh_model=w.kh_model)
+    for lvl in range(1, ctx.nlevels):
+        G.gmg_set_launch(ctx, "line_solve", lvl, G.GMG_F64, 1, 0)
+        G.gmg_set_launch(ctx, "smooth", lvl, G.GMG_F64, 1, 0)
+    f = w.rhs()
+    fd, ud = ctx.to_device(f), ctx.empty()
+    it, rel, hist, st = G.gmg_solve(ctx, fd, ud, rtol=w.rtol, maxit=50)
+    u_ref, it_ref, hist_ref, st_ref = orc.mg_solve(f, rtol=w.rtol, maxit=50)
+    assert st == 0 and it == it_ref
+    assert np.allclose(hist, hist_ref[:len(hist)], rtol=1e-10, atol=0)

@@ -72,7 +72,7 @@ def test_autotune_then_solve_matches_oracle(prec_precond):
     it0, rel0, _, st0 = G.gmg_solve(ctx, fd, ud0, rtol=1e-10, maxit=60)
     G.gmg_autotune(ctx, reps=2)
     table = G.launch_table(ctx)
-    assert all(r in (4, 8, 16) and 0 <= g <= 8 for r, g in table.values())
+    assert all(r in (1, 4, 8, 16) and 0 <= g <= 8 for r, g in table.values())
     ud = ctx.empty()
     it, rel, _, st = G.gmg_solve(ctx, fd, ud, rtol=1e-10, maxit=60)
     assert st == st0 == 0 and it == it0
@@ -93,8 +93,11 @@ def test_launch_shape_validation():
     ctx, _, _ = problem(16, 16, 8, nlevels=2)
     G.gmg_set_launch(ctx, "spmv", 1, G.GMG_F32, 16, 3)
     assert G.gmg_get_launch(ctx, "spmv", 1, G.GMG_F32) == (16, 3)
+    G.gmg_set_launch(ctx, "line_solve", 0, G.GMG_F64, 1, 0)     # cyclic reduction
+    assert G.gmg_get_launch(ctx, "line_solve", 0, G.GMG_F64) == (1, 0)
     for bad in [("spmv", 2, 0, 4, 0), ("spmv", 0, 2, 4, 0), ("spmv", 0, 0, 5, 0),
-                ("spmv", 0, 0, 4, -1), ("spmv", 0, 0, 4, 5000), (99, 0, 0, 4, 0)]:
+                ("spmv", 0, 0, 4, -1), ("spmv", 0, 0, 4, 5000), (99, 0, 0, 4, 0),
+                ("spmv", 0, 0, 1, 0), ("cg_tridiag", 0, 0, 1, 0)]:
         with pytest.raises(G.GmgError):
             G.gmg_set_launch(ctx, *bad)
     with pytest.raises(G.GmgError):
