@@ -48,6 +48,7 @@ def _load():
     lib.or_csr.argtypes = [C.c_void_p, C.c_int, C.POINTER(C.c_int64), C.POINTER(C.c_int32), _D]
     lib.or_profiles.argtypes = [C.c_void_p, _D, _D]
     lib.or_faces.argtypes = [C.c_void_p, C.c_int, _D, _D, _D]
+    lib.or_walls.argtypes = [C.c_void_p, C.c_int, _D]
     for name in ("or_spmv", "or_line_solve"):
         getattr(lib, name).argtypes = [C.c_void_p, C.c_int, _D, _D]
     lib.or_residual.argtypes = [C.c_void_p, C.c_int, _D, _D, _D]
@@ -78,10 +79,11 @@ class OracleProblem:
     """The discrete operator hierarchy, assembled as CSR on the host."""
 
     def __init__(self, nx, ny, nz, nlevels=1, kv=1.0, sigma=1.0, zfaces=None, kh=None,
-                 bc_v=0, rho=2.0 / 3.0, ncoarse=2, matfree=False):
+                 bc_v=0, rho=2.0 / 3.0, ncoarse=2, matfree=False, bc_h=0):
         lib = _load()
         self.nx, self.ny, self.nz, self.nlevels = int(nx), int(ny), int(nz), int(nlevels)
         self.rho = float(rho)
+        self.bc_h, self.bc_v = int(bc_h), int(bc_v)
         zf = None if zfaces is None else np.ascontiguousarray(zfaces, dtype=np.float64)
         kk = None if kh is None else np.ascontiguousarray(kh, dtype=np.float64)
         if zf is not None and zf.size != nz + 1:
@@ -89,7 +91,7 @@ class OracleProblem:
         if kk is not None and kk.size != nx * ny:
             raise ValueError("kh needs nx*ny entries")
         create = lib.or_create_matfree if matfree else lib.or_create
-        h = create(nx, ny, nz, nlevels, 0, bc_v, float(kv), float(sigma),
+        h = create(nx, ny, nz, nlevels, int(bc_h), bc_v, float(kv), float(sigma),
                           _p(zf) if zf is not None else None,
                           _p(kk) if kk is not None else None, float(rho), int(ncoarse))
         if not h:
@@ -143,6 +145,12 @@ class OracleProblem:
         kc, cx, cy = (np.zeros(nx * ny) for _ in range(3))
         self._chk(_lib.or_faces(self._h, depth, _p(kc), _p(cx), _p(cy)))
         return kc, cx, cy
+
+    def walls(self, depth=0):
+        nx, ny, _ = self.shape(depth)
+        w = np.zeros(nx * ny)
+        self._chk(_lib.or_walls(self._h, depth, _p(w)))
+        return w
 
     def _vec(self, x, depth):
         x = np.ascontiguousarray(x, dtype=np.float64)

@@ -27,6 +27,11 @@
  * a = sigma dz, d = dz, alpha_TT' = -C_TT', alpha_T = sum alpha_TT',
  * b_k = -t_k, c_k = -t_{k+1}.  On a uniform grid with constant K, dividing a
  * row by the cell volume gives the flat-box stencil of Sec. 2.1.1.
+ *
+ * Horizontal boundaries: doubly periodic, or the homogeneous Dirichlet walls
+ * of Sec. 2.1.1.  At a wall the sum over T' includes the wall itself as a
+ * neighbour with value 0 and coupling 2 K_T times the face ratio (the wall is
+ * half a cell away), and no face crosses the domain edge.
  */
 #include "oracle.h"
 
@@ -44,6 +49,8 @@ typedef struct {
   double *K;   /* per-column coefficient, j*nx+i */
   double *cx;  /* coupling of face (i+1/2, j): columns (i,j) and (i+1 mod nx, j) */
   double *cy;  /* coupling of face (i, j+1/2): columns (i,j) and (i, j+1 mod ny) */
+  int bch;     /* 0 doubly periodic, 1 homogeneous Dirichlet at the four walls */
+  double *wall; /* per column: couplings of its wall faces (Dirichlet only) */
   int64_t n;   /* rows */
   int64_t nnz;
   int64_t *rowptr;
@@ -114,17 +121,31 @@ static void build_profiles(or_problem *p) {
 }
 
 /* Face couplings of one level from its per-column K: harmonic mean per face,
- * computed once per face so that A is exactly symmetric. */
+ * computed once per face so that A is exactly symmetric.  With Dirichlet
+ * walls (the paper's horizontal boundary condition, Sec. 2.1.1) the faces
+ * across the domain edge do not exist; a wall face lies half a cell from the
+ * column centre and couples the column to the zero boundary value with
+ * 2 K_T (face length over half the spacing), which only enters the diagonal. */
 static void build_faces(level_t *L) {
   int nx = L->nx, ny = L->ny;
   double fx = L->hy / L->hx, fy = L->hx / L->hy;
   for (int j = 0; j < ny; ++j)
     for (int i = 0; i < nx; ++i) {
-      double kc = L->K[(int64_t)j * nx + i];
+      int64_t c = (int64_t)j * nx + i;
+      double kc = L->K[c];
       double ke = L->K[(int64_t)j * nx + wrap(i + 1, nx)];
       double kn = L->K[(int64_t)wrap(j + 1, ny) * nx + i];
-      L->cx[(int64_t)j * nx + i] = fx * 2.0 * kc * ke / (kc + ke);
-      L->cy[(int64_t)j * nx + i] = fy * 2.0 * kc * kn / (kc + kn);
+      L->cx[c] = fx * 2.0 * kc * ke / (kc + ke);
+      L->cy[c] = fy * 2.0 * kc * kn / (kc + kn);
+      L->wall[c] = 0.0;
+      if (L->bch) {
+        if (i == nx - 1) L->cx[c] = 0.0;
+        if (j == ny - 1) L->cy[c] = 0.0;
+        if (i == 0) L->wall[c] += fx * 2.0 * kc;
+        if (i == nx - 1) L->wall[c] += fx * 2.0 * kc;
+        if (j == 0) L->wall[c] += fy * 2.0 * kc;
+        if (j == ny - 1) L->wall[c] += fy * 2.0 * kc;
+      }
     }
 }
 
@@ -166,16 +187,19 @@ static int assemble_row(const or_problem *p, const level_t *L, int i, int j, int
   int js = wrap(j - 1, ny), jn = wrap(j + 1, ny);
   double ce = L->cx[(int64_t)j * nx + i], cw = L->cx[(int64_t)j * nx + iw];
   double cn = L->cy[(int64_t)j * nx + i], cs = L->cy[(int64_t)js * nx + i];
-  /* diagonal: zero-order term, both vertical faces, the four horizontal faces */
+  double wall = L->wall[(int64_t)j * nx + i];
+  /* diagonal: zero-order term, both vertical faces, the four horizontal faces
+   * (wall faces included) */
   double diag = L->area * (p->sigma * dz[k] + tf[k] + tf[k + 1]) +
-                dz[k] * (ce + cw + cn + cs);
+                dz[k] * (ce + cw + cn + cs + wall);
   n = row_add(cols, vals, n, (int32_t)g, diag);
   if (k > 0) n = row_add(cols, vals, n, (int32_t)(g - 1), -L->area * tf[k]);
   if (k < nz - 1) n = row_add(cols, vals, n, (int32_t)(g + 1), -L->area * tf[k + 1]);
-  n = row_add(cols, vals, n, (int32_t)gidx(L, ie, j, k), -dz[k] * ce);
-  n = row_add(cols, vals, n, (int32_t)gidx(L, iw, j, k), -dz[k] * cw);
-  n = row_add(cols, vals, n, (int32_t)gidx(L, i, jn, k), -dz[k] * cn);
-  n = row_add(cols, vals, n, (int32_t)gidx(L, i, js, k), -dz[k] * cs);
+  /* faces across a Dirichlet wall have zero coupling and no entry */
+  if (ce != 0.0) n = row_add(cols, vals, n, (int32_t)gidx(L, ie, j, k), -dz[k] * ce);
+  if (cw != 0.0) n = row_add(cols, vals, n, (int32_t)gidx(L, iw, j, k), -dz[k] * cw);
+  if (cn != 0.0) n = row_add(cols, vals, n, (int32_t)gidx(L, i, jn, k), -dz[k] * cn);
+  if (cs != 0.0) n = row_add(cols, vals, n, (int32_t)gidx(L, i, js, k), -dz[k] * cs);
   row_sort(cols, vals, n);
   return n;
 }
@@ -218,7 +242,7 @@ void or_destroy(or_problem *p) {
   if (p->lev)
     for (int d = 0; d < p->nlevels; ++d) {
       level_t *L = &p->lev[d];
-      free(L->K); free(L->cx); free(L->cy);
+      free(L->K); free(L->cx); free(L->cy); free(L->wall);
       free(L->rowptr); free(L->col); free(L->val);
       free(L->u); free(L->f); free(L->r); free(L->t);
     }
@@ -235,7 +259,7 @@ static or_problem *create(int nx, int ny, int nz, int nlevels, int bc_h, int bc_
     set_err("need nx, ny, nz >= 2 and nlevels >= 1");
     return NULL;
   }
-  if (bc_h != 0) { set_err("only doubly periodic horizontal boundaries"); return NULL; }
+  if (bc_h != 0 && bc_h != 1) { set_err("bc_h must be 0 or 1"); return NULL; }
   if (bc_v != 0 && bc_v != 1) { set_err("bc_v must be 0 or 1"); return NULL; }
   if (!(sigma > 0.0) || !(kv >= 0.0)) { set_err("need sigma > 0, kv >= 0"); return NULL; }
   if (ncoarse < 1) { set_err("ncoarse >= 1"); return NULL; }
@@ -274,6 +298,8 @@ static or_problem *create(int nx, int ny, int nz, int nlevels, int bc_h, int bc_
     L->K = (double *)xcalloc((size_t)nc, sizeof(double));
     L->cx = (double *)xcalloc((size_t)nc, sizeof(double));
     L->cy = (double *)xcalloc((size_t)nc, sizeof(double));
+    L->wall = (double *)xcalloc((size_t)nc, sizeof(double));
+    L->bch = bc_h;
     if (d == 0) {
       for (int64_t c = 0; c < nc; ++c) {
         L->K[c] = kh ? kh[c] : 1.0;
@@ -389,6 +415,13 @@ int or_faces(const or_problem *p, int d, double *kcol, double *cx, double *cy) {
   memcpy(kcol, L->K, nc * sizeof(double));
   memcpy(cx, L->cx, nc * sizeof(double));
   memcpy(cy, L->cy, nc * sizeof(double));
+  return 0;
+}
+
+int or_walls(const or_problem *p, int d, double *wall) {
+  if (bad_depth(p, d)) return -1;
+  const level_t *L = &p->lev[d];
+  memcpy(wall, L->wall, (size_t)L->nx * L->ny * sizeof(double));
   return 0;
 }
 
@@ -525,18 +558,28 @@ int or_restrict(const or_problem *p, int dfine, const double *rf, double *fc) {
 /* Prolongation: cell-centred bilinear interpolation in the horizontal only
  * (Sec. 2.2, "(piecewise) linear").  Fine child (2I+a, 2J+b) takes weights
  * 9/16, 3/16, 3/16, 1/16 from its coarse parent, the parent's neighbour on
- * its side in x, in y, and the diagonal one; periodic wrap. */
+ * its side in x, in y, and the diagonal one; periodic wrap.  Behind a
+ * Dirichlet wall the missing coarse cell is the mirror image of the parent
+ * with opposite sign (the linear interpolant that vanishes on the wall). */
 static void prolongate_add(const level_t *C, const level_t *F, const double *uc, double *uf) {
   int nz = F->nz;
 #pragma omp parallel for schedule(static)
   for (int64_t fc = 0; fc < (int64_t)F->nx * F->ny; ++fc) {
     int i = (int)(fc % F->nx), j = (int)(fc / F->nx);
     int I = i / 2, J = j / 2;
-    int I2 = wrap(I + ((i & 1) ? 1 : -1), C->nx);
-    int J2 = wrap(J + ((j & 1) ? 1 : -1), C->ny);
+    int I2 = I + ((i & 1) ? 1 : -1);
+    int J2 = J + ((j & 1) ? 1 : -1);
+    double sx = 1.0, sy = 1.0;
+    if (C->bch) {
+      if (I2 < 0 || I2 >= C->nx) { I2 = I; sx = -1.0; }
+      if (J2 < 0 || J2 >= C->ny) { J2 = J; sy = -1.0; }
+    } else {
+      I2 = wrap(I2, C->nx);
+      J2 = wrap(J2, C->ny);
+    }
     for (int k = 0; k < nz; ++k) {
-      double v = 9.0 * uc[gidx(C, I, J, k)] + 3.0 * uc[gidx(C, I2, J, k)] +
-                 3.0 * uc[gidx(C, I, J2, k)] + uc[gidx(C, I2, J2, k)];
+      double v = 9.0 * uc[gidx(C, I, J, k)] + 3.0 * sx * uc[gidx(C, I2, J, k)] +
+                 3.0 * sy * uc[gidx(C, I, J2, k)] + sx * sy * uc[gidx(C, I2, J2, k)];
       uf[gidx(F, i, j, k)] += v / 16.0;
     }
   }

@@ -23,7 +23,8 @@ extern "C" {
 
 typedef struct or_problem or_problem;
 
-/* Build the hierarchy.  bc_h: 0 = doubly periodic (only value supported).
+/* Build the hierarchy.  bc_h: 0 = doubly periodic, 1 = homogeneous Dirichlet
+ * on the four side walls (wall faces couple with 2 K_T to a zero value).
  * bc_v: 0 = Dirichlet top/bottom, 1 = Neumann.  zfaces: nz+1 increasing faces
  * in [0,1] (NULL = (k/nz)^2).  kh: nx*ny per-column coefficients in order
  * j*nx+i (NULL = 1).  Returns NULL on invalid input; or_last_error() says why. */
@@ -43,6 +44,9 @@ int64_t or_nnz(const or_problem *p, int depth);
 int or_csr(const or_problem *p, int depth, int64_t *rowptr, int32_t *col, double *val);
 int or_profiles(const or_problem *p, double *dz, double *tface);
 int or_faces(const or_problem *p, int depth, double *kcol, double *cx, double *cy);
+/* per column (j*nx+i): the summed couplings of its Dirichlet wall faces
+ * (all zero for periodic boundaries) */
+int or_walls(const or_problem *p, int depth, double *wall);
 
 /* Single operations (the plain definitions). */
 int or_spmv(const or_problem *p, int depth, const double *x, double *y);
