@@ -63,13 +63,13 @@ SOLVES = ("mg_f64", "pcg_f64", "mg_mixed", "fcg_mixed")
 MEASURED_TRAFFIC = {
     # k_cg_p1, 64x16 workgroups, tile groups of 8 (the stored launch shape);
     # profiles/cg_p1_1024x1024x128_pmc.md.  Plain-copy calibration: 2 GiB read
-    # + 2 GiB written read FETCH_SIZE 898801.4 KiB, WRITE_SIZE 2097246.4 KiB.
+    # + 2 GiB written read FETCH_SIZE 898804.5 KiB, WRITE_SIZE 2097240.6 KiB.
     ("cg_spmv", 0, "f64"): {
-        "fetch_kib": 2306393.098,
-        "write_kib": 3145863.483,
-        "copy_fetch_scale": 2097152.0 / 898801.4375,
-        "copy_write_scale": 2097152.0 / 2097246.4107,
-        "source_sha256": "939e39884e5dc7457656e65a52de49ff5c3b10fea48f35aff53fe900c3b528a9",
+        "fetch_kib": 2326968.019,
+        "write_kib": 3145864.422,
+        "copy_fetch_scale": 2097152.0 / 898804.5179,
+        "copy_write_scale": 2097152.0 / 2097240.5893,
+        "source_sha256": "3f5f5aa0cc575e7447ce05dbaafcb01b04523eed27a8af626b9944839cb0e60f",
         "shape": [16, 8],
     },
 }

@@ -66,11 +66,14 @@ typedef enum {
 typedef enum { GMG_F64 = 0, GMG_F32 = 1 } gmg_prec;
 
 typedef struct {
-  int32_t nx, ny, nz;     /* finest grid; nx, ny divisible by 2^(nlevels-1),
-                             >= 2 columns per direction on the coarsest level;
-                             2 <= nz <= 128 */
+  int32_t nx, ny, nz;     /* finest grid; nx, ny >= 2 and divisible by
+                             2^(nlevels-1) (the coarsest level may be a single
+                             column per direction); 2 <= nz <= 128 */
   int32_t nlevels;        /* >= 1 */
-  int32_t bc_h;           /* 0 = doubly periodic (the only value supported) */
+  int32_t bc_h;           /* 0 = doubly periodic; 1 = homogeneous Dirichlet on the
+                             four side walls (Sec. 2.1.1): a wall face couples the
+                             outermost column to zero with 2 K times the face
+                             ratio, and prolongation reflects oddly at walls */
   int32_t bc_v;           /* 0 = Dirichlet top and bottom, 1 = Neumann */
   double kv;              /* vertical coefficient K_v >= 0 */
   double sigma;           /* zero-order coefficient > 0 */

@@ -264,8 +264,8 @@ static or_problem *create(int nx, int ny, int nz, int nlevels, int bc_h, int bc_
   if (!(sigma > 0.0) || !(kv >= 0.0)) { set_err("need sigma > 0, kv >= 0"); return NULL; }
   if (ncoarse < 1) { set_err("ncoarse >= 1"); return NULL; }
   int div = 1 << (nlevels - 1);
-  if (nx % div || ny % div || nx / div < 2 || ny / div < 2) {
-    set_err("nx, ny must be divisible by 2^(nlevels-1) with >= 2 coarsest columns");
+  if (nx % div || ny % div) {
+    set_err("nx, ny must be divisible by 2^(nlevels-1)");
     return NULL;
   }
   if ((int64_t)nx * ny * nz > INT32_MAX) {

@@ -70,12 +70,10 @@ int validate(const gmg_params* p) {
   if (p->nz < 2) return fail(GMG_EINVAL, "nz must be >= 2");
   if (p->nz > 128) return fail(GMG_EUNSUPPORTED, "nz > 128 is not supported (nz = %d)", p->nz);
   const int64_t div = int64_t(1) << (p->nlevels - 1);
-  if (p->nx % div || p->ny % div || p->nx / div < 2 || p->ny / div < 2)
-    return fail(GMG_EINVAL,
-                "nx=%d, ny=%d must be divisible by 2^(nlevels-1)=%lld with >= 2 coarsest columns",
-                p->nx, p->ny, (long long)div);
-  if (p->bc_h != 0)
-    return fail(GMG_EUNSUPPORTED, "only doubly periodic horizontal boundaries (bc_h = 0)");
+  if (p->nx % div || p->ny % div)
+    return fail(GMG_EINVAL, "nx=%d, ny=%d must be divisible by 2^(nlevels-1)=%lld", p->nx,
+                p->ny, (long long)div);
+  if (p->bc_h != 0 && p->bc_h != 1) return fail(GMG_EINVAL, "bc_h must be 0 or 1");
   if (p->bc_v != 0 && p->bc_v != 1) return fail(GMG_EINVAL, "bc_v must be 0 or 1");
   if (!(p->kv >= 0.0) || !isfinite(p->kv)) return fail(GMG_EINVAL, "kv must be finite, >= 0");
   if (!(p->sigma > 0.0) || !isfinite(p->sigma)) return fail(GMG_EINVAL, "sigma must be > 0");
@@ -116,13 +114,15 @@ int validate_params(const gmg_params* p) { return validate(p); }
 template <>
 Lvl<double> view<double>(const gmg_ctx* c, int d) {
   const LevelBuf& L = c->lev[d];
-  return Lvl<double>{L.nx, L.ny, L.nz, L.ldx, L.cx64, L.cy64, L.sub64, L.sup64, L.dg64, c->dz64};
+  return Lvl<double>{L.nx,    L.ny,    L.nz,  L.ldx,    L.cx64,    L.cy64,
+                     L.sub64, L.sup64, L.dg64, c->dz64, L.wall64, c->p.bc_h};
 }
 
 template <>
 Lvl<float> view<float>(const gmg_ctx* c, int d) {
   const LevelBuf& L = c->lev[d];
-  return Lvl<float>{L.nx, L.ny, L.nz, L.ldx, L.cx32, L.cy32, L.sub32, L.sup32, L.dg32, c->dz32};
+  return Lvl<float>{L.nx,    L.ny,    L.nz,  L.ldx,    L.cx32,    L.cy32,
+                    L.sub32, L.sup32, L.dg32, c->dz32, L.wall32, c->p.bc_h};
 }
 
 }  // namespace gmg
@@ -148,6 +148,7 @@ int gmg_destroy(gmg_ctx* c) {
   for (LevelBuf& L : c->lev) {
     dfree(L.cx64); dfree(L.cy64); dfree(L.sub64); dfree(L.sup64); dfree(L.dg64);
     dfree(L.cx32); dfree(L.cy32); dfree(L.sub32); dfree(L.sup32); dfree(L.dg32);
+    dfree(L.wall64); dfree(L.wall32);
     if (L.u) (void)hipFree(L.u);
     if (L.ualt) (void)hipFree(L.ualt);
     if (L.f) (void)hipFree(L.f);
@@ -233,14 +234,31 @@ int gmg::setup_impl(const gmg_params* p, void* stream, gmg_ctx** out, bool field
         }
       K.swap(Kc);
     }
-    std::vector<double> cx(K.size()), cy(K.size());
+    // Dirichlet side walls (Sec. 2.1.1): no face crosses the domain edge (the
+    // wrap-around couplings are zero, so the kernels' periodic neighbour reads
+    // contribute nothing), and each wall face, half a cell from the column
+    // centre, couples the column to the zero wall value with 2 K times the
+    // face ratio -- a diagonal-only term kept per column.
+    const bool walls = p->bc_h == 1;
+    std::vector<double> cx(K.size()), cy(K.size()), wall(K.size(), 0.0);
     for (int j = 0; j < L.ny; ++j)
       for (int i = 0; i < L.nx; ++i) {
-        const double kc = K[(size_t)j * L.nx + i];
+        const size_t q = (size_t)j * L.nx + i;
+        const double kc = K[q];
         const double ke = K[(size_t)j * L.nx + (i + 1) % L.nx];
         const double kn = K[(size_t)((j + 1) % L.ny) * L.nx + i];
-        cx[(size_t)j * L.nx + i] = (hy / hx) * 2.0 * kc * ke / (kc + ke);
-        cy[(size_t)j * L.nx + i] = (hx / hy) * 2.0 * kc * kn / (kc + kn);
+        cx[q] = (walls && i == L.nx - 1) ? 0.0 : (hy / hx) * 2.0 * kc * ke / (kc + ke);
+        cy[q] = (walls && j == L.ny - 1) ? 0.0 : (hx / hy) * 2.0 * kc * kn / (kc + kn);
+        // a periodic level one column wide is its own neighbour: the flux
+        // through those faces vanishes identically, and leaving the coupling
+        // in would move a self term out of the column block M into A - M,
+        // which changes the line smoother
+        if (L.nx == 1) cx[q] = 0.0;
+        if (L.ny == 1) cy[q] = 0.0;
+        if (walls) {
+          const int nwx = (i == 0) + (i == L.nx - 1), nwy = (j == 0) + (j == L.ny - 1);
+          wall[q] = nwx * (hy / hx) * 2.0 * kc + nwy * (hx / hy) * 2.0 * kc;
+        }
       }
     std::vector<double> sub(nz), sup(nz), dg(nz);
     for (int k = 0; k < nz; ++k) {
@@ -251,7 +269,8 @@ int gmg::setup_impl(const gmg_params* p, void* stream, gmg_ctx** out, bool field
     if ((st = upload(&L.cx64, cx)) || (st = upload(&L.cy64, cy)) || (st = upload(&L.sub64, sub)) ||
         (st = upload(&L.sup64, sup)) || (st = upload(&L.dg64, dg)) || (st = upload(&L.cx32, cx)) ||
         (st = upload(&L.cy32, cy)) || (st = upload(&L.sub32, sub)) ||
-        (st = upload(&L.sup32, sup)) || (st = upload(&L.dg32, dg)))
+        (st = upload(&L.sup32, sup)) || (st = upload(&L.dg32, dg)) ||
+        (st = upload(&L.wall64, wall)) || (st = upload(&L.wall32, wall)))
       return cleanup(st);
     const size_t bytes = (size_t)L.elems * c->esize;
     hipError_t e = hipSuccess;

@@ -30,6 +30,10 @@ struct Lvl {
   const T* __restrict__ sup;
   const T* __restrict__ dg;
   const T* __restrict__ dz;
+  // per column (j*nx + i): summed couplings of the column's Dirichlet wall
+  // faces, added to the diagonal (all zero with periodic boundaries)
+  const T* __restrict__ wall;
+  int bch;  // 0 doubly periodic, 1 Dirichlet side walls (prolongation reflects)
 };
 
 // Scalars shared between the kernels of one CG solve; lives in device memory
@@ -79,9 +83,9 @@ struct LevelBuf {
   int64_t ldx, elems;
   double area;
   double *cx64 = nullptr, *cy64 = nullptr, *sub64 = nullptr, *sup64 = nullptr,
-         *dg64 = nullptr;
+         *dg64 = nullptr, *wall64 = nullptr;
   float *cx32 = nullptr, *cy32 = nullptr, *sub32 = nullptr, *sup32 = nullptr,
-        *dg32 = nullptr;
+        *dg32 = nullptr, *wall32 = nullptr;
   // V-cycle work fields in the context's precond precision (bytes per
   // element = esize): u, ualt (ping-pong partner), f.  Level 0 uses the
   // caller's f and u, so only ualt is allocated there.  (The residual is

@@ -61,7 +61,7 @@ __device__ __forceinline__ Col<T> load_col(const Lvl<T>& L, int i, int j) {
   c.cw = L.cx[row + iw];
   c.cn = L.cy[row + i];
   c.cs = L.cy[(int64_t)js * nx + i];
-  c.S = c.ce + c.cw + c.cn + c.cs;
+  c.S = c.ce + c.cw + c.cn + c.cs + L.wall[row + i];
   const int64_t jstride = (int64_t)L.nz * L.ldx;
   c.base = (int64_t)j * jstride + i;
   c.oe = ie - i;
@@ -190,7 +190,7 @@ __device__ __forceinline__ Cf<T> col_coef(const Lvl<T>& L, const Geo& g) {
   c.cw = L.cx[row + g.iw];
   c.cn = L.cy[row + g.ic];
   c.cs = L.cy[(int64_t)g.js * L.nx + g.ic];
-  c.S = c.ce + c.cw + c.cn + c.cs;
+  c.S = c.ce + c.cw + c.cn + c.cs + L.wall[row + g.ic];
   return c;
 }
 
@@ -939,10 +939,10 @@ __device__ __forceinline__ void resrestrict_body(const Lvl<T>& F, const Lvl<T>& 
     P.ydN = F.cy[r1c + i0 + 1];
     P.ySa = F.cy[rs + i0];
     P.ySb = F.cy[rs + i0 + 1];
-    P.Sa = P.xab + P.xWa + P.yac + P.ySa;
-    P.Sb = P.xbE + P.xab + P.ybd + P.ySb;
-    P.Sc = P.xcd + P.xWc + P.ycN + P.yac;
-    P.Sd = P.xdE + P.xcd + P.ydN + P.ybd;
+    P.Sa = P.xab + P.xWa + P.yac + P.ySa + F.wall[r0 + i0];
+    P.Sb = P.xbE + P.xab + P.ybd + P.ySb + F.wall[r0 + i0 + 1];
+    P.Sc = P.xcd + P.xWc + P.ycN + P.yac + F.wall[r1c + i0];
+    P.Sd = P.xdE + P.xcd + P.ydN + P.ybd + F.wall[r1c + i0 + 1];
     P.ra = rowc(u, j0, jst);
     P.rc = rowc(u, j0 + 1, jst);
     P.rS = rowc(u, js, jst);
@@ -1111,6 +1111,7 @@ struct ProlongPol {
   char* rf;
   uint32_t oI, oI2, of, ckb, fkb;
   int nz, k0;
+  T wb, wc, wd;  // weights of the x, y and diagonal neighbours (3, 3, 1 inside)
 
   __device__ __forceinline__ void load(int s, In& v) {
     const int k = k0 + s;
@@ -1122,14 +1123,16 @@ struct ProlongPol {
     v.u = ldn<T>(rf, of + layer_off<FULL>(k, nz, fkb));
   }
   __device__ __forceinline__ void step(int s, const In& v) {
-    const T p = T(9) * v.a + T(3) * v.b + T(3) * v.c + v.d;
+    const T p = T(9) * v.a + wb * v.b + wc * v.c + wd * v.d;
     sto<T>(rf, of + layer_off<FULL>(k0 + s, nz, fkb), v.u + p * T(0.0625));
   }
 };
 
 // One lane per fine column (i, j); its coarse parent (I, J) = (i/2, j/2) and
-// the coarse neighbours on the child's side, I2 = I -+ 1, J2 = J -+ 1
-// (periodic), weighted 9/3/3/1 over 16.
+// the coarse neighbours on the child's side, I2 = I -+ 1, J2 = J -+ 1, weighted
+// 9/3/3/1 over 16.  Periodic boundaries wrap; behind a Dirichlet wall the
+// neighbour is the parent's mirror image with opposite sign (the linear
+// interpolant that vanishes on the wall).
 template <typename T, int SR>
 __device__ __forceinline__ void prolongate_body(const Lvl<T>& C, const Lvl<T>& F,
                                                 const T* __restrict__ uc, T* __restrict__ uf,
@@ -1139,8 +1142,23 @@ __device__ __forceinline__ void prolongate_body(const Lvl<T>& C, const Lvl<T>& F
   const int I = g.ic >> 1, J = g.j >> 1;
   int I2 = I + ((g.ic & 1) ? 1 : -1);
   int J2 = J + ((g.j & 1) ? 1 : -1);
-  I2 = (I2 < 0) ? C.nx - 1 : (I2 == C.nx ? 0 : I2);
-  J2 = (J2 < 0) ? C.ny - 1 : (J2 == C.ny ? 0 : J2);
+  T sx = T(1), sy = T(1);
+  if (I2 < 0 || I2 == C.nx) {
+    if (C.bch) {
+      I2 = I;
+      sx = T(-1);
+    } else {
+      I2 = (I2 < 0) ? C.nx - 1 : 0;
+    }
+  }
+  if (J2 < 0 || J2 == C.ny) {
+    if (C.bch) {
+      J2 = J;
+      sy = T(-1);
+    } else {
+      J2 = (J2 < 0) ? C.ny - 1 : 0;
+    }
+  }
   const uint32_t ES = sizeof(T);
   auto run = [&](auto full) {
     constexpr bool FL = decltype(full)::value;
@@ -1156,6 +1174,9 @@ __device__ __forceinline__ void prolongate_body(const Lvl<T>& C, const Lvl<T>& F
     P.fkb = (uint32_t)F.ldx * ES;
     P.nz = F.nz;
     P.k0 = g.k0;
+    P.wb = T(3) * sx;
+    P.wc = T(3) * sy;
+    P.wd = sx * sy;
     walk<4, FL>(P, g.n);
   };
   if (g.n == KSEG)

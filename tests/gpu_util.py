@@ -11,7 +11,7 @@ import workloads as W
 
 
 def problem(nx, ny, nz, nlevels=1, kv=1e3, seed=3, kh_model="uniform", bc_v=0, ncoarse=2,
-            prec_precond=0, matfree=False):
+            prec_precond=0, matfree=False, bc_h=0, kscale=1.0, zfaces=None):
     """(library context, oracle problem, kh) for one operator."""
     import paper_1402_3545_amd as G
     if kh_model == "uniform":
@@ -20,11 +20,12 @@ def problem(nx, ny, nz, nlevels=1, kv=1e3, seed=3, kh_model="uniform", bc_v=0, n
         kh = W.kh_lognormal(seed, nx, ny)
     else:
         kh = W.kh_constant(nx, ny)
-    zf = W.quadratic_faces(nz)
+    kh = kh * kscale
+    zf = W.quadratic_faces(nz) if zfaces is None else zfaces
     ctx = G.GmgContext(nx, ny, nz, nlevels, kv=kv, sigma=1.0, zfaces=zf, kh=kh, bc_v=bc_v,
-                       ncoarse=ncoarse, prec_precond=prec_precond)
+                       ncoarse=ncoarse, prec_precond=prec_precond, bc_h=bc_h)
     orc = oracle.OracleProblem(nx, ny, nz, nlevels, kv=kv, sigma=1.0, zfaces=zf, kh=kh,
-                               bc_v=bc_v, ncoarse=ncoarse, matfree=matfree)
+                               bc_v=bc_v, ncoarse=ncoarse, matfree=matfree, bc_h=bc_h)
     return ctx, orc, kh
 
 

@@ -1,0 +1,247 @@
+"""Parity with the oracle for the homogeneous Dirichlet side walls of
+Sec. 2.1.1 (bc_h = 1): every kernel, the V-cycle, the solvers and the batched
+solver, on the same bars as the periodic tests (FP64 1e-12 relative to the
+summed terms, FP32 stencils 2e-6, FP32 line kernels 4e-7 n_z), plus the
+paper's own regime: Neumann top and bottom, equidistant layers and
+K = (nu_CFL h / 2)^2 with nu_CFL = 8.4."""
+
+import numpy as np
+import pytest
+
+import workloads as W
+from tests.gpu_util import abs_matvec, max_rel, problem
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+SHAPES = [(4, 4, 8), (40, 6, 37), (64, 64, 64), (96, 32, 2), (34, 10, 128)]
+MULTI = [((8, 8, 4), 2), ((40, 24, 37), 3), ((64, 64, 64), 4), ((32, 96, 128), 2)]
+F64 = 1e-12
+F32_STENCIL = 2e-6
+
+
+def f32_line_bar(nz):
+    return max(2e-6, 4e-7 * nz)
+
+
+@pytest.fixture(autouse=True, scope="module")
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("needs a GPU")
+
+
+def _dtype(prec):
+    return torch.float64 if prec == 0 else torch.float32
+
+
+def _inputs(n, seed, prec):
+    x = W.uniform_pm1(seed, 1, n)
+    f = W.uniform_pm1(seed, 2, n)
+    if prec == 1:
+        x = x.astype(np.float32).astype(np.float64)
+        f = f.astype(np.float32).astype(np.float64)
+    return x, f
+
+
+@pytest.mark.parametrize("bc_v", [0, 1])
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("shape", SHAPES)
+def test_stencil_kernels_with_walls(shape, prec, bc_v):
+    import paper_1402_3545_amd as G
+    nx, ny, nz = shape
+    ctx, orc, _ = problem(nx, ny, nz, seed=51, bc_h=1, bc_v=bc_v)
+    u, f = _inputs(nx * ny * nz, 52, prec)
+    ud, fd = ctx.to_device(u, dtype=_dtype(prec)), ctx.to_device(f, dtype=_dtype(prec))
+    yd = ctx.empty(dtype=_dtype(prec))
+    bar = F64 if prec == 0 else F32_STENCIL
+    G.spmv(ctx, 0, ud, yd)
+    assert max_rel(ctx.from_device(yd), orc.spmv(u), abs_matvec(orc, u)) < bar
+    nrm2 = G.gmg_residual(ctx, 0, fd, ud, yd, norm=True)
+    got = ctx.from_device(yd)
+    assert max_rel(got, orc.residual(f, u), abs_matvec(orc, u) + np.abs(f)) < bar
+    assert nrm2 == pytest.approx(float(got @ got), rel=1e-12 if prec == 0 else 1e-6)
+
+
+@pytest.mark.parametrize("pcr", [False, True])
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("shape", SHAPES)
+def test_line_kernels_with_walls(shape, prec, pcr):
+    """The wall term sits on the diagonal of the column systems: line solve and
+    two smoothing sweeps, twisted elimination and cyclic reduction."""
+    import paper_1402_3545_amd as G
+    nx, ny, nz = shape
+    ctx, orc, _ = problem(nx, ny, nz, kv=1e3, seed=53, bc_h=1)
+    if pcr:
+        for p in (G.GMG_F64, G.GMG_F32):
+            G.gmg_set_launch(ctx, "line_solve", 0, p, 1, 0)
+            G.gmg_set_launch(ctx, "smooth", 0, p, 1, 0)
+    r, f = _inputs(nx * ny * nz, 54, prec)
+    bar = F64 if prec == 0 else f32_line_bar(nz)
+    rd, zd = ctx.to_device(r, dtype=_dtype(prec)), ctx.empty(dtype=_dtype(prec))
+    G.line_solve(ctx, 0, rd, zd)
+    ref = orc.line_solve(r)
+    assert max_rel(ctx.from_device(zd), ref, np.abs(ref).max()) < bar
+    ud, fd = ctx.to_device(r, dtype=_dtype(prec)), ctx.to_device(f, dtype=_dtype(prec))
+    G.line_smooth(ctx, 0, fd, ud, nsweeps=2)
+    sref = orc.smooth(f, orc.smooth(f, r))
+    assert max_rel(ctx.from_device(ud), sref, np.abs(sref).max()) < 2 * bar
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("shape,L", MULTI)
+def test_transfers_with_walls(shape, L, prec):
+    """Restriction with the coarse smoothing step, and the prolongation that
+    reflects oddly at the walls, on every level."""
+    import paper_1402_3545_amd as G
+    nx, ny, nz = shape
+    ctx, orc, _ = problem(nx, ny, nz, nlevels=L, seed=55, bc_h=1)
+    for lvl in range(1, L):
+        rf, _ = _inputs(orc.size(lvl - 1), 56 + lvl, prec)
+        rfd = ctx.to_device(rf, lvl - 1, dtype=_dtype(prec))
+        fcd, ucd = ctx.empty(lvl, dtype=_dtype(prec)), ctx.empty(lvl, dtype=_dtype(prec))
+        G.gmg_restrict_smooth(ctx, lvl, rfd, fcd, ucd)
+        fc_ref, uc_ref = orc.restrict_smooth(rf, lvl)
+        bar = F64 if prec == 0 else f32_line_bar(nz)
+        assert max_rel(ctx.from_device(fcd, lvl), fc_ref, np.abs(fc_ref).max()) < bar
+        assert max_rel(ctx.from_device(ucd, lvl), uc_ref, np.abs(uc_ref).max()) < bar
+        uc, _ = _inputs(orc.size(lvl), 60 + lvl, prec)
+        uf, _ = _inputs(orc.size(lvl - 1), 70 + lvl, prec)
+        ucd = ctx.to_device(uc, lvl, dtype=_dtype(prec))
+        ufd = ctx.to_device(uf, lvl - 1, dtype=_dtype(prec))
+        G.gmg_prolongate(ctx, lvl, ucd, ufd)
+        ref = orc.prolongate_add(uc, uf, lvl)
+        bar = F64 if prec == 0 else F32_STENCIL
+        assert max_rel(ctx.from_device(ufd, lvl - 1), ref, np.abs(ref).max()) < bar
+
+
+VC = [((8, 8, 4), 2, 2), ((40, 24, 37), 3, 2), ((64, 64, 64), 4, 3), ((32, 64, 128), 5, 2)]
+
+
+@pytest.mark.parametrize("bc_v", [0, 1])
+@pytest.mark.parametrize("shape,L,nc", VC)
+def test_vcycle_with_walls(shape, L, nc, bc_v):
+    """The V-cycle (fused residual-restriction included) as one linear map."""
+    import paper_1402_3545_amd as G
+    nx, ny, nz = shape
+    ctx, orc, _ = problem(nx, ny, nz, nlevels=L, ncoarse=nc, seed=57, bc_h=1, bc_v=bc_v)
+    n = nx * ny * nz
+    f, u = W.uniform_pm1(57, 1, n), W.uniform_pm1(57, 2, n)
+    fd, ud = ctx.to_device(f), ctx.to_device(u)
+    G.gmg_vcycle(ctx, fd, ud)
+    ref = orc.vcycle(f, u)
+    assert max_rel(ctx.from_device(ud), ref, np.abs(ref).max()) < 1e-11
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("bc_h", [0, 1])
+@pytest.mark.parametrize("shape,L", [((8, 8, 4), 4), ((16, 8, 8), 4), ((2, 2, 128), 2)])
+def test_vcycle_down_to_one_column(shape, L, bc_h, prec):
+    """Coarsest levels of a single column in one or both directions (the
+    paper's deepest hierarchies end there): every kernel sees its own column as
+    the periodic neighbour, or four walls."""
+    import paper_1402_3545_amd as G
+    nx, ny, nz = shape
+    ctx, orc, _ = problem(nx, ny, nz, nlevels=L, seed=61, bc_h=bc_h, prec_precond=prec)
+    n = nx * ny * nz
+    f, u = W.uniform_pm1(61, 1, n), W.uniform_pm1(61, 2, n)
+    if prec == 1:
+        f = f.astype(np.float32).astype(np.float64)
+        u = u.astype(np.float32).astype(np.float64)
+    fd, ud = ctx.to_device(f, dtype=_dtype(prec)), ctx.to_device(u, dtype=_dtype(prec))
+    G.gmg_vcycle(ctx, fd, ud)
+    ref = orc.vcycle(f, u)
+    assert max_rel(ctx.from_device(ud), ref, np.abs(ref).max()) < (1e-11 if prec == 0 else 1e-4)
+
+
+def _paper_regime(n=64, nz=32, L=4, prec_precond=0, nu=8.4):
+    """Flat box of the paper: Dirichlet walls, Neumann top and bottom,
+    equidistant layers, K = (nu h / 2)^2 times a per-column factor in [0.5, 2],
+    K_v large against K (thin atmosphere)."""
+    K = (0.5 * nu / n) ** 2
+    return problem(n, n, nz, nlevels=L, kv=K * 1e4, seed=58, bc_h=1, bc_v=1,
+                   kscale=K, zfaces=W.uniform_faces(nz), prec_precond=prec_precond)
+
+
+def test_mg_with_walls_follows_oracle_history():
+    import paper_1402_3545_amd as G
+    ctx, orc, _ = _paper_regime()
+    f = W.rhs(58, 0, 64, 64, 32)
+    fd, ud = ctx.to_device(f), ctx.empty()
+    it, rel, hist, st = G.gmg_solve(ctx, fd, ud, rtol=1e-8, maxit=80)
+    u_ref, it_ref, hist_ref, st_ref = orc.mg_solve(f, rtol=1e-8, maxit=80)
+    assert st == 0 and st_ref == 0 and it == it_ref
+    # the stiff vertical coupling (K_v / K = 1e4) puts the rounding floor of a
+    # residual norm near 1e-12 of ||f|| (|A||u| is far larger than |A u|), so
+    # late history entries are compared against that floor
+    assert np.allclose(hist, hist_ref, rtol=1e-10, atol=1e-12)
+    u = ctx.from_device(ud)
+    assert max_rel(u, u_ref, np.abs(u_ref).max()) < 1e-10
+
+
+def test_pcg_with_walls_matches_oracle():
+    import paper_1402_3545_amd as G
+    ctx, orc, _ = _paper_regime()
+    f = W.rhs(59, 0, 64, 64, 32)
+    fd, ud = ctx.to_device(f), ctx.empty()
+    it, rel, hist, st = G.pcg_solve(ctx, fd, ud, rtol=1e-8, maxit=800)
+    _, it_ref, hist_ref, rt_ref, st_ref = orc.pcg_solve(f, rtol=1e-8, maxit=800)
+    assert st == 0 and st_ref == 0 and abs(it - it_ref) <= 1
+    m = min(it, it_ref) + 1
+    assert np.allclose(hist[:m], hist_ref[:m], rtol=1e-6, atol=0)
+    u = ctx.from_device(ud)
+    assert orc.residual_norm2_rows(f, u) ** 0.5 / np.linalg.norm(f) < 1.01e-8
+
+
+@pytest.mark.parametrize("precond", [0, 1])
+def test_mixed_and_flexible_with_walls(precond):
+    """FP32 cycles inside FP64 refinement (precond 0 = plain refinement) or
+    flexible CG: judged by the oracle's FP64 true residual."""
+    import paper_1402_3545_amd as G
+    ctx, orc, _ = _paper_regime(prec_precond=1)
+    f = W.rhs(60, 0, 64, 64, 32)
+    fd, ud = ctx.to_device(f), ctx.empty()
+    if precond == 0:
+        it, rel, hist, st = G.gmg_solve(ctx, fd, ud, rtol=1e-8, maxit=80)
+    else:
+        it, rel, hist, st = G.pcg_solve(ctx, fd, ud, rtol=1e-8, maxit=80, precond=1)
+    assert st == 0
+    u = ctx.from_device(ud)
+    true_rel = orc.residual_norm2_rows(f, u) ** 0.5 / np.linalg.norm(f)
+    assert true_rel < 1e-8 and true_rel == pytest.approx(rel, rel=1e-5)
+
+
+def test_batched_solve_with_walls():
+    import oracle
+    import paper_1402_3545_amd as G
+    shapes = [(32, 8, 3), (48, 16, 3), (64, 32, 4)]
+    kws = []
+    for q, (n, nz, L) in enumerate(shapes):
+        K = (4.2 / n) ** 2
+        kws.append(dict(nx=n, ny=n, nz=nz, nlevels=L, kv=K * 1e4, sigma=1.0,
+                        zfaces=W.uniform_faces(nz), kh=K * W.kh_uniform(5000 + q, n, n),
+                        bc_h=1, bc_v=1))
+    b = G.GmgBatch(kws, nrhs=1)
+    fh = [W.uniform_pm1(5000 + q, 1, kw["nx"] * kw["ny"] * kw["nz"]) for q, kw in enumerate(kws)]
+    fs = [b.to_device(f, q) for q, f in enumerate(fh)]
+    us = [b.empty(q) for q in range(len(kws))]
+    it, rel, st = G.gmg_batch_solve(b, fs, us, rtol=1e-8, maxit=80)
+    assert st == 0, G.gmg_last_error()
+    for q, kw in enumerate(kws):
+        orc = oracle.OracleProblem(kw["nx"], kw["ny"], kw["nz"], kw["nlevels"], kv=kw["kv"],
+                                   sigma=1.0, zfaces=kw["zfaces"], kh=kw["kh"], bc_h=1, bc_v=1,
+                                   matfree=True)
+        u = b.from_device(us[q], q)
+        true_rel = orc.residual_norm2_rows(fh[q], u) ** 0.5 / np.linalg.norm(fh[q])
+        assert true_rel < 1e-8, (q, true_rel)
+        ctx = G.GmgContext(prec_precond=G.GMG_F32, **kw)
+        ud = ctx.empty()
+        it1, _, _, st1 = G.gmg_solve(ctx, ctx.to_device(fh[q]), ud, rtol=1e-8, maxit=80)
+        assert st1 == 0 and it1 == it[q]
+        u1 = ctx.from_device(ud)
+        assert np.abs(u1 - u).max() <= 1e-12 * np.abs(u1).max()
+
+
+def test_bc_h_validation():
+    import paper_1402_3545_amd as G
+    with pytest.raises(G.GmgError):
+        G.GmgContext(8, 8, 4, 1, bc_h=2)

@@ -45,7 +45,7 @@ def _params(**kw):
 
 @pytest.mark.parametrize("kw,status", [
     ({"nz": 1}, -1), ({"nz": 200}, -5), ({"nx": 6, "nlevels": 3}, -1),
-    ({"nx": 4, "nlevels": 3}, -1), ({"bc_h": 1}, -5), ({"bc_v": 2}, -1),
+    ({"nx": 4, "nlevels": 4}, -1), ({"bc_h": 2}, -1), ({"bc_h": -1}, -1), ({"bc_v": 2}, -1),
     ({"sigma": 0.0}, -1), ({"kv": -1.0}, -1), ({"rho": 0.0}, -1), ({"ncoarse": 0}, -1),
     ({"prec_precond": 3}, -1), ({"nlevels": 0}, -1)])
 def test_setup_rejects_invalid_parameters(kw, status):

@@ -124,6 +124,27 @@ def test_flat_box_stencil_on_coarse_levels():
             assert row[idx(i, (j + 1) % cy, k)] == pytest.approx(-Kbar / hy**2, rel=1e-12)
 
 
+def test_single_column_periodic_level_is_the_vertical_operator():
+    """A periodic level of one column is its own neighbour in every direction:
+    the horizontal fluxes vanish and each row is |T| (sigma dz_k + vertical
+    terms), i.e. the flat-box stencil of Sec. 2.1.1 without its horizontal part
+    (here |T| = 1)."""
+    nz, Kv = 5, 2.0
+    p = oracle.OracleProblem(4, 4, nz, 3, kv=Kv, sigma=1.3, zfaces=W.uniform_faces(nz),
+                             kh=W.kh_uniform(2, 4, 4), bc_v=0)
+    assert p.shape(2) == (1, 1, nz)
+    A = _dense(p, 2)
+    hz = 1.0 / nz
+    for k in range(nz):
+        vert = (3 if k in (0, nz - 1) else 2) * Kv / hz**2
+        assert A[k, k] / hz == pytest.approx(1.3 + vert, rel=1e-12)
+        for m in range(nz):
+            if abs(m - k) == 1:
+                assert A[k, m] / hz == pytest.approx(-Kv / hz**2, rel=1e-12)
+            elif m != k:
+                assert A[k, m] == 0.0
+
+
 @pytest.mark.parametrize("shape", [(4, 4, 8), (2, 6, 3), (8, 4, 5), (6, 2, 2)])
 def test_symmetric_m_matrix_and_cholesky(shape):
     nx, ny, nz = shape
@@ -490,6 +511,8 @@ def test_rowwise_forms_equal_csr_forms():
 def test_invalid_inputs_raise():
     with pytest.raises(ValueError):
         oracle.OracleProblem(6, 6, 4, 3)      # 6 not divisible by 4
+    with pytest.raises(ValueError):
+        oracle.OracleProblem(4, 4, 4, 4)      # 4 not divisible by 8
     with pytest.raises(ValueError):
         oracle.OracleProblem(4, 4, 1, 1)      # nz < 2
     with pytest.raises(ValueError):

@@ -84,6 +84,37 @@ def test_flat_box_eigenmodes_with_walls(shape, bc_v):
     assert np.allclose(np.sort(ev), np.sort(lams), rtol=1e-11, atol=0)
 
 
+def _check_flat_box_modes(A, nx, ny, nz, K, Kv, sig, bc_v):
+    hx, hy, hz = 1.0 / nx, 1.0 / ny, 1.0 / nz
+    vol = hx * hy * hz
+    Vx, mx = _sine_modes(nx)
+    Vy, my = _sine_modes(ny)
+    Vz, mz = _sine_modes(nz) if bc_v == 0 else _cosine_modes(nz)
+    scale = np.abs(A).max()
+    for a in range(nx):
+        for b in range(ny):
+            for c in range(nz):
+                v = np.einsum("j,i,k->jik", Vy[:, b], Vx[:, a], Vz[:, c]).reshape(-1)
+                lam = vol * (sig + K * (mx[a] / hx**2 + my[b] / hy**2) + Kv * mz[c] / hz**2)
+                assert np.abs(A @ v - lam * v).max() < 1e-12 * scale * np.abs(v).max()
+
+
+@pytest.mark.parametrize("bc_v", [0, 1])
+def test_coarse_levels_are_flat_boxes_down_to_one_column(bc_v):
+    """With constant K every coarse level is the flat box rediscretised on its
+    own grid (coarse K = mean of the children = K), down to a single column,
+    where each wall lies half a cell away on all four sides (mu = 4 per
+    direction at n = 1)."""
+    nx, ny, nz, L = 8, 4, 3, 3
+    K, Kv, sig = 0.45, 1.3, 0.9
+    p = oracle.OracleProblem(nx, ny, nz, L, kv=Kv, sigma=sig, zfaces=W.uniform_faces(nz),
+                             kh=np.full(nx * ny, K), bc_v=bc_v, bc_h=1)
+    for d in range(L):
+        cx, cy, _ = p.shape(d)
+        _check_flat_box_modes(p.scipy(d).toarray(), cx, cy, nz, K, Kv, sig, bc_v)
+    assert p.shape(L - 1)[:2] == (2, 1)
+
+
 def test_constant_field_flux_through_the_walls():
     """Neumann ends.  For u = 1 every interior face carries no flux; a wall face carries
     K_c (1 - 0) / (h/2) times its area, h_y dz for an x-wall and h_x dz for a
