@@ -156,6 +156,82 @@ def cpu_baseline(w, f, kh, zf):
     }
 
 
+def cfl_sweep(args, torch):
+    """Robustness of the solvers to the horizontal CFL number (Sec. 5.2): the
+    flat box with Dirichlet side walls and Neumann ends on n^2 x nz, for each
+    nu_CFL of the sweep the line-preconditioned CG and FP64 multigrid with 5,
+    7 and 10 levels (coarsest 32^2, 8^2, 1^2 at n = 512), with the paper's
+    coarse smoothing counts and, where those differ from two, also with two.
+    Every solve starts from u = 0, runs to a relative residual of 1e-5 on the
+    resident input, and is timed with HIP events after one untimed solve.
+    Prints one JSON object per solve."""
+    import numpy as np
+
+    import paper_1402_3545_amd as G
+    import workloads as W
+    n, nz = args.cfl_n, args.cfl_nz
+    depth_levels = [L for L in (5, 7, 10) if n % (1 << (L - 1)) == 0]
+    table = None
+    rows = []
+
+    def timed_solve(ctx, fd, ud, fn):
+        ud.zero_()
+        fn()
+        ud.zero_()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        it, rel, _, st = fn()
+        b.record()
+        b.synchronize()
+        return it, rel, st, a.elapsed_time(b)
+
+    for nu in W.CFL_SWEEP:
+        configs = [("pcg_f64", 1, 2)]
+        for L in depth_levels:
+            nc = W.paper_coarse_sweeps(L, nu)
+            configs.append(("mg_f64", L, nc))
+            if nc != 2:
+                configs.append(("mg_f64", L, 2))
+        for solver, L, nc in configs:
+            fb = W.FlatBox(n, nz, nu, L, ncoarse=nc)
+            ctx = G.GmgContext(n, n, nz, L, **fb.params())
+            if table is None:
+                deep = G.GmgContext(n, n, nz, max(depth_levels), **fb.params())
+                table, stored = G.tuned(deep, reps=3)
+                log(f"[cfl] launch shapes: {'stored' if stored else 'autotuned'}")
+                if args.tune_out:
+                    with open(args.tune_out, "w") as fh:
+                        json.dump({G.launch_key(deep): table}, fh, indent=1, sort_keys=True)
+                del deep
+            G.apply_launch_table(ctx, table)
+            fd, ud = ctx.to_device(fb.rhs()), ctx.empty()
+            if solver == "pcg_f64":
+                fn = lambda: G.pcg_solve(ctx, fd, ud, fb.rtol, 50000, check=False)
+            else:
+                fn = lambda: G.gmg_solve(ctx, fd, ud, fb.rtol, 300, check=False)
+            it, rel, st, ms = timed_solve(ctx, fd, ud, fn)
+            rec = {"workload": fb.name, "nu_cfl": nu, "solver": solver, "levels": L,
+                   "coarse_sweeps": nc, "iters": it, "relres": rel, "status": st,
+                   "ms": round(ms, 3), "ms_per_iter": round(ms / max(it, 1), 4)}
+            if nu == 8.4 and L in (1, 5):
+                # the paper's "total solution time" definition at its main CFL
+                # number: from host memory, copies and layout conversion included
+                uh = np.zeros(fb.unknowns)
+                method = "pcg" if solver == "pcg_f64" else "mg"
+                G.gmg_solve_host(ctx, fb.rhs(), uh, method, fb.rtol, 50000)
+                uh[:] = 0.0
+                it_h, _, tm_h, st_h = G.gmg_solve_host(ctx, fb.rhs(), uh, method, fb.rtol, 50000)
+                rec["host_solution"] = {"iters": it_h, "status": st_h,
+                                        "total_ms": round(sum(tm_h.values()), 3),
+                                        **{k + "_ms": round(v, 3) for k, v in tm_h.items()}}
+            rows.append(rec)
+            print(json.dumps(rec), flush=True)
+            log(f"[cfl] nu {nu:g} {solver} L{L} nc{nc}: {it} it, {ms:.1f} ms, status {st}")
+            del ctx, fd, ud
+            torch.cuda.synchronize()
+    return rows
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -173,6 +249,11 @@ def main():
                          "always autotune (force); done before the warm-up, untimed")
     ap.add_argument("--tune-out", default=None,
                     help="write the launch-shape table of this run (JSON) to this path")
+    ap.add_argument("--cfl-sweep", action="store_true",
+                    help="only run the CFL robustness sweep on the flat box with Dirichlet "
+                         "side walls (one JSON object per solve)")
+    ap.add_argument("--cfl-n", type=int, default=512, help="horizontal size of the sweep")
+    ap.add_argument("--cfl-nz", type=int, default=128, help="layers of the sweep")
     args = ap.parse_args()
     solves = [x for x in args.solves.split(",") if x]
     if any(x not in SOLVES for x in solves) or not solves:
@@ -187,6 +268,9 @@ def main():
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.cfl_sweep:
+        cfl_sweep(args, torch)
+        return
     if args.copy_probe:
         gbs = copy_probe(torch)
         print(json.dumps({"copy_probe_bytes_read": COPY_PROBE_BYTES,

@@ -313,6 +313,31 @@ def test_line_preconditioned_condition_number_with_walls():
     assert kappas[0] < kappas[1] < 1 + 8 * 4.2**2
 
 
+def test_multigrid_robust_to_cfl_number_cg_not():
+    """Sec. 5.2 on the flat box (Dirichlet walls, Neumann ends): with enough
+    levels the multigrid iteration count hardly changes from nu_CFL = 8.4 to
+    840, while CG's grows several-fold (kappa ~ nu^2 until the walls bound it);
+    with only 3 levels the coarse problem is too ill-conditioned for two
+    smoothing steps at large nu, and more coarse steps restore the count."""
+    mg, cg, mg3 = {}, {}, {}
+    for nu in (8.4, 84.0, 840.0):
+        fb = W.FlatBox(64, 16, nu, 5)
+        p = oracle.OracleProblem(64, 64, 16, 5, **fb.params())
+        mg[nu] = p.mg_solve(fb.rhs(), rtol=fb.rtol, maxit=200)[1]
+        fb1 = W.FlatBox(64, 16, nu, 1)
+        q = oracle.OracleProblem(64, 64, 16, 1, **fb1.params())
+        cg[nu] = q.pcg_solve(fb1.rhs(), rtol=fb1.rtol, maxit=5000)[1]
+        fb3 = W.FlatBox(64, 16, nu, 3)
+        r = oracle.OracleProblem(64, 64, 16, 3, **fb3.params())
+        mg3[nu] = r.mg_solve(fb3.rhs(), rtol=fb3.rtol, maxit=300)[1]
+    assert max(mg.values()) <= mg[8.4] + 2 and mg[8.4] <= 12
+    assert cg[84.0] > 2 * cg[8.4] and cg[8.4] > 4 * mg[8.4]
+    assert mg3[840.0] > 5 * mg[840.0]
+    fb = W.FlatBox(64, 16, 840.0, 3, ncoarse=30)
+    p = oracle.OracleProblem(64, 64, 16, 3, **fb.params())
+    assert p.mg_solve(fb.rhs(), rtol=fb.rtol, maxit=300)[1] <= mg[840.0] + 1
+
+
 def test_rowwise_forms_with_walls_equal_csr():
     nx, ny, nz = 8, 6, 7
     kh = W.kh_uniform(8, nx, ny)

@@ -219,6 +219,78 @@ LARGEST = Workload("periodic-2048x2048x128-kv1e5-Klognormal", 2048, 2048, 128, 7
                    "lognormal", 1e-8)
 
 
+# ---------------------------------------------------------------------------
+# The paper's flat-box model problem (robustness study)
+# ---------------------------------------------------------------------------
+
+# Depth of the atmosphere over the Earth's radius: H = D / R with D = 10 km
+# and R = 6371 km (the paper only says H << 1).
+FLAT_BOX_DEPTH = 10.0 / 6371.0
+
+
+@dataclasses.dataclass(frozen=True)
+class FlatBox:
+    """-omega^2 (Lap_2D u + lambda^2 u_zz) + u = f on [0,1]^2 x [0,H]
+    (Sec. 2.1.1): homogeneous Dirichlet side walls, Neumann top and bottom,
+    equidistant layers, constant coefficients K = omega^2, K_v = omega^2
+    lambda^2, with omega = nu_CFL h / 2 (eq. OmegaNumerical; nu_CFL = 8.4 in
+    the paper's main runs, lambda -> 1 at high resolution)."""
+    n: int
+    nz: int
+    nu: float
+    nlevels: int
+    ncoarse: int = 2
+    lam: float = 1.0
+    depth: float = FLAT_BOX_DEPTH
+    seed: int = 7
+    rtol: float = 1e-5      # five orders of magnitude, as in the paper's runs
+
+    @property
+    def name(self) -> str:
+        return (f"flatbox-{self.n}x{self.n}x{self.nz}-nu{self.nu:g}-L{self.nlevels}"
+                f"-nc{self.ncoarse}")
+
+    @property
+    def unknowns(self) -> int:
+        return self.n * self.n * self.nz
+
+    @property
+    def K(self) -> float:
+        return (0.5 * self.nu / self.n) ** 2
+
+    @property
+    def kv(self) -> float:
+        return self.K * self.lam ** 2
+
+    def kh(self) -> np.ndarray:
+        return kh_constant(self.n, self.n, self.K)
+
+    def zfaces(self) -> np.ndarray:
+        return self.depth * uniform_faces(self.nz)
+
+    def rhs(self, r: int = 0) -> np.ndarray:
+        return rhs(self.seed, r, self.n, self.n, self.nz)
+
+    def params(self) -> dict:
+        """Keyword arguments shared by the library context and the oracle."""
+        return dict(kv=self.kv, sigma=1.0, zfaces=self.zfaces(), kh=self.kh(), bc_h=1, bc_v=1,
+                    ncoarse=self.ncoarse)
+
+
+# CFL numbers of the robustness sweep, and the smoothing steps on the
+# coarsest level the paper reports as sufficient for its 5-, 7- and 10-level
+# hierarchies on 512^2 x 128 (Sec. 5.2): two up to nu = 16.8 for all three,
+# then 30 / 5 / 2 at nu = 84 and 150 / 15 / 2 at nu = 840.
+CFL_SWEEP = (2.1, 4.2, 8.4, 16.8, 84.0, 840.0)
+
+
+def paper_coarse_sweeps(nlevels: int, nu: float) -> int:
+    if nu <= 16.8 or nlevels >= 10:
+        return 2
+    table = {5: {84.0: 30, 840.0: 150}, 7: {84.0: 5, 840.0: 15}}
+    return table.get(nlevels, {}).get(nu, 2)
+
+
 def coarsen_levels(n: int, nmin: int = 32) -> int:
     """Levels for a batched instance: coarsen while the size stays >= nmin and even."""
     levels = 1
