@@ -16,7 +16,10 @@ value = sum over the four solves of (unknowns x iterations) / step time.
 The dominant kernel's roofline comes from the library's own per-kernel HIP
 event timing over the timed region (gmg_timing_*), on the stream the kernels
 run on.  The CPU baseline times the FP64 oracle (CSR) on a bounded sample of
-the same workload: one V-cycle plus one residual.
+the same workload: six V-cycles and 24 line-PCG iterations from u = 0.
+Beside the step the line reports the solve from host memory (the paper's
+"total solution time") and flexible CG with the FP32 line preconditioner.
+`--cfl-sweep` runs the CFL robustness study of the paper's flat box instead.
 
 Prints one JSON line on stdout; progress goes to stderr.
 """
@@ -130,7 +133,11 @@ def copy_probe(torch, reps=5):
     return 2 * COPY_PROBE_BYTES / (ms / 1e3) / 1e9
 
 
-def cpu_baseline(w, f, kh, zf):
+def cpu_baseline(w, f, kh, zf, mg_cycles=6, cg_iters=24):
+    """The FP64 oracle (CSR, OpenMP rows) on a bounded sample of the same
+    workload: `mg_cycles` multigrid V-cycles and `cg_iters` line-PCG
+    iterations from u = 0 on the full grid (a few seconds of each); value =
+    unknowns x (cycles + iterations) / time, as for the GPU line."""
     import numpy as np
 
     import oracle
@@ -138,21 +145,22 @@ def cpu_baseline(w, f, kh, zf):
     p = oracle.OracleProblem(w.nx, w.ny, w.nz, w.nlevels, kv=w.kv, sigma=w.sigma, zfaces=zf,
                              kh=kh)
     t_asm = time.perf_counter() - t0
-    u = np.zeros_like(f)
     t0 = time.perf_counter()
-    u = p.vcycle(f, u)
-    r = p.residual(f, u)
-    t_cyc = time.perf_counter() - t0
-    rel = float(np.linalg.norm(r) / np.linalg.norm(f))
+    _, it_mg, hist_mg, _ = p.mg_solve(f, rtol=1e-300, maxit=mg_cycles)
+    t_mg = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    _, it_cg, _, _, _ = p.pcg_solve(f, rtol=1e-300, maxit=cg_iters)
+    t_cg = time.perf_counter() - t0
     del p
     return {
-        "value": w.unknowns / t_cyc,
+        "value": w.unknowns * (it_mg + it_cg) / (t_mg + t_cg),
         "unit": "unknowns*iterations/s",
         "cores": oracle.num_threads(),
         "kind": "oracle",
-        "sample": (f"one FP64 V(1,1) cycle + residual of the CSR oracle on the full "
-                   f"{w.nx}x{w.ny}x{w.nz} workload ({t_cyc:.1f} s; CSR assembly "
-                   f"{t_asm:.1f} s excluded; relres after the cycle {rel:.3e})"),
+        "sample": (f"{it_mg} FP64 V(1,1) cycles ({t_mg:.1f} s, relres {hist_mg[-1]:.2e}) and "
+                   f"{it_cg} FP64 line-PCG iterations ({t_cg:.1f} s) of the CSR oracle from u = 0 "
+                   f"on the full {w.nx}x{w.ny}x{w.nz} workload; CSR assembly {t_asm:.1f} s "
+                   f"excluded"),
     }
 
 
@@ -235,7 +243,7 @@ def cfl_sweep(args, torch):
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true",
                     help="skip the oracle timing (for profiler runs)")
@@ -385,6 +393,22 @@ def main():
         log(f"[bench] solve from host memory: {total:.1f} ms total "
             f"({', '.join(f'{k} {v:.1f}' for k, v in tm_h.items())})")
         del uh
+    # flexible CG with the FP32 line preconditioner alone: reported beside the
+    # step (one untimed and one timed solve), against the FP64 line-PCG
+    line_fcg = None
+    if "pcg_f64" in solves:
+        times = []
+        for _ in range(2):
+            ud.zero_()
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            it_l, rel_l, _, st_l = G.pcg_solve(ctx32, fd, ud, w.rtol, 2000, precond=2)
+            b.record()
+            b.synchronize()
+            times.append(a.elapsed_time(b))
+        line_fcg = {"iters": it_l, "ms": round(times[-1], 3), "relres": rel_l, "status": st_l,
+                    "fp64_pcg_ms_over_this": last["pcg_f64"]["ms"] / times[-1]}
+        log(f"[bench] FP32-line flexible CG: {it_l} it, {times[-1]:.1f} ms")
     prec_id = 0 if dom[2] == "f64" else 1
     traffic = measured_traffic(dom, G.gmg_get_launch(ctx64, dom[0], dom[1], prec_id))
 
@@ -421,6 +445,7 @@ def main():
             "solves_run": solves,
         },
         "solves": {n: {"iters": v["iters"], "ms": round(v["ms"], 3),
+                       "ms_median": round(float(np.median([r[n]["ms"] for r in runs])), 3),
                        "relres": v["relres"]} for n, v in last.items()},
         "mixed_vs_fp64_mg_speedup": speedup("mg_f64", "mg_mixed"),
         "fcg_mixed_vs_fp64_mg_speedup": speedup("mg_f64", "fcg_mixed"),
@@ -440,6 +465,7 @@ def main():
         "kernel_breakdown_ms": breakdown,
         "launch_shapes": shapes,
         "host_solution": host,
+        "fcg_line_mixed": line_fcg,
         "cpu_baseline": base,
     }
     print(json.dumps(line), flush=True)

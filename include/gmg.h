@@ -153,7 +153,10 @@ int gmg_solve(gmg_ctx *c, const double *f, double *u, double rtol, int maxit, in
  * vertical line preconditioner M in FP64, with the two fused kernels
  * (SpMV + vector updates + <p,q>; line solve + residual update + <r,r>, <r,z>).
  * precond = 1: flexible CG with one V-cycle (in prec_precond) as the
- * preconditioner.  Stops when the recursively updated ||r|| / ||r_0|| < rtol;
+ * preconditioner.  precond = 2: flexible CG with the line preconditioner M
+ * applied in prec_precond (with GMG_F32: FP32 Thomas on the FP32-rounded
+ * residual, an inexact preconditioner the flexible recurrence tolerates).
+ * Stops when the recursively updated ||r|| / ||r_0|| < rtol;
  * *relres gets the TRUE relative residual ||f - A u|| / ||f - A u_0|| at exit,
  * history (host, maxit+1, may be NULL) the recursive one per iteration. */
 int pcg_solve(gmg_ctx *c, const double *f, double *u, double rtol, int maxit, int precond,

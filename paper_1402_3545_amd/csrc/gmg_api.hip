@@ -572,8 +572,9 @@ int ensure_hist(gmg_ctx* c, int maxit) {
 // its FP32 correction enters the FP64 recurrences directly).
 template <typename TZ>
 int fcg_impl(gmg_ctx* c, const double* f, double* u, double rtol, int maxit, int* iters,
-             double* relres, double* history, hipStream_t s) {
+             double* relres, double* history, hipStream_t s, bool line_only = false) {
   const bool mixed = sizeof(TZ) == 4;
+  const Lvl<TZ> VZ = gmg::view<TZ>(c, 0);
   const Lvl<double> V = gmg::view<double>(c, 0);
   const int64_t n0 = c->lev[0].elems;
   int st;
@@ -601,7 +602,15 @@ int fcg_impl(gmg_ctx* c, const double* f, double* u, double rtol, int maxit, int
   TZ* z = mixed ? reinterpret_cast<TZ*>(c->eu32) : reinterpret_cast<TZ*>(c->vz);
   const TZ* rin = mixed ? reinterpret_cast<const TZ*>(c->er32) : reinterpret_cast<const TZ*>(c->vr);
   for (int it = 1; it <= maxit; ++it) {
-    if ((st = vcycle_impl<TZ>(c, rin, z, s, true, false))) return st;
+    if (line_only) {
+      // the vertical line preconditioner alone, in the preconditioner's
+      // precision: z = M^-1 r (on the FP32 copy of r in mixed precision)
+      HIP_TRY(timed(c, GMG_K_LINE_SOLVE, 0, prec_of<TZ>(), s, [&](gmg::Shape sh) {
+        return gmg::launch_line_solve_scaled<TZ>(VZ, rin, z, TZ(1), s, sh);
+      }));
+    } else if ((st = vcycle_impl<TZ>(c, rin, z, s, true, false))) {
+      return st;
+    }
     int64_t nb = 0;
     HIP_TRY(timed(c, GMG_K_FCG, 0, GMG_F64, s,
                   [&] { return gmg::launch_fcg_zq<TZ>(V, z, c->vq, c->partials, &nb, s); }));
@@ -1225,12 +1234,13 @@ int pcg_solve(gmg_ctx* c, const double* f, double* u, double rtol, int maxit, in
   if (!(rtol > 0.0)) return fail(GMG_EINVAL, "rtol must be > 0");
   if (maxit < 0) return fail(GMG_EINVAL, "maxit must be >= 0");
   if (f == u) return fail(GMG_EINVAL, "f and u must not overlap");
-  if (precond != 0 && precond != 1) return fail(GMG_EINVAL, "precond must be 0 or 1");
+  if (precond < 0 || precond > 2) return fail(GMG_EINVAL, "precond must be 0, 1 or 2");
   hipStream_t s = as_stream(stream);
-  if (precond == 1) {
+  if (precond >= 1) {
+    const bool line_only = precond == 2;
     if (c->p.prec_precond == GMG_F32)
-      return fcg_impl<float>(c, f, u, rtol, maxit, iters, relres, history, s);
-    return fcg_impl<double>(c, f, u, rtol, maxit, iters, relres, history, s);
+      return fcg_impl<float>(c, f, u, rtol, maxit, iters, relres, history, s, line_only);
+    return fcg_impl<double>(c, f, u, rtol, maxit, iters, relres, history, s, line_only);
   }
   const Lvl<double> V = gmg::view<double>(c, 0);
   const int64_t n0 = c->lev[0].elems;

@@ -147,6 +147,8 @@ def test_solvers_degenerate_cases():
     assert st == G.GMG_ENOCONV and it == 3
     with pytest.raises(G.GmgError):
         G.gmg_solve(ctx, fd, ud, rtol=0.0)
+    with pytest.raises(G.GmgError):
+        G.pcg_solve(ctx, fd, ud, rtol=1e-8, precond=3)
 
 
 @pytest.mark.parametrize("prec_precond", [0, 1])
@@ -170,6 +172,32 @@ def test_flexible_cg_with_multigrid_preconditioner(prec_precond):
     assert true_rel < 1e-8
     assert true_rel == pytest.approx(rel, rel=1e-6)
     u_ref, _, _, _ = orc.mg_solve(f, rtol=1e-12, maxit=100)
+    assert np.linalg.norm(u - u_ref) / np.linalg.norm(u_ref) < 1e-6
+
+
+@pytest.mark.parametrize("prec_precond", [0, 1])
+def test_flexible_cg_with_line_preconditioner(prec_precond):
+    """Flexible CG with the line preconditioner alone (precond = 2).  In FP64
+    it is PCG up to rounding: within one iteration of the oracle's PCG.  With
+    the FP32 line solve (an inexact preconditioner, relative error ~1e-6 per
+    application) the flexible recurrence still reaches the FP64 tolerance in
+    the true residual, with at most a few more iterations."""
+    import paper_1402_3545_amd as G
+    w = W.SMALL
+    ctx, orc, _ = problem(w.nx, w.ny, w.nz, nlevels=w.nlevels, kv=w.kv, seed=w.seed,
+                          kh_model=w.kh_model, prec_precond=prec_precond)
+    f = w.rhs()
+    fd, ud = ctx.to_device(f), ctx.empty()
+    it, rel, hist, st = G.pcg_solve(ctx, fd, ud, rtol=1e-8, maxit=500, precond=2)
+    u_ref, it_ref, _, _, st_ref = orc.pcg_solve(f, rtol=1e-8, maxit=500)
+    assert st == 0 and st_ref == 0
+    if prec_precond == 0:
+        assert abs(it - it_ref) <= 1
+    else:
+        assert it_ref - 1 <= it <= it_ref + 4
+    u = ctx.from_device(ud)
+    true_rel = orc.residual_norm2_rows(f, u) ** 0.5 / np.linalg.norm(f)
+    assert true_rel < 1e-8 and true_rel == pytest.approx(rel, rel=1e-6)
     assert np.linalg.norm(u - u_ref) / np.linalg.norm(u_ref) < 1e-6
 
 
