@@ -257,6 +257,10 @@ def main():
                          "always autotune (force); done before the warm-up, untimed")
     ap.add_argument("--tune-out", default=None,
                     help="write the launch-shape table of this run (JSON) to this path")
+    ap.add_argument("--workload", choices=("share", "small", "largest"), default="share",
+                    help="share: 1024^2 x 128 (the default line); small: 64^3 (cache "
+                         "resident); largest: 2048^2 x 128 (no CPU baseline: its CSR "
+                         "does not fit the host)")
     ap.add_argument("--cfl-sweep", action="store_true",
                     help="only run the CFL robustness sweep on the flat box with Dirichlet "
                          "side walls (one JSON object per solve)")
@@ -288,7 +292,7 @@ def main():
     import paper_1402_3545_amd as G
     import workloads as W
 
-    w = W.SHARE
+    w = {"share": W.SHARE, "small": W.SMALL, "largest": W.LARGEST}[args.workload]
     log(f"[bench] generating inputs for {w.name}")
     kh, zf, f = w.kh(), w.zfaces(), w.rhs()
     ctx64 = G.GmgContext(w.nx, w.ny, w.nz, w.nlevels, kv=w.kv, sigma=w.sigma, zfaces=zf, kh=kh,
@@ -410,10 +414,11 @@ def main():
                     "fp64_pcg_ms_over_this": last["pcg_f64"]["ms"] / times[-1]}
         log(f"[bench] FP32-line flexible CG: {it_l} it, {times[-1]:.1f} ms")
     prec_id = 0 if dom[2] == "f64" else 1
-    traffic = measured_traffic(dom, G.gmg_get_launch(ctx64, dom[0], dom[1], prec_id))
+    traffic = (measured_traffic(dom, G.gmg_get_launch(ctx64, dom[0], dom[1], prec_id))
+               if w is W.SHARE else None)
 
     base = None
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and w is not W.LARGEST:
         log("[bench] timing the CPU oracle sample")
         base = cpu_baseline(w, f, kh, zf)
         log(f"[bench] oracle: {base['value']:.3e} unknowns*it/s on {base['cores']} threads")
@@ -439,7 +444,8 @@ def main():
         "config": {
             "workload": w.name,
             "nx": w.nx, "ny": w.ny, "nz": w.nz, "levels": w.nlevels, "kv": w.kv,
-            "kh": "U[0.5,2] seed 2", "rtol": w.rtol,
+            "kh": {"uniform": "U[0.5,2]", "lognormal": "exp(0.5 N(0,1))",
+                   "const": "1"}[w.kh_model] + f" seed {w.seed}", "rtol": w.rtol,
             "step": ("FP64 MG + FP64 line-CG + FP32-cycle MG in FP64 refinement + FP64 "
                      "flexible CG with FP32 V-cycle, each from u=0"),
             "solves_run": solves,
