@@ -20,9 +20,11 @@ NCOLS = 512
 def share():
     if not torch.cuda.is_available():
         pytest.skip("needs a GPU")
+    import paper_1402_3545_amd as G
     w = W.SHARE
     ctx, orc, kh = problem(w.nx, w.ny, w.nz, nlevels=w.nlevels, kv=w.kv, seed=w.seed,
                            kh_model=w.kh_model, matfree=True)
+    G.tuned(ctx)      # the benchmark's stored launch shapes
     rng = np.random.default_rng(1234)
     cols = np.unique(np.concatenate([
         rng.integers(0, w.nx * w.ny, NCOLS),
@@ -104,3 +106,40 @@ def test_fullsize_mg_solve_true_residual(share):
     true_rel = orc.residual_norm2_rows(f, u) ** 0.5 / np.linalg.norm(f)
     assert true_rel < w.rtol
     assert true_rel == pytest.approx(rel, rel=1e-6)
+
+
+def test_fullsize_pcg_true_residual(share):
+    """The fused line-PCG of the benchmark (its stored launch shapes) on the
+    full share: FP64 true residual over all rows below the tolerance."""
+    import paper_1402_3545_amd as G
+    w, ctx, orc, _ = share
+    f = w.rhs()
+    fd, ud = ctx.to_device(f), ctx.empty()
+    it, rel, hist, st = G.pcg_solve(ctx, fd, ud, rtol=w.rtol, maxit=2000)
+    assert st == 0 and 20 < it < 400
+    true_rel = orc.residual_norm2_rows(f, ctx.from_device(ud)) ** 0.5 / np.linalg.norm(f)
+    assert true_rel < 1.01 * w.rtol
+    assert true_rel == pytest.approx(rel, rel=1e-6)
+
+
+@pytest.mark.parametrize("method", ["refinement", "fcg_vcycle", "fcg_line"])
+def test_fullsize_mixed_precision_true_residual(share, method):
+    """The FP32-preconditioned solvers of the benchmark on the full share, in
+    its stored launch shapes: FP64 true residual over all rows."""
+    import paper_1402_3545_amd as G
+    w, ctx, orc, _ = share
+    ctx32 = G.GmgContext(w.nx, w.ny, w.nz, w.nlevels, kv=w.kv, sigma=1.0, zfaces=w.zfaces(),
+                         kh=W.kh_uniform(w.seed, w.nx, w.ny), prec_precond=G.GMG_F32)
+    G.tuned(ctx32)
+    f = w.rhs()
+    fd, ud = ctx32.to_device(f), ctx32.empty()
+    if method == "refinement":
+        it, rel, _, st = G.gmg_solve(ctx32, fd, ud, rtol=w.rtol, maxit=60)
+    else:
+        it, rel, _, st = G.pcg_solve(ctx32, fd, ud, rtol=w.rtol, maxit=2000,
+                                     precond=1 if method == "fcg_vcycle" else 2)
+    assert st == 0
+    true_rel = orc.residual_norm2_rows(f, ctx32.from_device(ud)) ** 0.5 / np.linalg.norm(f)
+    assert true_rel < w.rtol
+    assert true_rel == pytest.approx(rel, rel=1e-5)
+    ctx32.close()
