@@ -16,7 +16,7 @@ value = sum over the four solves of (unknowns x iterations) / step time.
 The dominant kernel's roofline comes from the library's own per-kernel HIP
 event timing over the timed region (gmg_timing_*), on the stream the kernels
 run on.  The CPU baseline times the FP64 oracle (CSR) on a bounded sample of
-the same workload: six V-cycles and 24 line-PCG iterations from u = 0.
+the same workload: ten V-cycles and 36 line-PCG iterations from u = 0.
 Beside the step the line reports the solve from host memory (the paper's
 "total solution time") and flexible CG with the FP32 line preconditioner.
 `--cfl-sweep` runs the CFL robustness study of the paper's flat box instead.
@@ -133,7 +133,7 @@ def copy_probe(torch, reps=5):
     return 2 * COPY_PROBE_BYTES / (ms / 1e3) / 1e9
 
 
-def cpu_baseline(w, f, kh, zf, mg_cycles=6, cg_iters=24):
+def cpu_baseline(w, f, kh, zf, mg_cycles=10, cg_iters=36):
     """The FP64 oracle (CSR, OpenMP rows) on a bounded sample of the same
     workload: `mg_cycles` multigrid V-cycles and `cg_iters` line-PCG
     iterations from u = 0 on the full grid (a few seconds of each); value =
