@@ -6,8 +6,9 @@
  * anisotropic PDEs on GPU clusters" (arXiv:1402.3545).
  *
  * Operator (Sec. 2.1.1, column-block form; Sec. 3.1, matrix-free tensor-product
- * stencil).  Columns T = (i, j) of a doubly periodic nx x ny grid on the unit
- * square, nz layers between the faces z_0 < ... < z_nz.  With |T| = hx*hy,
+ * stencil).  Columns T = (i, j) of an nx x ny grid on the unit square, doubly
+ * periodic or with homogeneous Dirichlet side walls (gmg_params.bc_h), nz
+ * layers between the faces z_0 < ... < z_nz.  With |T| = hx*hy,
  * dz_k = z_{k+1} - z_k, cell centres zeta_k and vertical transmissibilities
  * t_k = kv / (zeta_k - zeta_{k-1}) (interior faces), t_0 = 2 kv / dz_0 and
  * t_nz = 2 kv / dz_{nz-1} (Dirichlet ends) or 0 (Neumann ends):
@@ -18,7 +19,8 @@
  *
  * where C_TT' is the harmonic mean of the column coefficients K_T, K_T' times
  * the face-length / centre-distance ratio (hy/hx in x, hx/hy in y), and
- * u_{T,-1} = u_{T,nz} = 0.  M = blockdiag(A_T) is the vertical line operator of
+ * u_{T,-1} = u_{T,nz} = 0.  With Dirichlet side walls a wall is a neighbour
+ * of value 0 at half a cell, coupled with 2 K_T times the face ratio.  M = blockdiag(A_T) is the vertical line operator of
  * Sec. 2.2.  Coarse levels halve nx and ny (horizontal-only semicoarsening),
  * average K over the four children and rediscretise.
  *
@@ -129,7 +131,8 @@ int gmg_restrict_smooth(gmg_ctx *c, int level, int prec, const void *rf, void *f
                         double rho, void *stream);
 
 /* Kernel "Prolongate" (Sec. 3.1, Algorithm 1): uf += P uc, cell-centred bilinear
- * interpolation in the horizontal (weights 9/16, 3/16, 3/16, 1/16; periodic).
+ * interpolation in the horizontal (weights 9/16, 3/16, 3/16, 1/16; periodic,
+ * or behind a Dirichlet wall the parent's mirror image with opposite sign).
  * level is the COARSE level (>= 1); uf lives on level-1. */
 int gmg_prolongate(gmg_ctx *c, int level, int prec, const void *uc, void *uf, void *stream);
 
