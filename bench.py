@@ -240,6 +240,50 @@ def cfl_sweep(args, torch):
     return rows
 
 
+def batched_run(args, torch):
+    """The batched workload (64 instances of seeded sizes, 4 right-hand sides
+    each, FP32 V-cycles in FP64 refinement to 1e-8): one untimed and one
+    timed batched solve on resident inputs.  Prints one JSON object."""
+    import numpy as np
+
+    import paper_1402_3545_amd as G
+    import workloads as W
+    insts = W.batched_instances()
+    nrhs = insts[0].nrhs
+    kws = [dict(nx=w.nx, ny=w.ny, nz=w.nz, nlevels=w.nlevels, kv=w.kv, sigma=w.sigma,
+                zfaces=w.zfaces(), kh=w.kh()) for w in insts]
+    b = G.GmgBatch(kws, nrhs=nrhs)
+    fs, us = [], []
+    for q, w in enumerate(insts):
+        for r in range(nrhs):
+            fs.append(b.to_device(w.rhs(r), q))
+            us.append(b.empty(q))
+    log(f"[batched] {len(insts)} instances x {nrhs} rhs, "
+        f"{sum(w.unknowns for w in insts) * nrhs:.3e} unknown-rhs pairs on the device")
+    times = []
+    for _ in range(2):
+        for u in us:
+            u.zero_()
+        torch.cuda.synchronize()
+        a, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        it, rel, st = G.gmg_batch_solve(b, fs, us, rtol=1e-8, maxit=60)
+        e.record()
+        e.synchronize()
+        times.append(a.elapsed_time(e))
+    sizes = np.repeat([w.unknowns for w in insts], nrhs)
+    work = float((sizes * it).sum())
+    rec = {"workload": f"batched-{len(insts)}x{nrhs}", "unknown_rhs": int(sizes.sum()),
+           "status": st, "ms": round(times[-1], 3), "iters_min": int(it.min()),
+           "iters_max": int(it.max()), "iters_mean": round(float(it.mean()), 2),
+           "max_relres": float(rel.max()),
+           "unknowns_iterations_per_s": work / (times[-1] / 1e3)}
+    print(json.dumps(rec), flush=True)
+    log(f"[batched] {times[-1]:.1f} ms, cycles {it.min()}-{it.max()}, "
+        f"{rec['unknowns_iterations_per_s']:.3e} unknowns*it/s")
+    b.close()
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -257,6 +301,8 @@ def main():
                          "always autotune (force); done before the warm-up, untimed")
     ap.add_argument("--tune-out", default=None,
                     help="write the launch-shape table of this run (JSON) to this path")
+    ap.add_argument("--batched", action="store_true",
+                    help="only run the batched workload (one JSON object)")
     ap.add_argument("--workload", choices=("share", "small", "largest"), default="share",
                     help="share: 1024^2 x 128 (the default line); small: 64^3 (cache "
                          "resident); largest: 2048^2 x 128 (no CPU baseline: its CSR "
@@ -282,6 +328,9 @@ def main():
     torch.cuda.set_device(dev)
     if args.cfl_sweep:
         cfl_sweep(args, torch)
+        return
+    if args.batched:
+        batched_run(args, torch)
         return
     if args.copy_probe:
         gbs = copy_probe(torch)
