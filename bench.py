@@ -240,6 +240,67 @@ def cfl_sweep(args, torch):
     return rows
 
 
+# Sec. 5.1, Table SingleGPUTiming (one M2090, nu_CFL = 8.4, tolerance 1e-5):
+# iterations, time per iteration and total solution time in ms by n_x.
+PAPER_SINGLE_GPU = {
+    "pcg": {128: (70, 2.8, 217.1), 256: (62, 7.5, 543.7), 512: (59, 29.7, 2029.0),
+            768: (58, 65.0, 4365.0)},
+    "mg": {128: (9, 12.8, 135.5), 256: (8, 27.3, 285.7), 512: (8, 88.8, 949.9)},
+}
+
+
+def paper_table(args, torch):
+    """The paper's single-GPU table on its own model problem: the flat box with
+    Dirichlet side walls at nu_CFL = 8.4, n_z = 128, 5 levels, tolerance 1e-5,
+    for each n_x of the table: line-PCG and FP64 multigrid on resident data
+    (one untimed and one timed solve), and the total solution time from host
+    memory (copies and layout conversion included).  One JSON object per
+    (solver, n_x), the paper's figures beside ours."""
+    import numpy as np
+
+    import paper_1402_3545_amd as G
+    import workloads as W
+    for n in (128, 256, 512, 768):
+        fb = W.FlatBox(n, 128, 8.4, 5)
+        ctx = G.GmgContext(n, n, fb.nz, fb.nlevels, **fb.params())
+        G.tuned(ctx, reps=3)
+        f = fb.rhs()
+        fd, ud = ctx.to_device(f), ctx.empty()
+        for solver in ("pcg", "mg"):
+            if n not in PAPER_SINGLE_GPU[solver]:
+                continue
+            fn = ((lambda: G.pcg_solve(ctx, fd, ud, fb.rtol, 5000)) if solver == "pcg"
+                  else (lambda: G.gmg_solve(ctx, fd, ud, fb.rtol, 100)))
+            times = []
+            for _ in range(2):
+                ud.zero_()
+                a, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                a.record()
+                it, rel, _, st = fn()
+                e.record()
+                e.synchronize()
+                times.append(a.elapsed_time(e))
+            uh = np.zeros_like(f)
+            G.gmg_solve_host(ctx, f, uh, solver, fb.rtol, 5000)
+            uh[:] = 0.0
+            it_h, _, tm_h, _ = G.gmg_solve_host(ctx, f, uh, solver, fb.rtol, 5000)
+            p_it, p_titer, p_total = PAPER_SINGLE_GPU[solver][n]
+            rec = {"workload": fb.name, "solver": solver, "n_x": n, "iters": it,
+                   "relres": rel, "status": st, "solve_ms": round(times[-1], 3),
+                   "t_iter_ms": round(times[-1] / max(it, 1), 4),
+                   "total_solution_ms": round(sum(tm_h.values()), 3),
+                   "copy_and_layout_ms": round(sum(v for k, v in tm_h.items()
+                                                   if k != "solve"), 3),
+                   "paper_m2090": {"iters": p_it, "t_iter_ms": p_titer,
+                                   "total_solution_ms": p_total}}
+            print(json.dumps(rec), flush=True)
+            log(f"[table] n {n} {solver}: {it} it (paper {p_it}), t_iter "
+                f"{rec['t_iter_ms']:.3f} ms (paper {p_titer}), total "
+                f"{rec['total_solution_ms']:.1f} ms (paper {p_total})")
+        del ctx, fd, ud
+        torch.cuda.synchronize()
+
+
 def batched_run(args, torch):
     """The batched workload (64 instances of seeded sizes, 4 right-hand sides
     each, FP32 V-cycles in FP64 refinement to 1e-8): one untimed and one
@@ -301,6 +362,9 @@ def main():
                          "always autotune (force); done before the warm-up, untimed")
     ap.add_argument("--tune-out", default=None,
                     help="write the launch-shape table of this run (JSON) to this path")
+    ap.add_argument("--paper-table", action="store_true",
+                    help="only run the paper's single-GPU table on its flat box (one JSON "
+                         "object per solver and size)")
     ap.add_argument("--batched", action="store_true",
                     help="only run the batched workload (one JSON object)")
     ap.add_argument("--workload", choices=("share", "small", "largest"), default="share",
@@ -331,6 +395,9 @@ def main():
         return
     if args.batched:
         batched_run(args, torch)
+        return
+    if args.paper_table:
+        paper_table(args, torch)
         return
     if args.copy_probe:
         gbs = copy_probe(torch)
