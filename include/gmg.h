@@ -210,6 +210,11 @@ typedef enum {
 int gmg_timing_enable(gmg_ctx *c, int enable);
 int gmg_timing_read(gmg_ctx *c, int kernel, int level, int prec, int64_t *count,
                     double *total_ms);
+/* Restrict the timing to the kernel kinds whose bit (1u << gmg_kernel) is set
+ * in kernel_mask; ~0u (the default) times every kernel.  Untimed kernels are
+ * launched without events, so a measurement of one kernel kind adds no
+ * overhead to the others.  Takes effect for launches after the call. */
+int gmg_timing_filter(gmg_ctx *c, uint32_t kernel_mask);
 
 /* Layout conversion of one field on the device between the canonical
  * z-contiguous order (j*nx + i)*nz + k -- the order of the caller's host data

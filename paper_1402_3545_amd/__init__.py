@@ -26,7 +26,8 @@ GMG_F64, GMG_F32 = 0, 1
 EXPORTS = ("gmg_default_params", "gmg_setup", "gmg_destroy", "gmg_field_layout", "spmv",
            "line_solve", "line_smooth", "gmg_residual", "gmg_restrict_smooth", "gmg_prolongate",
            "gmg_vcycle", "gmg_solve", "pcg_solve", "gmg_batch_setup", "gmg_batch_layout",
-           "gmg_batch_solve", "gmg_timing_enable", "gmg_timing_read", "gmg_set_launch",
+           "gmg_batch_solve", "gmg_timing_enable", "gmg_timing_read", "gmg_timing_filter",
+           "gmg_set_launch",
            "gmg_get_launch", "gmg_autotune", "gmg_transpose_in", "gmg_transpose_out",
            "gmg_solve_host", "gmg_last_error")
 
@@ -92,6 +93,7 @@ def _load():
                                   dblp, vp]),
         "gmg_timing_enable": (i32, [vp, i32]),
         "gmg_timing_read": (i32, [vp, i32, i32, i32, i64p, dblp]),
+        "gmg_timing_filter": (i32, [vp, C.c_uint32]),
         "gmg_set_launch": (i32, [vp, i32, i32, i32, i32, i32]),
         "gmg_get_launch": (i32, [vp, i32, i32, i32, intp, intp]),
         "gmg_autotune": (i32, [vp, i32, vp]),
@@ -388,6 +390,16 @@ def pcg_solve(ctx, f, u, rtol=1e-8, maxit=1000, precond=0, stream=None, check=Tr
 
 def gmg_timing_enable(ctx, enable=True):
     _check(_lib.gmg_timing_enable(ctx.handle, 1 if enable else 0))
+
+
+def gmg_timing_filter(ctx, kernels=None):
+    """Time only the given kernel kinds (names or ids); None times every kind."""
+    mask = 0xFFFFFFFF
+    if kernels is not None:
+        mask = 0
+        for k in kernels:
+            mask |= 1 << (KERNELS.index(k) if isinstance(k, str) else int(k))
+    _check(_lib.gmg_timing_filter(ctx.handle, C.c_uint32(mask)))
 
 
 def gmg_timing_read(ctx, kernel, level=-1, prec=GMG_F64):

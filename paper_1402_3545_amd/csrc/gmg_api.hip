@@ -372,7 +372,7 @@ hipError_t timed(gmg_ctx* c, int kind, int level, int prec, hipStream_t s, F&& l
     else
       return launch();
   };
-  if (!c->timing) return go();
+  if (!c->timing || !((c->timing_mask >> kind) & 1u)) return go();
   hipEvent_t a = pool_event(c), b = pool_event(c);
   if (!a || !b) return hipErrorOutOfMemory;
   hipError_t e = hipEventRecord(a, s);
@@ -830,6 +830,12 @@ int gmg_timing_enable(gmg_ctx* c, int enable) {
     c->tms.assign((size_t)GMG_K_COUNT * gmg::kMaxLevels * 2, 0.0);
   }
   c->timing = enable != 0;
+  return GMG_OK;
+}
+
+int gmg_timing_filter(gmg_ctx* c, uint32_t kernel_mask) {
+  if (!c || c->batch) return fail(GMG_EINVAL, "context is NULL or batched");
+  c->timing_mask = kernel_mask;
   return GMG_OK;
 }
 

@@ -127,8 +127,9 @@ struct gmg_ctx {
   std::vector<gmg::Shape> shape =
       std::vector<gmg::Shape>((size_t)GMG_K_COUNT * gmg::kMaxLevels * 2);
   gmg::Batch* batch = nullptr;       // non-null: a batched context (gmg_batch_setup)
-  // per-kernel timing
+  // per-kernel timing (of the kernel kinds whose bit is set in timing_mask)
   bool timing = false;
+  uint32_t timing_mask = ~0u;
   std::vector<hipEvent_t> evpool;
   size_t evused = 0;
   std::vector<gmg_timed_launch> pending;

@@ -102,3 +102,31 @@ def test_launch_shape_validation():
             G.gmg_set_launch(ctx, *bad)
     with pytest.raises(G.GmgError):
         G.gmg_autotune(ctx, reps=0)
+
+
+def test_timing_filter_times_only_selected_kinds():
+    """With a filter only the selected kernel kinds are bracketed by events;
+    the solve itself is unchanged (bitwise)."""
+    import paper_1402_3545_amd as G
+    w = W.SMALL
+    ctx, _, _ = problem(w.nx, w.ny, w.nz, nlevels=w.nlevels, kv=w.kv, seed=w.seed,
+                        kh_model=w.kh_model)
+    f = w.rhs()
+    fd = ctx.to_device(f)
+    outs = []
+    for kinds in (None, ["cg_spmv"], ["smooth", "prolongate"]):
+        ud = ctx.empty()
+        G.gmg_timing_filter(ctx, kinds)
+        G.gmg_timing_enable(ctx, True)
+        G.pcg_solve(ctx, fd, ud, rtol=1e-8, maxit=500)
+        G.gmg_solve(ctx, fd, ud, rtol=1e-8, maxit=50)
+        table = G.gmg_timing_table(ctx)
+        G.gmg_timing_enable(ctx, False)
+        timed = {k[0] for k in table}
+        if kinds is None:
+            assert {"cg_spmv", "cg_tridiag", "smooth", "prolongate"} <= timed
+        else:
+            assert timed == set(kinds)
+        outs.append(ud.clone())
+    G.gmg_timing_filter(ctx, None)
+    assert all(torch.equal(outs[0], o) for o in outs[1:])

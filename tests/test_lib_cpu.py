@@ -78,4 +78,5 @@ def test_null_context_is_rejected():
     assert G._lib.gmg_set_launch(None, 0, 0, 0, 4, 0) == G.GMG_EINVAL
     assert G._lib.gmg_get_launch(None, 0, 0, 0, None, None) == G.GMG_EINVAL
     assert G._lib.gmg_autotune(None, 3, None) == G.GMG_EINVAL
+    assert G._lib.gmg_timing_filter(None, 1) == G.GMG_EINVAL
     assert G._lib.gmg_destroy(None) == G.GMG_OK
