@@ -245,3 +245,35 @@ def test_bc_h_validation():
     import paper_1402_3545_amd as G
     with pytest.raises(G.GmgError):
         G.GmgContext(8, 8, 4, 1, bc_h=2)
+
+
+@pytest.mark.parametrize("bc_h", [0, 1])
+def test_batched_solve_down_to_one_column(bc_h):
+    """Batched instances whose hierarchies end at a single column (grouped
+    launches over 1x1 levels): every pair matches the single-instance
+    refinement and the oracle's FP64 true residual."""
+    import oracle
+    import paper_1402_3545_amd as G
+    shapes = [(16, 8, 5), (32, 16, 6), (24, 4, 4)]
+    kws = [dict(nx=n, ny=n, nz=nz, nlevels=L, kv=1e3, sigma=1.0,
+                zfaces=W.quadratic_faces(nz), kh=W.kh_uniform(7000 + q, n, n), bc_h=bc_h)
+           for q, (n, nz, L) in enumerate(shapes)]
+    b = G.GmgBatch(kws, nrhs=1)
+    fh = [W.uniform_pm1(7000 + q, 1, kw["nx"] * kw["ny"] * kw["nz"]) for q, kw in enumerate(kws)]
+    us = [b.empty(q) for q in range(len(kws))]
+    it, rel, st = G.gmg_batch_solve(b, [b.to_device(f, q) for q, f in enumerate(fh)], us,
+                                    rtol=1e-8, maxit=100)
+    assert st == 0, G.gmg_last_error()
+    for q, kw in enumerate(kws):
+        orc = oracle.OracleProblem(kw["nx"], kw["ny"], kw["nz"], kw["nlevels"], kv=kw["kv"],
+                                   sigma=1.0, zfaces=kw["zfaces"], kh=kw["kh"], bc_h=bc_h,
+                                   matfree=True)
+        u = b.from_device(us[q], q)
+        true_rel = orc.residual_norm2_rows(fh[q], u) ** 0.5 / np.linalg.norm(fh[q])
+        assert true_rel < 1e-8, (q, true_rel)
+        ctx = G.GmgContext(prec_precond=G.GMG_F32, **kw)
+        ud = ctx.empty()
+        it1, _, _, st1 = G.gmg_solve(ctx, ctx.to_device(fh[q]), ud, rtol=1e-8, maxit=100)
+        assert st1 == 0 and it1 == it[q]
+        u1 = ctx.from_device(ud)
+        assert np.abs(u1 - u).max() <= 1e-12 * np.abs(u1).max()
