@@ -298,6 +298,25 @@ def test_condition_number_matches_paper(golden_dir, grid):
     assert round(kappa) == kappa_paper
 
 
+def test_condition_number_drops_fourfold_per_level():
+    """Sec. 3 (coarse grid solver): the condition number of each coarser level
+    is smaller by the square of the grid-spacing ratio.  On the periodic flat
+    box with Neumann ends kappa_l - 1 = 8 K/(h_l^2 sigma) exactly, so doubling
+    h divides kappa - 1 by 4 on every level of the hierarchy."""
+    n, nz, L = 16, 3, 3
+    K = (4.2 / n) ** 2
+    p = oracle.OracleProblem(n, n, nz, L, kv=0.5 * K, sigma=1.0, zfaces=W.uniform_faces(nz),
+                             kh=np.full(n * n, K), bc_v=1)
+    kap = []
+    for d in range(L):
+        A = _dense(p, d)
+        ev = sla.eigh(A, _block_diag_part(A, nz), eigvals_only=True)
+        kap.append(ev.max() / ev.min())
+    assert kap[0] == pytest.approx(1 + 8 * 4.2**2, rel=1e-9)
+    for d in range(1, L):
+        assert (kap[d] - 1) == pytest.approx((kap[0] - 1) / 4**d, rel=1e-9)
+
+
 def test_condition_number_dirichlet_closed_form():
     """With Dirichlet ends the same Fourier argument gives
     kappa = 1 + 8K / (h^2 (sigma + s_min)), s_min the smallest eigenvalue of the
