@@ -257,7 +257,10 @@ int gmg_solve_host(gmg_ctx *c, int method, const double *f_host, double *u_host,
  *           twisted elimination, rows = 4); the line solve and the smoother
  *           (GMG_K_LINE_SOLVE, GMG_K_SMOOTH) also take rows = 1: one
  *           wavefront per column, solved by parallel cyclic reduction
- *           (n_z <= 128), for levels with too few columns to fill the GPU.
+ *           (n_z <= 128), for levels with too few columns to fill the GPU;
+ *           the smoother also takes rows = 2: the twisted elimination with
+ *           the horizontal neighbours staged in LDS by the workgroup (each u
+ *           value of the tile and its halo read once) instead of read per lane.
  *   group - tile columns per dispatch group: tiles are walked group by group
  *           and tile rows follow each other inside a group, so that a tile's
  *           neighbours run close in time and share an XCD's L2; 0 walks the
@@ -266,10 +269,10 @@ int gmg_solve_host(gmg_ctx *c, int method, const double *f_host, double *u_host,
  * the FP64 reductions (norms and dot products).
  * gmg_set_launch / gmg_get_launch: one entry of the context's table;
  * GMG_EINVAL for a bad kernel id, level or precision, rows not in {4, 8, 16}
- * (or 1 for the line solve and smoother), group outside [0, 4096], and for
- * batched contexts.
+ * (or 1 for the line solve and smoother, 2 for the smoother), group outside
+ * [0, 4096], and for batched contexts.
  * gmg_autotune: for every level and for the precisions the context's solvers
- * use, runs each candidate shape (rows 4/8/16 or 4/1, group 0/1/2/4/8) of each kernel
+ * use, runs each candidate shape (rows 4/8/16, 4/1 or 4/1/2, group 0/1/2/4/8) of each kernel
  * kind `reps` times on the context's own work buffers (their contents are
  * overwritten; caller memory is not touched), times it with HIP events on
  * `stream` and keeps the fastest.  Synchronises `stream`.  reps in [1, 1000]. */

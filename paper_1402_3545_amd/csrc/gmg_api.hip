@@ -651,13 +651,15 @@ int fcg_impl(gmg_ctx* c, const double* f, double* u, double rtol, int maxit, int
 // Candidate launch shapes: rows per workgroup and tile columns per dispatch
 // group (0 = row-major).  Stencil kernels: 4, 8 or 16 rows; line kernels: the
 // twisted elimination (4) and, for the line solve and the smoother, one
-// wavefront per column by cyclic reduction (1, tile order irrelevant).
+// wavefront per column by cyclic reduction (1, tile order irrelevant); the
+// smoother also with its neighbours staged in LDS (2).
 constexpr int kStencilRows[] = {4, 8, 16};
 constexpr int kLineRows[] = {4};
 constexpr int kLinePcrRows[] = {4, 1};
+constexpr int kSmoothRows[] = {4, 1, 2};
 constexpr int kTuneGroups[] = {0, 1, 2, 4, 8};
 
-enum class Cand { STENCIL, LINE, LINE_PCR };
+enum class Cand { STENCIL, LINE, LINE_PCR, SMOOTH };
 
 // Time `reps` launches of every candidate shape of one kernel kind and store
 // the fastest in the context's table.  `nti` is the kernel's tile count across
@@ -668,10 +670,14 @@ int tune_kind(gmg_ctx* c, int kind, int level, int prec, Cand cand, int nti, int
   gmg::Shape best{};
   float best_ms = 0.0f;
   bool have = false;
-  const int* rows_c = cand == Cand::STENCIL ? kStencilRows
-                      : cand == Cand::LINE  ? kLineRows
-                                            : kLinePcrRows;
-  const int nrows = cand == Cand::STENCIL ? 3 : cand == Cand::LINE ? 1 : 2;
+  const int* rows_c = cand == Cand::STENCIL    ? kStencilRows
+                      : cand == Cand::LINE     ? kLineRows
+                      : cand == Cand::LINE_PCR ? kLinePcrRows
+                                               : kSmoothRows;
+  const int nrows = cand == Cand::STENCIL    ? 3
+                    : cand == Cand::LINE     ? 1
+                    : cand == Cand::LINE_PCR ? 2
+                                             : 3;
   for (int q0 = 0; q0 < nrows; ++q0) {
     const int rows = rows_c[q0];
     for (int group : kTuneGroups) {
@@ -738,7 +744,7 @@ int tune_levels(gmg_ctx* c, int reps, hipStream_t s, hipEvent_t ea, hipEvent_t e
            return gmg::launch_line_solve_scaled<T>(V, x2, x1, rho, s, sh);
          })))
       return st;
-    if ((st = tune_kind(c, GMG_K_SMOOTH, d, P, Cand::LINE_PCR, ntl, reps, s, ea, eb, [&](Shape sh) {
+    if ((st = tune_kind(c, GMG_K_SMOOTH, d, P, Cand::SMOOTH, ntl, reps, s, ea, eb, [&](Shape sh) {
            return gmg::launch_smooth<T>(V, x2, x0, x1, rho, s, sh);
          })))
       return st;
@@ -970,8 +976,11 @@ int gmg_set_launch(gmg_ctx* c, int kernel, int level, int prec, int rows, int gr
   int st;
   if ((st = check_prec(prec))) return st;
   const bool pcr_ok = kernel == GMG_K_LINE_SOLVE || kernel == GMG_K_SMOOTH;
-  if (!(rows == 4 || rows == 8 || rows == 16 || (rows == 1 && pcr_ok)))
-    return fail(GMG_EINVAL, "rows must be 4, 8 or 16 (1 for the line solve and smoother), got %d",
+  if (!(rows == 4 || rows == 8 || rows == 16 || (rows == 1 && pcr_ok) ||
+        (rows == 2 && kernel == GMG_K_SMOOTH)))
+    return fail(GMG_EINVAL,
+                "rows must be 4, 8 or 16 (1 for the line solve and smoother, 2 for the "
+                "smoother), got %d",
                 rows);
   if (group < 0 || group > 4096) return fail(GMG_EINVAL, "group must be in [0, 4096]");
   c->shape[gmg::tslot(kernel, level, prec)] = gmg::Shape{rows, group};

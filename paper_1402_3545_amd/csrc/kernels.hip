@@ -453,6 +453,10 @@ template <typename T>
 struct StepIn<T, LINE_RESTRICT_SMOOTH> { typename Vec2<T>::type lo, hi; };
 template <typename T>
 struct StepIn<T, LINE_CG> { T r, q; };
+// Smoothers with the horizontal neighbours staged in LDS: the lane's next row
+// (un), f, and one value of the workgroup's halo (ex).
+template <typename T>
+struct StepNb { T un, f, ex; };
 
 // Body of the line kernels for tile b of a level (tiles of 32 columns x LROWS
 // rows, nti tiles across; wavefront w of the workgroup owns grid row
@@ -470,11 +474,14 @@ struct StepIn<T, LINE_CG> { T r, q; };
 // ahead (double buffer) so that memory latency overlaps the elimination.  The
 // back sweep recomputes c' (and the pivots) of each G-row segment from its
 // checkpoint and substitutes backwards.
-template <typename T, int HALF, int MODE>
+template <typename T, int HALF, int MODE, bool NB = false>
 __device__ __forceinline__ void line_body(const Lvl<T>& L, const LineArgs<T>& a, int nti,
                                           int ntj, int group, int b) {
   constexpr int NR = 2 * HALF;
   constexpr bool kSmooth = (MODE == LINE_SMOOTH || MODE == LINE_SMOOTH_NORM);
+  // smoothers only: horizontal neighbours through LDS instead of per-lane loads
+  constexpr bool NBL = NB && kSmooth;
+  static_assert(!NBL || LROWS == 4, "the staged halo assumes four rows per workgroup");
   constexpr int G = HALF < 8 ? HALF : 8;                       // back-sweep segment
   constexpr int NG = HALF / G;
   // prefetch chunk: bounded by the registers the buffered loads take
@@ -505,8 +512,11 @@ __device__ __forceinline__ void line_body(const Lvl<T>& L, const LineArgs<T>& a,
   const int j = tj * LROWS + __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   const bool active = (i < L.nx) && (j < L.ny);
   // inactive lanes compute on a valid column and store nothing; they still
-  // take part in the cross-lane exchange
-  const int ic = min(i, L.nx - 1), jc = min(j, L.ny - 1);
+  // take part in the cross-lane exchange.  With the staged neighbours they
+  // take the periodic image of their column and row, so that the values they
+  // stage are the neighbours the active lanes need across the grid's edge.
+  const int ic = NBL ? (i < L.nx ? i : i % L.nx) : min(i, L.nx - 1);
+  const int jc = NBL ? (j < L.ny ? j : j % L.ny) : min(j, L.ny - 1);
   const Col<T> c = load_col(L, ic, jc);
   const int jn = (jc + 1 == L.ny) ? 0 : jc + 1;
   const int js = (jc == 0) ? L.ny - 1 : jc - 1;
@@ -516,6 +526,53 @@ __device__ __forceinline__ void line_body(const Lvl<T>& L, const LineArgs<T>& a,
   const uint32_t kbytes = (uint32_t)L.ldx * ES;   // one layer
   const int k0 = half ? NR - 1 : 0;
   const int dir = half ? -1 : 1;
+
+  // Staged neighbours: every chunk of CH steps, the workgroup writes the u
+  // values of its 4 rows, the rows above and below them and the columns left
+  // and right of its 32 columns, at the layers of both halves, into LDS; each
+  // wave contributes its own row (the lanes' current rows) and one halo value
+  // per lane and step (wave 0 the row below, wave 3 the row above, waves 1
+  // and 2 the side columns of the two halves' layers).
+  const int wv = (int)(threadIdx.x >> 6);
+  const int xl = lane & 31;
+  const char* exbase = nullptr;
+  int exh = half;
+  if constexpr (NBL) {
+    const int i0 = ti * 32, j0 = tj * LROWS;
+    auto wrapx = [&](int q) { q %= L.nx; return q < 0 ? q + L.nx : q; };
+    auto wrapy = [&](int q) { q %= L.ny; return q < 0 ? q + L.ny : q; };
+    int exrow, excol;
+    if (wv == 0) {
+      exrow = wrapy(j0 - 1);
+      excol = ic;
+    } else if (wv == LROWS - 1) {
+      exrow = wrapy(j0 + LROWS);
+      excol = ic;
+    } else {
+      const int l = lane % 12;
+      exrow = wrapy(j0 - 1 + (l >> 1));
+      excol = (l & 1) ? wrapx(i0 + 32) : wrapx(i0 - 1);
+      exh = wv - 1;
+    }
+    exbase = reinterpret_cast<const char*>(a.a + (int64_t)exrow * jstride + excol);
+  }
+  constexpr int NBW = 34, NBR = LROWS + 2;  // staged tile: rows x columns
+  constexpr int NBSTEP = 2 * NBR * NBW;      // one step, both halves
+  auto nbi = [&](int buf, int t, int h, int r, int x) {
+    return ((buf * CH + t) * 2 + h) * NBR * NBW + r * NBW + x;
+  };
+  // + 64 slots that the lanes without a halo value write to (no branch)
+  __shared__ T s_nb[NBL ? 2 * CH * NBSTEP + 64 : 1];
+  // LDS slot of the lane's halo value at step 0 of buffer 0 (or its spare)
+  int exslot = 0;
+  bool exreal = true;
+  if constexpr (NBL) {
+    const bool rowhalo = wv == 0 || wv == LROWS - 1;
+    exreal = rowhalo || lane < 12;
+    const int r = wv == 0 ? 0 : (wv == LROWS - 1 ? NBR - 1 : (lane >> 1));
+    const int x = rowhalo ? xl + 1 : ((lane & 1) ? NBW - 1 : 0);
+    exslot = exreal ? nbi(0, 0, exh, r, x) : 2 * CH * NBSTEP + lane;
+  }
 
   // wave-uniform row bases
   const char* rA = reinterpret_cast<const char*>(a.a + (int64_t)jc * jstride);
@@ -551,9 +608,15 @@ __device__ __forceinline__ void line_body(const Lvl<T>& L, const LineArgs<T>& a,
   };
   auto kcl = [&](int k) { return (uint32_t)min(k, nz - 1); };
   auto off = [&](int k, int col) { return (uint32_t)col * ES + kcl(k) * kbytes; };
-  auto load_step = [&](int k, StepIn<T, MODE>& v) {
+  using SI = std::conditional_t<NBL, StepNb<T>, StepIn<T, MODE>>;
+  auto load_step = [&](int k, SI& v) {
     const uint32_t o = off(k, ic);
-    if constexpr (MODE == LINE_SOLVE) {
+    if constexpr (NBL) {
+      v.un = ldo<T>(rA, (uint32_t)ic * ES + (uint32_t)min(max(k + dir, 0), nz - 1) * kbytes);
+      v.f = ldn<T>(rB, o);
+      // the halo value at this step's layer of half exh
+      v.ex = ldo<T>(exbase, kcl(exh == half ? k : NR - 1 - k) * kbytes);
+    } else if constexpr (MODE == LINE_SOLVE) {
       v.r = ldn<T>(rA, o);
     } else if constexpr (kSmooth) {
       v.un = ldo<T>(rA, (uint32_t)ic * ES + (uint32_t)min(max(k + dir, 0), nz - 1) * kbytes);
@@ -578,12 +641,24 @@ __device__ __forceinline__ void line_body(const Lvl<T>& L, const LineArgs<T>& a,
   T uprv = T(0), ucur = T(0);
   if constexpr (kSmooth) ucur = ldo<T>(rA, off(k0, ic));
 
-  StepIn<T, MODE> buf[2][CH];
+  SI buf[2][CH];
   int kl = k0, kf = k0;  // next row to load, next row to eliminate
 #pragma unroll
   for (int t = 0; t < CH; ++t) load_step(next_row(kl), buf[0][t]);
 #pragma unroll
   for (int ch = 0; ch < NCH; ++ch) {
+    if constexpr (NBL) {
+      // stage this chunk's rows: LDS buffer ch&1 was last read two chunks
+      // ago, before the barrier of the previous chunk
+#pragma unroll
+      for (int t = 0; t < CH; ++t) {
+        const T ctr = t == 0 ? ucur : buf[ch & 1][t - 1].un;
+        s_nb[nbi(ch & 1, t, half, wv + 1, xl + 1)] = ctr;
+        const int step_off = ((ch & 1) * CH + t) * NBSTEP;
+        s_nb[exreal ? exslot + step_off : exslot] = buf[ch & 1][t].ex;
+      }
+      __syncthreads();
+    }
     if (ch + 1 < NCH) {
 #pragma unroll
       for (int t = 0; t < CH; ++t) load_step(next_row(kl), buf[(ch + 1) & 1][t]);
@@ -591,7 +666,7 @@ __device__ __forceinline__ void line_body(const Lvl<T>& L, const LineArgs<T>& a,
 #pragma unroll
     for (int t = 0; t < CH; ++t) {
       const int s = ch * CH + t;
-      const StepIn<T, MODE>& v = buf[ch & 1][t];
+      const SI& v = buf[ch & 1][t];
       const int k = next_row(kf);
       const bool real = k < nz;
       const T sub = s_sub[k], sup = s_sup[k], dzk = s_dz[k];
@@ -606,7 +681,19 @@ __device__ __forceinline__ void line_body(const Lvl<T>& L, const LineArgs<T>& a,
         // neighbours, r = f - A u = g - M u and u' = u + rho M^-1 r solves
         // M (u'/rho) = g + ((1 - rho)/rho) M u: the new iterate comes out of
         // the elimination directly and u is not read again.
-        const T h = c.ce * v.ue + c.cw * v.uw + c.cn * v.unn + c.cs * v.us;
+        T ue, uw, unn, us;
+        if constexpr (NBL) {
+          ue = s_nb[nbi(ch & 1, t, half, wv + 1, xl + 2)];
+          uw = s_nb[nbi(ch & 1, t, half, wv + 1, xl)];
+          unn = s_nb[nbi(ch & 1, t, half, wv + 2, xl + 1)];
+          us = s_nb[nbi(ch & 1, t, half, wv, xl + 1)];
+        } else {
+          ue = v.ue;
+          uw = v.uw;
+          unn = v.unn;
+          us = v.us;
+        }
+        const T h = c.ce * ue + c.cw * uw + c.cn * unn + c.cs * us;
         const T mu = diag * ucur + cpv * uprv + cnx * v.un;
         const T g = v.f + dzk * h;
         rhs = real ? g + wmu * mu : T(0);
@@ -702,13 +789,13 @@ __device__ __forceinline__ void line_body(const Lvl<T>& L, const LineArgs<T>& a,
   }
 }
 
-template <typename T, int HALF, int MODE>
+template <typename T, int HALF, int MODE, bool NB = false>
 __global__ __launch_bounds__(NTHREADS) void k_line(Lvl<T> L, LineArgs<T> a, int nti, int ntj,
                                                    int group) {
   if constexpr (MODE == LINE_CG) {
     if (a.st->done) return;  // uniform: the solve has already stopped
   }
-  line_body<T, HALF, MODE>(L, a, nti, ntj, group, xcd_remap(blockIdx.x, gridDim.x));
+  line_body<T, HALF, MODE, NB>(L, a, nti, ntj, group, xcd_remap(blockIdx.x, gridDim.x));
 }
 
 // ---------------------------------------------------------------------------
@@ -1736,24 +1823,27 @@ hipError_t line_dispatch(const Lvl<T>& L, const LineArgs<T>& a, hipStream_t s, i
   const int nti = cdiv(L.nx, 32), ntj = cdiv(L.ny, LROWS);
   const dim3 grid(nti * ntj), block(NTHREADS);
   const int half = (L.nz + 1) / 2;
-  if (half <= 4)
-    hipLaunchKernelGGL((k_line<T, 4, MODE>), grid, block, 0, s, L, a, nti, ntj,
-                       group);
-  else if (half <= 8)
-    hipLaunchKernelGGL((k_line<T, 8, MODE>), grid, block, 0, s, L, a, nti, ntj,
-                       group);
-  else if (half <= 16)
-    hipLaunchKernelGGL((k_line<T, 16, MODE>), grid, block, 0, s, L, a, nti, ntj,
-                       group);
-  else if (half <= 32)
-    hipLaunchKernelGGL((k_line<T, 32, MODE>), grid, block, 0, s, L, a, nti, ntj,
-                       group);
-  else if (half <= 64)
-    hipLaunchKernelGGL((k_line<T, 64, MODE>), grid, block, 0, s, L, a, nti, ntj,
-                       group);
-  else
-    return hipErrorInvalidValue;
-  return hipGetLastError();
+  auto go = [&](auto nb) -> hipError_t {
+    constexpr bool NB = decltype(nb)::value;
+    if (half <= 4)
+      hipLaunchKernelGGL((k_line<T, 4, MODE, NB>), grid, block, 0, s, L, a, nti, ntj, group);
+    else if (half <= 8)
+      hipLaunchKernelGGL((k_line<T, 8, MODE, NB>), grid, block, 0, s, L, a, nti, ntj, group);
+    else if (half <= 16)
+      hipLaunchKernelGGL((k_line<T, 16, MODE, NB>), grid, block, 0, s, L, a, nti, ntj, group);
+    else if (half <= 32)
+      hipLaunchKernelGGL((k_line<T, 32, MODE, NB>), grid, block, 0, s, L, a, nti, ntj, group);
+    else if (half <= 64)
+      hipLaunchKernelGGL((k_line<T, 64, MODE, NB>), grid, block, 0, s, L, a, nti, ntj, group);
+    else
+      return hipErrorInvalidValue;
+    return hipGetLastError();
+  };
+  // smoothers: horizontal neighbours staged in LDS when asked for (rows = 2)
+  if constexpr (MODE == LINE_SMOOTH || MODE == LINE_SMOOTH_NORM) {
+    if (rows == 2) return go(std::true_type{});
+  }
+  return go(std::false_type{});
 }
 
 }  // namespace
@@ -1918,7 +2008,7 @@ hipError_t launch_smooth_norm(const Lvl<T>& L, const T* f, const T* uin, T* uout
   a.rho = rho;
   a.partials = partials;
   *nblocks = line_blocks(L.nx, L.ny);
-  return line_dispatch<T, LINE_SMOOTH_NORM>(L, a, s, sh.group);
+  return line_dispatch<T, LINE_SMOOTH_NORM>(L, a, s, sh.group, sh.rows);
 }
 
 template <typename T>

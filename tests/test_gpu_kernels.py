@@ -224,3 +224,25 @@ def test_line_kernels_by_cyclic_reduction(shape, prec):
     G.line_smooth(ctx, 0, fd, ud, nsweeps=2)
     sref = orc.smooth(f, orc.smooth(f, r))
     assert max_rel(ctx.from_device(ud), sref, np.abs(sref).max()) < 2 * bar
+
+
+@pytest.mark.parametrize("bc_h", [0, 1])
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("shape", SHAPES + [(1, 1, 8), (3, 3, 5), (65, 9, 3)])
+def test_line_smooth_with_staged_neighbours(shape, prec, bc_h):
+    """The smoother with its horizontal neighbours staged in LDS by the
+    workgroup (launch shape rows = 2): same bars as the per-lane loads, also
+    on grids narrower than a tile and with walls."""
+    import paper_1402_3545_amd as G
+    nx, ny, nz = shape
+    if nx < 2 or ny < 2:
+        pytest.skip("the finest grid needs two columns per direction")
+    ctx, orc, _ = problem(nx, ny, nz, seed=7, bc_h=bc_h)
+    for p in (G.GMG_F64, G.GMG_F32):
+        G.gmg_set_launch(ctx, "smooth", 0, p, 2, 0)
+    u, f = _inputs(nx * ny * nz, 14, prec)
+    ud, fd = ctx.to_device(u, dtype=_dtype(prec)), ctx.to_device(f, dtype=_dtype(prec))
+    G.line_smooth(ctx, 0, fd, ud, nsweeps=2)
+    ref = orc.smooth(f, orc.smooth(f, u))
+    bar = F64 if prec == 0 else f32_line_bar(nz)
+    assert max_rel(ctx.from_device(ud), ref, np.abs(ref).max()) < 2 * bar

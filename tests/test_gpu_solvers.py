@@ -217,3 +217,30 @@ def test_mg_with_cyclic_reduction_on_coarse_levels():
     u_ref, it_ref, hist_ref, st_ref = orc.mg_solve(f, rtol=w.rtol, maxit=50)
     assert st == 0 and it == it_ref
     assert np.allclose(hist, hist_ref[:len(hist)], rtol=1e-10, atol=0)
+
+
+@pytest.mark.parametrize("prec_precond", [0, 1])
+def test_mg_with_staged_smoother_on_every_level(prec_precond):
+    """The V-cycle with the smoother's neighbours staged in LDS on every level
+    (the norm-computing pre-smoothing step included): FP64 follows the oracle's
+    history; the FP32-cycle refinement reaches the FP64 tolerance."""
+    import paper_1402_3545_amd as G
+    w = W.SMALL
+    ctx, orc, _ = problem(w.nx, w.ny, w.nz, nlevels=w.nlevels, kv=w.kv, seed=w.seed,
+                          kh_model=w.kh_model, prec_precond=prec_precond)
+    for lvl in range(ctx.nlevels):
+        for p in (G.GMG_F64, G.GMG_F32):
+            G.gmg_set_launch(ctx, "smooth", lvl, p, 2, 0)
+    f = w.rhs()
+    fd, ud = ctx.to_device(f), ctx.empty()
+    it, rel, hist, st = G.gmg_solve(ctx, fd, ud, rtol=1e-8, maxit=50)
+    u_ref, it_ref, hist_ref, st_ref = orc.mg_solve(f, rtol=1e-8, maxit=50)
+    assert st == 0
+    if prec_precond == 0:
+        assert it == it_ref
+        # to 1e-8 the last entries sit near the residual's rounding floor
+        assert np.allclose(hist, hist_ref[:len(hist)], rtol=1e-10, atol=1e-14)
+    else:
+        assert it <= it_ref + 2
+    u = ctx.from_device(ud)
+    assert orc.residual_norm2_rows(f, u) ** 0.5 / np.linalg.norm(f) < 1e-8

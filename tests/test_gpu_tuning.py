@@ -60,6 +60,26 @@ def test_kernels_bitwise_identical_across_shapes(grid, prec):
         assert nrm == pytest.approx(ref_nrm, rel=1e-13 if prec == 0 else 1e-12)
 
 
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("grid", [(40, 6, 37), (64, 64, 64), (34, 10, 128), (2, 2, 9)])
+def test_staged_smoother_bitwise_equal_to_per_lane_loads(grid, prec):
+    """Staging the neighbours in LDS changes where the values come from, not
+    the arithmetic: the smoother's output is bitwise identical."""
+    import paper_1402_3545_amd as G
+    nx, ny, nz = grid
+    dt = torch.float64 if prec == 0 else torch.float32
+    outs = []
+    for rows in (4, 2):
+        ctx, _, _ = problem(nx, ny, nz, seed=22)
+        G.gmg_set_launch(ctx, "smooth", 0, prec, rows, 0)
+        n = nx * ny * nz
+        u = ctx.to_device(W.uniform_pm1(33, 1, n), dtype=dt)
+        f = ctx.to_device(W.uniform_pm1(33, 2, n), dtype=dt)
+        G.line_smooth(ctx, 0, f, u, nsweeps=3)
+        outs.append(ctx.from_device(u))    # the grid's elements (padding is not part of u)
+    assert np.array_equal(outs[0], outs[1])
+
+
 @pytest.mark.parametrize("prec_precond", [0, 1])
 def test_autotune_then_solve_matches_oracle(prec_precond):
     import paper_1402_3545_amd as G
@@ -95,9 +115,12 @@ def test_launch_shape_validation():
     assert G.gmg_get_launch(ctx, "spmv", 1, G.GMG_F32) == (16, 3)
     G.gmg_set_launch(ctx, "line_solve", 0, G.GMG_F64, 1, 0)     # cyclic reduction
     assert G.gmg_get_launch(ctx, "line_solve", 0, G.GMG_F64) == (1, 0)
+    G.gmg_set_launch(ctx, "smooth", 1, G.GMG_F32, 2, 4)         # staged neighbours
+    assert G.gmg_get_launch(ctx, "smooth", 1, G.GMG_F32) == (2, 4)
     for bad in [("spmv", 2, 0, 4, 0), ("spmv", 0, 2, 4, 0), ("spmv", 0, 0, 5, 0),
                 ("spmv", 0, 0, 4, -1), ("spmv", 0, 0, 4, 5000), (99, 0, 0, 4, 0),
-                ("spmv", 0, 0, 1, 0), ("cg_tridiag", 0, 0, 1, 0)]:
+                ("spmv", 0, 0, 1, 0), ("cg_tridiag", 0, 0, 1, 0), ("line_solve", 0, 0, 2, 0),
+                ("spmv", 0, 0, 2, 0)]:
         with pytest.raises(G.GmgError):
             G.gmg_set_launch(ctx, *bad)
     with pytest.raises(G.GmgError):
