@@ -699,7 +699,12 @@ __device__ __forceinline__ void line_body(const Lvl<T>& L, const LineArgs<T>& a,
         rhs = real ? g + wmu * mu : T(0);
         if constexpr (MODE == LINE_SMOOTH_NORM) {
           const double r = (active && real) ? (double)(g - mu) : 0.0;
+          // pin the running sum to a register at each step: otherwise the
+          // scheduler stretches the sum's dependence chain across the sweep
+          // and the kernel needs twice the registers (one wave per SIMD)
+          asm volatile("" : "+v"(acc_rr));
           acc_rr = fma(r, r, acc_rr);
+          asm volatile("" : "+v"(acc_rr));
         }
         uprv = ucur;
         ucur = v.un;
