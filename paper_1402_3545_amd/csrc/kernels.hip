@@ -764,8 +764,12 @@ __device__ __forceinline__ void line_body(const Lvl<T>& L, const LineArgs<T>& a,
         rk = dp[s] * pseg[t] + (s > 0 ? cpv * dp[s > 0 ? s - 1 : 0] : T(0));
       }
       if constexpr (MODE == LINE_CG) {
+        // pin both running sums to registers at each step (as in the
+        // norm-computing smoother's forward sweep)
+        asm volatile("" : "+v"(acc_rr), "+v"(acc_rz));
         acc_rr += st ? (double)rk * (double)rk : 0.0;
         acc_rz += st ? (double)rk * (double)x : 0.0;
+        asm volatile("" : "+v"(acc_rr), "+v"(acc_rz));
       }
       if (st) {
         const uint32_t o = off(k, ic);
