@@ -68,13 +68,13 @@ SOLVES = ("mg_f64", "pcg_f64", "mg_mixed", "fcg_mixed")
 MEASURED_TRAFFIC = {
     # k_cg_p1, 64x16 workgroups, tile groups of 8 (the stored launch shape);
     # profiles/cg_p1_1024x1024x128_pmc.md.  Plain-copy calibration: 2 GiB read
-    # + 2 GiB written read FETCH_SIZE 898802.2 KiB, WRITE_SIZE 2097237.6 KiB.
+    # + 2 GiB written read FETCH_SIZE 898803.7 KiB, WRITE_SIZE 2097249.9 KiB.
     ("cg_spmv", 0, "f64"): {
-        "fetch_kib": 2327038.0694,
-        "write_kib": 3145864.664,
-        "copy_fetch_scale": 2097152.0 / 898802.2143,
-        "copy_write_scale": 2097152.0 / 2097237.5536,
-        "source_sha256": "fc47d4c0d03101d56734a9510676b38d27014feb6f82e104e917cde1a19c9c13",
+        "fetch_kib": 2326885.6073,
+        "write_kib": 3145864.4161,
+        "copy_fetch_scale": 2097152.0 / 898803.6786,
+        "copy_write_scale": 2097152.0 / 2097249.8929,
+        "source_sha256": "4fb7ba4658ebb405d8938cb52a16118762f5777919b7dc44a70181c01c5e55c2",
         "shape": [16, 8],
     },
 }
