@@ -57,6 +57,7 @@ WORDS_PER_CELL = {
     "cg_tridiag": 4.0,       # read r, q, write r, z
     "correct": 4.0,          # read u, f (8 B), e (4 B), write u (8 B), r (4 B): 32 B
     "residual_restrict": 2.25,  # per FINE cell: read u, f, write 1/4 f_c
+    "prolong_smooth": 3.25,  # read u, f, write u', read 1/4 u_c (u + P u_c not stored)
 }
 
 SOLVES = ("mg_f64", "pcg_f64", "mg_mixed", "fcg_mixed")

@@ -200,12 +200,15 @@ int gmg_batch_solve(gmg_ctx *c, const double *const *f, double *const *u, double
  * fused fine-level residual + restriction (timed under the fine level; the
  * residual is not stored); GMG_K_AUX fills and final updates.  Inside the
  * V-cycle each coarse level starts with a scaled line solve, timed as
- * GMG_K_LINE_SOLVE of that level. */
+ * GMG_K_LINE_SOLVE of that level.  GMG_K_PROLONG_SMOOTH is the V-cycle's
+ * prolongation onto a level folded into that level's post-smoother (one
+ * kernel instead of GMG_K_PROLONGATE + GMG_K_SMOOTH; timed under the fine
+ * level), used where its launch shape says so (below). */
 typedef enum {
   GMG_K_SPMV = 0, GMG_K_RESIDUAL = 1, GMG_K_LINE_SOLVE = 2, GMG_K_SMOOTH = 3,
   GMG_K_RESTRICT_SMOOTH = 4, GMG_K_PROLONGATE = 5, GMG_K_CG_SPMV = 6, GMG_K_CG_TRIDIAG = 7,
   GMG_K_REDUCE = 8, GMG_K_AUX = 9, GMG_K_CORRECT = 10, GMG_K_FCG = 11,
-  GMG_K_RESIDUAL_RESTRICT = 12, GMG_K_COUNT = 13
+  GMG_K_RESIDUAL_RESTRICT = 12, GMG_K_PROLONG_SMOOTH = 13, GMG_K_COUNT = 14
 } gmg_kernel;
 int gmg_timing_enable(gmg_ctx *c, int enable);
 int gmg_timing_read(gmg_ctx *c, int kernel, int level, int prec, int64_t *count,
@@ -261,6 +264,11 @@ int gmg_solve_host(gmg_ctx *c, int method, const double *f_host, double *u_host,
  *           the smoother also takes rows = 2: the twisted elimination with
  *           the horizontal neighbours staged in LDS by the workgroup (each u
  *           value of the tile and its halo read once) instead of read per lane.
+ *           GMG_K_PROLONG_SMOOTH of level l (l < nlevels - 1) takes rows = 4
+ *           (the default: the V-cycle prolongates from level l+1 and then
+ *           post-smooths level l, two kernels) or rows = 2 (one kernel: the
+ *           staged smoother adds the prolongated correction to every value
+ *           it stages, so u + P u_c is never stored; the same arithmetic).
  *   group - tile columns per dispatch group: tiles are walked group by group
  *           and tile rows follow each other inside a group, so that a tile's
  *           neighbours run close in time and share an XCD's L2; 0 walks the
@@ -269,13 +277,15 @@ int gmg_solve_host(gmg_ctx *c, int method, const double *f_host, double *u_host,
  * the FP64 reductions (norms and dot products).
  * gmg_set_launch / gmg_get_launch: one entry of the context's table;
  * GMG_EINVAL for a bad kernel id, level or precision, rows not in {4, 8, 16}
- * (or 1 for the line solve and smoother, 2 for the smoother), group outside
- * [0, 4096], and for batched contexts.
+ * (or 1 for the line solve and smoother, 2 for the smoother; GMG_K_PROLONG_SMOOTH
+ * takes 4 or 2 only), group outside [0, 4096], and for batched contexts.
  * gmg_autotune: for every level and for the precisions the context's solvers
  * use, runs each candidate shape (rows 4/8/16, 4/1 or 4/1/2, group 0/1/2/4/8) of each kernel
  * kind `reps` times on the context's own work buffers (their contents are
  * overwritten; caller memory is not touched), times it with HIP events on
- * `stream` and keeps the fastest.  Synchronises `stream`.  reps in [1, 1000]. */
+ * `stream` and keeps the fastest; the folded prolongation (rows = 2 of
+ * GMG_K_PROLONG_SMOOTH, groups 0/1/2/4/8) is kept for a level where it beats
+ * the best prolongation plus the best smoother.  Synchronises `stream`.  reps in [1, 1000]. */
 int gmg_set_launch(gmg_ctx *c, int kernel, int level, int prec, int rows, int group);
 int gmg_get_launch(const gmg_ctx *c, int kernel, int level, int prec, int *rows, int *group);
 int gmg_autotune(gmg_ctx *c, int reps, void *stream);

@@ -34,7 +34,7 @@ EXPORTS = ("gmg_default_params", "gmg_setup", "gmg_destroy", "gmg_field_layout",
 # kernel ids of the timing facility (gmg_kernel in include/gmg.h)
 KERNELS = ("spmv", "residual", "line_solve", "smooth", "restrict_smooth", "prolongate",
            "cg_spmv", "cg_tridiag", "reduce", "aux", "correct", "fcg",
-           "residual_restrict")
+           "residual_restrict", "prolong_smooth")
 
 
 class GmgError(RuntimeError):
@@ -433,7 +433,7 @@ def gmg_last_error() -> str:
 # ---------------------------------------------------------------------------
 # kernel kinds whose launch shape the solvers use
 TUNED_KERNELS = ("spmv", "residual", "line_solve", "smooth", "prolongate", "cg_spmv",
-                 "cg_tridiag", "correct", "fcg", "residual_restrict")
+                 "cg_tridiag", "correct", "fcg", "residual_restrict", "prolong_smooth")
 LAUNCH_TABLE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "launch_shapes.json")
 
 

@@ -482,13 +482,22 @@ int vcycle_impl(gmg_ctx* c, const T* f0, T* u0, hipStream_t s, bool zero_guess =
   for (int d = L - 2; d >= 0; --d) {
     const Lvl<T> V = gmg::view<T>(c, d);
     const Lvl<T> C = gmg::view<T>(c, d + 1);
-    HIP_TRY(timed(c, GMG_K_PROLONGATE, d + 1, P, s,
-                  [&](gmg::Shape sh) { return gmg::launch_prolongate<T>(C, V, cur[d + 1], cur[d], s, sh); }));
     T* other = (d == 0) ? u0
                         : (cur[d] == c->lev[d].u ? static_cast<T*>(c->lev[d].ualt)
                                                  : static_cast<T*>(c->lev[d].u));
-    HIP_TRY(timed(c, GMG_K_SMOOTH, d, P, s,
-                  [&](gmg::Shape sh) { return gmg::launch_smooth<T>(V, fl[d], cur[d], other, rho, s, sh); }));
+    if (c->shape[gmg::tslot(GMG_K_PROLONG_SMOOTH, d, P)].rows == 2) {
+      // one kernel: smooth u + P u_c without storing it
+      HIP_TRY(timed(c, GMG_K_PROLONG_SMOOTH, d, P, s, [&](gmg::Shape sh) {
+        return gmg::launch_prolong_smooth<T>(V, C, fl[d], cur[d], cur[d + 1], other, rho, s, sh);
+      }));
+    } else {
+      HIP_TRY(timed(c, GMG_K_PROLONGATE, d + 1, P, s, [&](gmg::Shape sh) {
+        return gmg::launch_prolongate<T>(C, V, cur[d + 1], cur[d], s, sh);
+      }));
+      HIP_TRY(timed(c, GMG_K_SMOOTH, d, P, s, [&](gmg::Shape sh) {
+        return gmg::launch_smooth<T>(V, fl[d], cur[d], other, rho, s, sh);
+      }));
+    }
     cur[d] = other;
   }
   return GMG_OK;
@@ -666,7 +675,8 @@ enum class Cand { STENCIL, LINE, LINE_PCR, SMOOTH };
 // (groups at or above it are row-major again and are skipped).
 template <typename F>
 int tune_kind(gmg_ctx* c, int kind, int level, int prec, Cand cand, int nti, int reps,
-              hipStream_t s, hipEvent_t ea, hipEvent_t eb, F&& launch) {
+              hipStream_t s, hipEvent_t ea, hipEvent_t eb, F&& launch,
+              float* best_out = nullptr) {
   gmg::Shape best{};
   float best_ms = 0.0f;
   bool have = false;
@@ -698,6 +708,7 @@ int tune_kind(gmg_ctx* c, int kind, int level, int prec, Cand cand, int nti, int
     }
   }
   c->shape[gmg::tslot(kind, level, prec)] = best;
+  if (best_out) *best_out = best_ms;
   return GMG_OK;
 }
 
@@ -744,9 +755,10 @@ int tune_levels(gmg_ctx* c, int reps, hipStream_t s, hipEvent_t ea, hipEvent_t e
            return gmg::launch_line_solve_scaled<T>(V, x2, x1, rho, s, sh);
          })))
       return st;
+    float ms_smooth = 0.0f;
     if ((st = tune_kind(c, GMG_K_SMOOTH, d, P, Cand::SMOOTH, ntl, reps, s, ea, eb, [&](Shape sh) {
            return gmg::launch_smooth<T>(V, x2, x0, x1, rho, s, sh);
-         })))
+         }, &ms_smooth)))
       return st;
     if (d + 1 < L) {
       const Lvl<T> C = gmg::view<T>(c, d + 1);
@@ -758,11 +770,33 @@ int tune_levels(gmg_ctx* c, int reps, hipStream_t s, hipEvent_t ea, hipEvent_t e
                           })))
         return st;
       // prolongation from level d+1 onto level d, kept under the coarse level
+      float ms_prol = 0.0f;
       if ((st = tune_kind(c, GMG_K_PROLONGATE, d + 1, P, Cand::STENCIL, nts, reps, s, ea, eb,
                           [&](Shape sh) {
                             return gmg::launch_prolongate<T>(C, V, uc, x1, s, sh);
-                          })))
+                          }, &ms_prol)))
         return st;
+      // the prolongation folded into the post-smoother: kept where it beats
+      // the two kernels
+      Shape fused{4, 0};
+      float best_ms = ms_smooth + ms_prol;
+      for (int group : kTuneGroups) {
+        if (group >= ntl) continue;
+        const Shape sh{2, group};
+        auto go = [&] { return gmg::launch_prolong_smooth<T>(V, C, x2, x0, uc, x1, rho, s, sh); };
+        HIP_TRY(go());  // warm-up
+        HIP_TRY(hipEventRecord(ea, s));
+        for (int q = 0; q < reps; ++q) HIP_TRY(go());
+        HIP_TRY(hipEventRecord(eb, s));
+        HIP_TRY(hipEventSynchronize(eb));
+        float ms = 0.0f;
+        HIP_TRY(hipEventElapsedTime(&ms, ea, eb));
+        if (ms < best_ms) {
+          best_ms = ms;
+          fused = sh;
+        }
+      }
+      c->shape[gmg::tslot(GMG_K_PROLONG_SMOOTH, d, P)] = fused;
     }
   }
   return GMG_OK;
@@ -976,12 +1010,17 @@ int gmg_set_launch(gmg_ctx* c, int kernel, int level, int prec, int rows, int gr
   int st;
   if ((st = check_prec(prec))) return st;
   const bool pcr_ok = kernel == GMG_K_LINE_SOLVE || kernel == GMG_K_SMOOTH;
-  if (!(rows == 4 || rows == 8 || rows == 16 || (rows == 1 && pcr_ok) ||
-        (rows == 2 && kernel == GMG_K_SMOOTH)))
+  if (kernel == GMG_K_PROLONG_SMOOTH) {
+    if (rows != 4 && rows != 2)
+      return fail(GMG_EINVAL, "rows of the folded prolongation must be 4 (off) or 2, got %d",
+                  rows);
+  } else if (!(rows == 4 || rows == 8 || rows == 16 || (rows == 1 && pcr_ok) ||
+               (rows == 2 && kernel == GMG_K_SMOOTH))) {
     return fail(GMG_EINVAL,
                 "rows must be 4, 8 or 16 (1 for the line solve and smoother, 2 for the "
                 "smoother), got %d",
                 rows);
+  }
   if (group < 0 || group > 4096) return fail(GMG_EINVAL, "group must be in [0, 4096]");
   c->shape[gmg::tslot(kernel, level, prec)] = gmg::Shape{rows, group};
   return GMG_OK;

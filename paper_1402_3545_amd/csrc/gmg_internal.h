@@ -180,6 +180,12 @@ hipError_t launch_line_solve(const Lvl<T>& L, const T* r, T* z, hipStream_t s, S
 template <typename T>
 hipError_t launch_smooth(const Lvl<T>& L, const T* f, const T* uin, T* uout, T rho,
                          hipStream_t s, Shape sh = {});
+// uout = one Smooth of (uin + P uc) on F with right-hand side f: the V-cycle's
+// prolongation from C folded into the post-smoother (staged form; sh.group
+// is the tile order).  uin is read only; uout must not alias uin or uc.
+template <typename T>
+hipError_t launch_prolong_smooth(const Lvl<T>& F, const Lvl<T>& C, const T* f, const T* uin,
+                                 const T* uc, T* uout, T rho, hipStream_t s, Shape sh = {});
 
 template <typename T>
 hipError_t launch_restrict_smooth(const Lvl<T>& C, const Lvl<T>& F, const T* rf, T* fc, T* uc,

@@ -391,7 +391,8 @@ enum LineMode {
   LINE_SMOOTH = 1,         // u' = u + rho M^-1 (f - A u)
   LINE_RESTRICT_SMOOTH = 2,
   LINE_CG = 3,
-  LINE_SMOOTH_NORM = 4     // LINE_SMOOTH plus ||f - A u||^2 partials
+  LINE_SMOOTH_NORM = 4,    // LINE_SMOOTH plus ||f - A u||^2 partials
+  LINE_PROLONG_SMOOTH = 5  // LINE_SMOOTH of u + P u_c: the prolongation folded in
 };
 
 template <typename T>
@@ -406,6 +407,8 @@ struct LineArgs {
   const CgState* st;  // CG
   int init;           // CG: initial step (alpha = 0)
   double* partials;   // CG: <r,r>, <r,z>; SMOOTH_NORM: ||f - A u||^2 per workgroup
+  Lvl<T> C;           // PROLONG_SMOOTH: the coarse level
+  const T* uc;        // PROLONG_SMOOTH: the coarse-level correction
 };
 
 template <typename T>
@@ -457,6 +460,9 @@ struct StepIn<T, LINE_CG> { T r, q; };
 // (un), f, and one value of the workgroup's halo (ex).
 template <typename T>
 struct StepNb { T un, f, ex; };
+// ... and, with the prolongation folded in, one value of the coarse tile (cv).
+template <typename T>
+struct StepNbP { T un, f, ex, cv; };
 
 // Body of the line kernels for tile b of a level (tiles of 32 columns x LROWS
 // rows, nti tiles across; wavefront w of the workgroup owns grid row
@@ -478,16 +484,21 @@ template <typename T, int HALF, int MODE, bool NB = false>
 __device__ __forceinline__ void line_body(const Lvl<T>& L, const LineArgs<T>& a, int nti,
                                           int ntj, int group, int b) {
   constexpr int NR = 2 * HALF;
-  constexpr bool kSmooth = (MODE == LINE_SMOOTH || MODE == LINE_SMOOTH_NORM);
+  // the prolongation folded into the post-smoother (staged form only)
+  constexpr bool PRO = MODE == LINE_PROLONG_SMOOTH;
+  constexpr bool kSmooth = (MODE == LINE_SMOOTH || MODE == LINE_SMOOTH_NORM || PRO);
+  static_assert(!PRO || NB, "the prolongation is folded into the staged smoother only");
   // smoothers only: horizontal neighbours through LDS instead of per-lane loads
   constexpr bool NBL = NB && kSmooth;
   static_assert(!NBL || LROWS == 4, "the staged halo assumes four rows per workgroup");
   constexpr int G = HALF < 8 ? HALF : 8;                       // back-sweep segment
   constexpr int NG = HALF / G;
   // prefetch chunk: bounded by the registers the buffered loads take
+  // (FP64 with the prolongation folded in: 2, or the coarse values would
+  // push the kernel past 256 registers)
   constexpr int CHW = (MODE == LINE_SOLVE || sizeof(T) == 4) && MODE != LINE_RESTRICT_SMOOTH
                           ? (kSmooth ? 4 : 8)
-                          : 4;
+                          : (PRO ? 2 : 4);
   constexpr int CH = HALF < CHW ? HALF : CHW;
   constexpr int NCH = HALF / CH;
   constexpr uint32_t ES = sizeof(T);
@@ -574,6 +585,82 @@ __device__ __forceinline__ void line_body(const Lvl<T>& L, const LineArgs<T>& a,
     exslot = exreal ? nbi(0, 0, exh, r, x) : 2 * CH * NBSTEP + lane;
   }
 
+  // Prolongation folded in (u + P u_c is smoothed; u + P u_c is never
+  // stored): the fine values the workgroup stages (rows j0-1 .. j0+4, columns
+  // i0-1 .. i0+32) take their corrections from the coarse columns
+  // i0/2-1 .. i0/2+16 and rows j0/2-1 .. j0/2+2 (CNR x CNW).  Every chunk,
+  // lanes 0 .. CNS-1 stage one coarse value each for every step of the chunk
+  // and for the next chunk's first step (the layer of the last step's next
+  // row), for both halves' layers; then each lane adds the 9/3/3/1 sum of
+  // its own next rows and its halo value before they go to the fine stage.
+  // Fine indices stay unwrapped (F.nx = 2 C.nx, so periodic images of fine
+  // and coarse columns line up with the wrapped coarse loads); behind a wall
+  // the coarse neighbour is the parent's mirror image with opposite sign.
+  constexpr int CNW = 18, CNR = 4, CNS = 2 * CNR * CNW;
+  constexpr int CST = CH + 1;
+  __shared__ T s_cs[PRO ? CST * CNS + NTHREADS : 1];
+  const char* cbase = nullptr;
+  uint32_t ckb = 0;
+  int chh = 0, cslot = 0;
+  bool creal = false;
+  // the four coarse slots of a fine cell, packed one per byte (a, b, c, d:
+  // parent, x neighbour, y neighbour, diagonal; each < 72), with the mirror
+  // signs of the x and y neighbours in bits 15 and 23
+  uint32_t po = 0, pe = 0;  // own column (at the lane's half), halo value (at half exh)
+  if constexpr (PRO) {
+    const int q = (int)threadIdx.x;
+    creal = q < CNS;
+    const int qq = creal ? q : 0;
+    chh = qq / (CNR * CNW);
+    const int cr = (qq / CNW) % CNR, cx = qq % CNW;
+    const int ib = ti * 16 - 1, jb = tj * (LROWS / 2) - 1;
+    auto wrapn = [](int v, int n) { v %= n; return v < 0 ? v + n : v; };
+    const int I = wrapn(ib + cx, a.C.nx), J = wrapn(jb + cr, a.C.ny);
+    cbase = reinterpret_cast<const char*>(a.uc + (int64_t)J * a.C.nz * a.C.ldx + I);
+    ckb = (uint32_t)a.C.ldx * ES;
+    cslot = creal ? q : CST * CNS + q;
+    // slots (relative to one step and half) of the four coarse values of the
+    // fine cell (fi, fj) and the mirror signs
+    auto slots = [&](int fi, int fj) -> uint32_t {
+      const int I0 = fi >> 1, J0 = fj >> 1;
+      int I2 = I0 + ((fi & 1) ? 1 : -1), J2 = J0 + ((fj & 1) ? 1 : -1);
+      uint32_t mx = 0, my = 0;
+      if (a.C.bch && (I2 < 0 || I2 >= a.C.nx)) {
+        I2 = I0;
+        mx = 1;
+      }
+      if (a.C.bch && (J2 < 0 || J2 >= a.C.ny)) {
+        J2 = J0;
+        my = 1;
+      }
+      const int x0 = I0 - ib, x2 = I2 - ib, y0 = J0 - jb, y2 = J2 - jb;
+      return (uint32_t)(y0 * CNW + x0) | ((uint32_t)(y0 * CNW + x2) << 8) | (mx << 15) |
+             ((uint32_t)(y2 * CNW + x0) << 16) | (my << 23) | ((uint32_t)(y2 * CNW + x2) << 24);
+    };
+    const int i0 = ti * 32, j0 = tj * LROWS;
+    po = slots(i, j);
+    int hi = i, hj = j;  // lanes without a halo value: any cell of the tile
+    if (wv == 0) {
+      hj = j0 - 1;
+    } else if (wv == LROWS - 1) {
+      hj = j0 + LROWS;
+    } else if (lane < 12) {
+      hj = j0 - 1 + (lane >> 1);
+      hi = (lane & 1) ? i0 + 32 : i0 - 1;
+    }
+    pe = slots(hi, hj);
+  }
+  // u + P u_c from the coarse stage (step t of the chunk, half h)
+  // (the same arithmetic, in the same order, as the prolongation kernel)
+  auto corr = [&](uint32_t ps, int t, int h, T u) {
+    const T* cs = s_cs + (t * 2 + h) * (CNR * CNW);
+    const T sx = (ps & 0x8000u) ? T(-1) : T(1), sy = (ps & 0x800000u) ? T(-1) : T(1);
+    const T wb = T(3) * sx, wc = T(3) * sy, wd = sx * sy;
+    const T pp = T(9) * cs[ps & 0x7fu] + wb * cs[(ps >> 8) & 0x7fu] +
+                 wc * cs[(ps >> 16) & 0x7fu] + wd * cs[ps >> 24];
+    return u + pp * T(0.0625);
+  };
+
   // wave-uniform row bases
   const char* rA = reinterpret_cast<const char*>(a.a + (int64_t)jc * jstride);
   const char* rAn = reinterpret_cast<const char*>(a.a + (int64_t)jn * jstride);
@@ -608,7 +695,8 @@ __device__ __forceinline__ void line_body(const Lvl<T>& L, const LineArgs<T>& a,
   };
   auto kcl = [&](int k) { return (uint32_t)min(k, nz - 1); };
   auto off = [&](int k, int col) { return (uint32_t)col * ES + kcl(k) * kbytes; };
-  using SI = std::conditional_t<NBL, StepNb<T>, StepIn<T, MODE>>;
+  using SI = std::conditional_t<NBL, std::conditional_t<PRO, StepNbP<T>, StepNb<T>>,
+                                StepIn<T, MODE>>;
   auto load_step = [&](int k, SI& v) {
     const uint32_t o = off(k, ic);
     if constexpr (NBL) {
@@ -616,6 +704,7 @@ __device__ __forceinline__ void line_body(const Lvl<T>& L, const LineArgs<T>& a,
       v.f = ldn<T>(rB, o);
       // the halo value at this step's layer of half exh
       v.ex = ldo<T>(exbase, kcl(exh == half ? k : NR - 1 - k) * kbytes);
+      if constexpr (PRO) v.cv = ldo<T>(cbase, kcl(chh == half ? k : NR - 1 - k) * ckb);
     } else if constexpr (MODE == LINE_SOLVE) {
       v.r = ldn<T>(rA, o);
     } else if constexpr (kSmooth) {
@@ -642,11 +731,31 @@ __device__ __forceinline__ void line_body(const Lvl<T>& L, const LineArgs<T>& a,
   if constexpr (kSmooth) ucur = ldo<T>(rA, off(k0, ic));
 
   SI buf[2][CH];
+  T cnext[2] = {T(0), T(0)};  // PRO: coarse value of the next chunk's first step
   int kl = k0, kf = k0;  // next row to load, next row to eliminate
+  auto load_cnext = [&](T& cv) {
+    if constexpr (PRO) cv = ldo<T>(cbase, kcl(chh == half ? kl : NR - 1 - kl) * ckb);
+  };
 #pragma unroll
   for (int t = 0; t < CH; ++t) load_step(next_row(kl), buf[0][t]);
+  load_cnext(cnext[0]);
 #pragma unroll
   for (int ch = 0; ch < NCH; ++ch) {
+    if constexpr (PRO) {
+      // coarse stage: its previous contents were last read before the
+      // previous chunk's fine-stage barrier
+#pragma unroll
+      for (int t = 0; t < CH; ++t)
+        s_cs[creal ? cslot + t * CNS : cslot] = buf[ch & 1][t].cv;
+      s_cs[creal ? cslot + CH * CNS : cslot] = cnext[ch & 1];
+      __syncthreads();
+      if (ch == 0) ucur = corr(po, 0, half, ucur);
+#pragma unroll
+      for (int t = 0; t < CH; ++t) {
+        buf[ch & 1][t].un = corr(po, t + 1, half, buf[ch & 1][t].un);
+        buf[ch & 1][t].ex = corr(pe, t, exh, buf[ch & 1][t].ex);
+      }
+    }
     if constexpr (NBL) {
       // stage this chunk's rows: LDS buffer ch&1 was last read two chunks
       // ago, before the barrier of the previous chunk
@@ -662,6 +771,7 @@ __device__ __forceinline__ void line_body(const Lvl<T>& L, const LineArgs<T>& a,
     if (ch + 1 < NCH) {
 #pragma unroll
       for (int t = 0; t < CH; ++t) load_step(next_row(kl), buf[(ch + 1) & 1][t]);
+      load_cnext(cnext[(ch + 1) & 1]);
     }
 #pragma unroll
     for (int t = 0; t < CH; ++t) {
@@ -1848,11 +1958,15 @@ hipError_t line_dispatch(const Lvl<T>& L, const LineArgs<T>& a, hipStream_t s, i
       return hipErrorInvalidValue;
     return hipGetLastError();
   };
-  // smoothers: horizontal neighbours staged in LDS when asked for (rows = 2)
-  if constexpr (MODE == LINE_SMOOTH || MODE == LINE_SMOOTH_NORM) {
-    if (rows == 2) return go(std::true_type{});
+  if constexpr (MODE == LINE_PROLONG_SMOOTH) {
+    return go(std::true_type{});  // staged form only
+  } else {
+    // smoothers: horizontal neighbours staged in LDS when asked for (rows = 2)
+    if constexpr (MODE == LINE_SMOOTH || MODE == LINE_SMOOTH_NORM) {
+      if (rows == 2) return go(std::true_type{});
+    }
+    return go(std::false_type{});
   }
-  return go(std::false_type{});
 }
 
 }  // namespace
@@ -1983,6 +2097,20 @@ hipError_t launch_smooth(const Lvl<T>& L, const T* f, const T* uin, T* uout, T r
   a.o0 = uout;
   a.rho = rho;
   return line_dispatch<T, LINE_SMOOTH>(L, a, s, sh.group, sh.rows);
+}
+
+template <typename T>
+hipError_t launch_prolong_smooth(const Lvl<T>& F, const Lvl<T>& C, const T* f, const T* uin,
+                                 const T* uc, T* uout, T rho, hipStream_t s, Shape sh) {
+  if (F.nx != 2 * C.nx || F.ny != 2 * C.ny || F.nz != C.nz) return hipErrorInvalidValue;
+  LineArgs<T> a{};
+  a.a = uin;
+  a.b = f;
+  a.o0 = uout;
+  a.rho = rho;
+  a.C = C;
+  a.uc = uc;
+  return line_dispatch<T, LINE_PROLONG_SMOOTH>(F, a, s, sh.group, 2);
 }
 
 template <typename T>
@@ -2182,6 +2310,8 @@ hipError_t launch_add_f32_to_f64(double* u, const float* e, int64_t n, hipStream
   template hipError_t launch_line_solve<T>(const Lvl<T>&, const T*, T*, hipStream_t, Shape);  \
   template hipError_t launch_smooth<T>(const Lvl<T>&, const T*, const T*, T*, T, hipStream_t, \
                                        Shape);                                                \
+  template hipError_t launch_prolong_smooth<T>(const Lvl<T>&, const Lvl<T>&, const T*,        \
+                                               const T*, const T*, T*, T, hipStream_t, Shape);\
   template hipError_t launch_restrict_smooth<T>(const Lvl<T>&, const Lvl<T>&, const T*, T*,   \
                                                 T*, T, hipStream_t, Shape);                   \
   template hipError_t launch_prolongate<T>(const Lvl<T>&, const Lvl<T>&, const T*, T*,        \

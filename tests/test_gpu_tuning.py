@@ -26,6 +26,8 @@ def _need_gpu():
 
 def _set_all(G, ctx, rows, group):
     for k in G.TUNED_KERNELS:
+        if k == "prolong_smooth":  # a V-cycle choice (rows 4 or 2), not a tiling
+            continue
         for lvl in range(ctx.nlevels):
             for prec in (G.GMG_F64, G.GMG_F32):
                 G.gmg_set_launch(ctx, k, lvl, prec, rows, group)
@@ -93,7 +95,10 @@ def test_autotune_then_solve_matches_oracle(prec_precond):
     G.gmg_autotune(ctx, reps=2)
     table = G.launch_table(ctx)
     assert all(r in (1, 4, 8, 16) and 0 <= g <= 8 for k, (r, g) in table.items()
-               if not k.startswith("smooth/"))
+               if not k.startswith(("smooth/", "prolong_smooth/")))
+    # the folded prolongation is on (2) or off (4)
+    assert all(r in (2, 4) and 0 <= g <= 8 for k, (r, g) in table.items()
+               if k.startswith("prolong_smooth/"))
     # the smoother may also take the staged-neighbour form (rows = 2)
     assert all(r in (1, 2, 4) and 0 <= g <= 8 for k, (r, g) in table.items()
                if k.startswith("smooth/"))
