@@ -163,7 +163,7 @@ int build(Batch* b, hipStream_t s) {
     for (GItem<float>& it : its) {
       it.blk0 = blk;
       int nb;
-      if (kind == GKind::LINE_SOLVE || kind == GKind::SMOOTH) {
+      if (kind == GKind::LINE_SOLVE || kind == GKind::SMOOTH || kind == GKind::PROLONG_SMOOTH) {
         nb = it.nti * it.ntj;
       } else if (kind == GKind::RESRESTRICT) {
         nb = it.nti * it.ntj * (int)stencil_tiles_k(it.X.nz);
@@ -261,26 +261,22 @@ int build(Batch* b, hipStream_t s) {
     }
     emit(GKind::RESRESTRICT, 0, rr);
   }
+  // ascend: the prolongation folded into the staged post-smoother (one
+  // grouped launch per column-height class and level: u_f + P u_c is
+  // smoothed without being stored)
   for (int D = Lmax - 2; D >= 0; --D) {
-    std::vector<GItem<float>> pr, sm;
+    std::vector<GItem<float>> ps;
     for (int q = 0; q < b->npairs; ++q) {
       const gmg_ctx* c = b->inst[b->pair_inst[q]];
       if (D >= c->nlevels - 1) continue;
-      GItem<float> it{};
-      it.L = view<float>(c, D);
-      it.X = view<float>(c, D + 1);
-      it.a = cur[q][D + 1];
-      it.o = cur[q][D];
-      it.nti = (int)stencil_tiles_x(it.L.nx);
-      it.ntj = (int)stencil_tiles_y(it.L.ny);
-      it.pair = q;
-      pr.push_back(it);
       float* out = D == 0 ? b->pb[q].e32 : other_of(q, D);
-      sm.push_back(line_item(q, D, cur[q][D], rhs_of(q, D), out));
+      GItem<float> it = line_item(q, D, cur[q][D], rhs_of(q, D), out);
+      it.X = view<float>(c, D + 1);
+      it.c = cur[q][D + 1];
+      ps.push_back(it);
       cur[q][D] = out;
     }
-    emit(GKind::PROLONGATE, 0, pr);
-    emit_by_half(GKind::SMOOTH, sm);
+    emit_by_half(GKind::PROLONG_SMOOTH, ps);
   }
   for (int q = 0; q < b->npairs; ++q)
     if (cur[q][0] != b->pb[q].e32) return set_error(GMG_EINVAL, "internal: cycle output misplaced");

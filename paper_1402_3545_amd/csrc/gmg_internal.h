@@ -50,10 +50,11 @@ struct CgState {
 template <typename T>
 struct GItem {
   Lvl<T> L;      // level the kernel works on (resrestrict, prolongate: the FINE level)
-  Lvl<T> X;      // resrestrict, prolongate: the COARSE level
+  Lvl<T> X;      // resrestrict, prolongate, prolong-smooth: the COARSE level
   const T* a;    // line: rhs (solve) or u (smooth); resrestrict: u; prolongate: u_c
   const T* b;    // smooth, resrestrict: f
   T* o;          // line: output; resrestrict: f_c; prolongate: u_f (updated)
+  const T* c;    // prolong-smooth: u_c (a: u_f, b: f, o: the smoothed u_f + P u_c)
   int nti, ntj;  // tiles of the item
   int blk0;      // first workgroup of the item in its launch
   int pair;      // (instance, rhs) index: activity mask, partial-sum segment
@@ -251,7 +252,7 @@ hipError_t launch_transpose(const T* src, T* dst, int nx, int ny, int nz, int64_
 hipError_t launch_add_f32_to_f64(double* u, const float* e, int64_t n, hipStream_t s);
 
 // grouped launches (batched solves)
-enum class GKind { LINE_SOLVE = 0, SMOOTH = 1, RESRESTRICT = 2, PROLONGATE = 3 };
+enum class GKind { LINE_SOLVE = 0, SMOOTH = 1, RESRESTRICT = 2, PROLONGATE = 3, PROLONG_SMOOTH = 4 };
 hipError_t launch_grouped_f32(GKind kind, int half, const GItem<float>* items, int nitems,
                               int nblocks, const int* active, float rho, hipStream_t s);
 hipError_t launch_grouped_cr(const GItemCR* items, int nitems, int nblocks, const int* active,

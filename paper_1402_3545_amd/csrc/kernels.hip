@@ -218,6 +218,14 @@ template <typename T>
 __device__ __forceinline__ T ldn(const char* base, uint32_t off) {
   return __builtin_nontemporal_load(reinterpret_cast<const T*>(base + off));
 }
+// non-temporal load of a pair (double2 / float2) as one 16- or 8-byte access
+template <typename V>
+__device__ __forceinline__ V ldn2(const char* base, uint32_t off) {
+  using E = decltype(V{}.x);
+  typedef E N2 __attribute__((ext_vector_type(2)));
+  const N2 t = __builtin_nontemporal_load(reinterpret_cast<const N2*>(base + off));
+  return V{t.x, t.y};
+}
 template <typename T>
 __device__ __forceinline__ void sto(char* base, uint32_t off, T v) {
   if constexpr (std::is_arithmetic_v<T>)
@@ -381,6 +389,19 @@ __global__ __launch_bounds__(64 * SR) void k_stencil(Lvl<T> L, const T* __restri
     }
   }
   if constexpr (MODE >= (int)Stencil::RESIDUAL_NORM) block_partials<1, SR>(nrm, partials);
+}
+
+// u + (9 a + wb b + wc c + wd d) / 16: the cell-centred bilinear correction of
+// one fine cell from its coarse parent a, x and y neighbours b, c and diagonal
+// d, with the fused multiply-adds spelled out so that every kernel that forms
+// it (the prolongation, and the smoother that folds it in) rounds the same way.
+template <typename T>
+__device__ __forceinline__ T prolong_add(T u, T a, T b, T c, T d, T wb, T wc, T wd) {
+  T p = T(9) * a;
+  p = fma(wb, b, p);
+  p = fma(wc, c, p);
+  p = fma(wd, d, p);
+  return fma(p, T(0.0625), u);
 }
 
 // ---------------------------------------------------------------------------
@@ -651,14 +672,12 @@ __device__ __forceinline__ void line_body(const Lvl<T>& L, const LineArgs<T>& a,
     pe = slots(hi, hj);
   }
   // u + P u_c from the coarse stage (step t of the chunk, half h)
-  // (the same arithmetic, in the same order, as the prolongation kernel)
+  // (the prolongation kernel's arithmetic: prolong_add)
   auto corr = [&](uint32_t ps, int t, int h, T u) {
     const T* cs = s_cs + (t * 2 + h) * (CNR * CNW);
     const T sx = (ps & 0x8000u) ? T(-1) : T(1), sy = (ps & 0x800000u) ? T(-1) : T(1);
-    const T wb = T(3) * sx, wc = T(3) * sy, wd = sx * sy;
-    const T pp = T(9) * cs[ps & 0x7fu] + wb * cs[(ps >> 8) & 0x7fu] +
-                 wc * cs[(ps >> 16) & 0x7fu] + wd * cs[ps >> 24];
-    return u + pp * T(0.0625);
+    return prolong_add(u, cs[ps & 0x7fu], cs[(ps >> 8) & 0x7fu], cs[(ps >> 16) & 0x7fu],
+                       cs[ps >> 24], T(3) * sx, T(3) * sy, sx * sy);
   };
 
   // wave-uniform row bases
@@ -716,8 +735,8 @@ __device__ __forceinline__ void line_body(const Lvl<T>& L, const LineArgs<T>& a,
       v.f = ldn<T>(rB, o);
     } else if constexpr (MODE == LINE_RESTRICT_SMOOTH) {
       const uint32_t fo = (uint32_t)(2 * ic) * ES + kcl(k) * fkbytes;
-      v.lo = ldo<V2>(rF0, fo);
-      v.hi = ldo<V2>(rF1, fo);
+      v.lo = ldn2<V2>(rF0, fo);
+      v.hi = ldn2<V2>(rF1, fo);
     } else {
       v.r = ldn<T>(rW, o);
       v.q = ldn<T>(rA, o);
@@ -1076,8 +1095,8 @@ struct ResRestrictPol {
     v.uEd = ldo<T>(rc, oe + ok);
     v.sS = ldo<V2>(rS, o2 + ok);
     v.sN = ldo<V2>(rN, o2 + ok);
-    v.f0 = ldo<V2>(fa, o2 + ok);
-    v.f1 = ldo<V2>(fb, o2 + ok);
+    v.f0 = ldn2<V2>(fa, o2 + ok);
+    v.f1 = ldn2<V2>(fb, o2 + ok);
   }
   __device__ __forceinline__ void step(int s, const In& v) {
     const int k = k0 + s;
@@ -1225,7 +1244,7 @@ struct CorrectPol {
     v.en = ldo<float>(ren, oc4 + o4);
     v.us = ldo<double>(rus, oc8 + o8);
     v.es = ldo<float>(res, oc4 + o4);
-    v.f = ldo<double>(rf, oc8 + o8);
+    v.f = ldn<double>(rf, oc8 + o8);
   }
   __device__ __forceinline__ void step(int s, const In& v) {
     const int k = k0 + s;
@@ -1329,8 +1348,8 @@ struct ProlongPol {
     v.u = ldn<T>(rf, of + layer_off<FULL>(k, nz, fkb));
   }
   __device__ __forceinline__ void step(int s, const In& v) {
-    const T p = T(9) * v.a + wb * v.b + wc * v.c + wd * v.d;
-    sto<T>(rf, of + layer_off<FULL>(k0 + s, nz, fkb), v.u + p * T(0.0625));
+    sto<T>(rf, of + layer_off<FULL>(k0 + s, nz, fkb),
+           prolong_add(v.u, v.a, v.b, v.c, v.d, wb, wc, wd));
   }
 };
 
@@ -1681,7 +1700,13 @@ __global__ __launch_bounds__(NTHREADS) void k_line_grouped(const GItem<float>* _
   a.b = it.b;
   a.o0 = it.o;
   a.rho = rho;
-  line_body<float, HALF, MODE>(it.L, a, it.nti, it.ntj, 0, B - it.blk0);
+  if constexpr (MODE == LINE_PROLONG_SMOOTH) {
+    a.C = it.X;
+    a.uc = it.c;
+    line_body<float, HALF, MODE, true>(it.L, a, it.nti, it.ntj, 0, B - it.blk0);
+  } else {
+    line_body<float, HALF, MODE>(it.L, a, it.nti, it.ntj, 0, B - it.blk0);
+  }
 }
 
 __global__ __launch_bounds__(NTHREADS) void k_resrestrict_grouped(
@@ -1982,11 +2007,16 @@ hipError_t launch_grouped_f32(GKind kind, int half, const GItem<float>* items, i
   const dim3 grid(nblocks), block(NTHREADS);
   switch (kind) {
     case GKind::LINE_SOLVE:
-    case GKind::SMOOTH: {
+    case GKind::SMOOTH:
+    case GKind::PROLONG_SMOOTH: {
       const bool sm = kind == GKind::SMOOTH;
+      const bool ps = kind == GKind::PROLONG_SMOOTH;
 #define GMG_GLINE(H)                                                                         \
   if (half == H) {                                                                           \
-    if (sm)                                                                                  \
+    if (ps)                                                                                  \
+      hipLaunchKernelGGL((k_line_grouped<H, LINE_PROLONG_SMOOTH>), grid, block, 0, s, items, \
+                         nitems, active, rho);                                               \
+    else if (sm)                                                                             \
       hipLaunchKernelGGL((k_line_grouped<H, LINE_SMOOTH>), grid, block, 0, s, items, nitems, \
                          active, rho);                                                       \
     else                                                                                     \
