@@ -69,13 +69,13 @@ SOLVES = ("mg_f64", "pcg_f64", "mg_mixed", "fcg_mixed")
 MEASURED_TRAFFIC = {
     # k_cg_p1, 64x16 workgroups, tile groups of 8 (the stored launch shape);
     # profiles/cg_p1_1024x1024x128_pmc.md.  Plain-copy calibration: 2 GiB read
-    # + 2 GiB written read FETCH_SIZE 898803.5 KiB, WRITE_SIZE 2097240.8 KiB.
+    # + 2 GiB written read FETCH_SIZE 898802.1 KiB, WRITE_SIZE 2097242.3 KiB.
     ("cg_spmv", 0, "f64"): {
-        "fetch_kib": 2326915.4217,
-        "write_kib": 3145864.3472,
-        "copy_fetch_scale": 2097152.0 / 898803.5357,
-        "copy_write_scale": 2097152.0 / 2097240.7679,
-        "source_sha256": "3a6ccb7a36ae67388f9562a9b70b4f25ad6187e3d675ff4be0efde5f058ab174",
+        "fetch_kib": 2326838.1277,
+        "write_kib": 3145864.2301,
+        "copy_fetch_scale": 2097152.0 / 898802.0982,
+        "copy_write_scale": 2097152.0 / 2097242.2857,
+        "source_sha256": "3a5dec67f4e30b36e3bd12c6fd9940becd032c5caee12d0805f603058cf263b4",
         "shape": [16, 8],
     },
 }
