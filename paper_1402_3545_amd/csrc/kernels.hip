@@ -1746,9 +1746,22 @@ __device__ __forceinline__ void reduce_fixed(const double* __restrict__ partials
   double s[NC];
 #pragma unroll
   for (int c = 0; c < NC; ++c) s[c] = 0.0;
-  for (int64_t q = threadIdx.x; q < n; q += NTHREADS)
+  // each thread adds its partials in index order; the loads of a batch are
+  // issued together (the sums still run in the same order)
+  constexpr int BQ = 16;
+  for (int64_t q0 = threadIdx.x; q0 < n; q0 += (int64_t)BQ * NTHREADS) {
+    double v[BQ][NC];
 #pragma unroll
-    for (int c = 0; c < NC; ++c) s[c] += partials[q * NC + c];
+    for (int b = 0; b < BQ; ++b) {
+      const int64_t q = q0 + (int64_t)b * NTHREADS;
+#pragma unroll
+      for (int c = 0; c < NC; ++c) v[b][c] = q < n ? partials[q * NC + c] : 0.0;
+    }
+#pragma unroll
+    for (int b = 0; b < BQ; ++b)
+#pragma unroll
+      for (int c = 0; c < NC; ++c) s[c] += v[b][c];
+  }
 #pragma unroll
   for (int c = 0; c < NC; ++c) sm[c][threadIdx.x] = s[c];
   __syncthreads();
