@@ -67,16 +67,16 @@ SOLVES = ("mg_f64", "pcg_f64", "mg_mixed", "fcg_mixed")
 # dispatches) scaled by what the same counters read for a plain copy of known
 # size.  Reported only while the kernel source hashes to the recorded value.
 MEASURED_TRAFFIC = {
-    # k_cg_p1, 64x16 workgroups, tile groups of 8 (the stored launch shape);
+    # k_cg_p1, 64x16 workgroups, row-major tile order (the stored launch shape);
     # profiles/cg_p1_1024x1024x128_pmc.md.  Plain-copy calibration: 2 GiB read
-    # + 2 GiB written read FETCH_SIZE 898802.1 KiB, WRITE_SIZE 2097242.3 KiB.
+    # + 2 GiB written read FETCH_SIZE 898800.6 KiB, WRITE_SIZE 2097235.2 KiB.
     ("cg_spmv", 0, "f64"): {
-        "fetch_kib": 2326838.1277,
-        "write_kib": 3145864.2301,
-        "copy_fetch_scale": 2097152.0 / 898802.0982,
-        "copy_write_scale": 2097152.0 / 2097242.2857,
-        "source_sha256": "3a5dec67f4e30b36e3bd12c6fd9940becd032c5caee12d0805f603058cf263b4",
-        "shape": [16, 8],
+        "fetch_kib": 2285109.4668,
+        "write_kib": 3145863.0866,
+        "copy_fetch_scale": 2097152.0 / 898800.6429,
+        "copy_write_scale": 2097152.0 / 2097235.1786,
+        "source_sha256": "a8aa98bca0a8260d996213cd0dccd185cdcbb0507644915a930fec25d2d62037",
+        "shape": [16, 0],
     },
 }
 KERNEL_SOURCE = os.path.join(ROOT, "paper_1402_3545_amd", "csrc", "kernels.hip")
