@@ -626,13 +626,14 @@ int fcg_impl(gmg_ctx* c, const double* f, double* u, double rtol, int maxit, int
     HIP_TRY(timed(c, GMG_K_REDUCE, 0, GMG_F64, s,
                   [&] { return gmg::launch_fcg_fin(0, c->state, c->partials, nb, nullptr, s); }));
     HIP_TRY(timed(c, GMG_K_FCG, 0, GMG_F64, s, [&](gmg::Shape sh) {
-      return gmg::launch_fcg_dir<TZ>(V, z, c->vp, c->vq, c->vr, c->state, c->partials, &nb, s, sh);
+      return gmg::launch_fcg_dir<TZ>(V, z, u, c->vp, c->vq, c->vr, c->state, c->partials, &nb, s,
+                                     sh);
     }));
     HIP_TRY(timed(c, GMG_K_REDUCE, 0, GMG_F64, s,
                   [&] { return gmg::launch_fcg_fin(1, c->state, c->partials, nb, nullptr, s); }));
     HIP_TRY(timed(c, GMG_K_FCG, 0, GMG_F64, s, [&](gmg::Shape sh) {
-      return gmg::launch_fcg_update(V, u, c->vr, c->vp, c->vq, mixed ? c->er32 : nullptr,
-                                    c->state, c->partials, &nb, s, sh);
+      return gmg::launch_fcg_update(V, c->vr, c->vq, mixed ? c->er32 : nullptr, c->state,
+                                    c->partials, &nb, s, sh);
     }));
     HIP_TRY(timed(c, GMG_K_REDUCE, 0, GMG_F64, s,
                   [&] { return gmg::launch_fcg_fin(2, c->state, c->partials, nb, c->dhist, s); }));
@@ -640,6 +641,10 @@ int fcg_impl(gmg_ctx* c, const double* f, double* u, double rtol, int maxit, int
     HIP_TRY(hipStreamSynchronize(s));
     if (c->hstate->done) break;
   }
+  // the last step (the direction kernels apply each earlier one); skipped
+  // after a breakdown before the step
+  HIP_TRY(timed(c, GMG_K_AUX, 0, GMG_F64, s,
+                [&] { return gmg::launch_cg_final_update(V, u, c->vp, c->state, s); }));
   const CgState hs = *c->hstate;
   if (history)
     HIP_TRY(hipMemcpyAsync(history, c->dhist, (size_t)(hs.iter + 1) * sizeof(double),
@@ -845,13 +850,15 @@ int tune_solver(gmg_ctx* c, int reps, hipStream_t s, hipEvent_t ea, hipEvent_t e
       return st;
   }
   if ((st = tune_kind(c, GMG_K_FCG, 0, GMG_F64, Cand::STENCIL, nts, reps, s, ea, eb, [&](Shape sh) {
-         hipError_t e = mixed ? gmg::launch_fcg_dir<float>(V, c->eu32, c->vp, c->vq, c->vr,
-                                                            c->state, c->partials, &nb, s, sh)
-                              : gmg::launch_fcg_dir<double>(V, c->vz, c->vp, c->vq, c->vr,
-                                                             c->state, c->partials, &nb, s, sh);
+         // vt stands in for u (alpha = 0 writes it unchanged)
+         hipError_t e =
+             mixed ? gmg::launch_fcg_dir<float>(V, c->eu32, c->vt, c->vp, c->vq, c->vr, c->state,
+                                                c->partials, &nb, s, sh)
+                   : gmg::launch_fcg_dir<double>(V, c->vz, c->vt, c->vp, c->vq, c->vr, c->state,
+                                                 c->partials, &nb, s, sh);
          if (e != hipSuccess) return e;
-         return gmg::launch_fcg_update(V, c->vt, c->vr, c->vp, c->vq, mixed ? c->er32 : nullptr,
-                                       c->state, c->partials, &nb, s, sh);
+         return gmg::launch_fcg_update(V, c->vr, c->vq, mixed ? c->er32 : nullptr, c->state,
+                                       c->partials, &nb, s, sh);
        })))
     return st;
   return GMG_OK;

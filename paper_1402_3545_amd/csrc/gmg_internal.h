@@ -232,13 +232,15 @@ hipError_t launch_reduce(const double* partials, int64_t nblocks, int ncomp, dou
 template <typename TZ>
 hipError_t launch_fcg_zq(const Lvl<double>& L, const TZ* z, const double* q, double* partials,
                          int64_t* nblocks, hipStream_t s);
+// u += alpha_prev p_old; p = z + beta p; q = A z + beta q; <p,q>, <p,r>
 template <typename TZ>
-hipError_t launch_fcg_dir(const Lvl<double>& L, const TZ* z, double* p, double* q,
+hipError_t launch_fcg_dir(const Lvl<double>& L, const TZ* z, double* u, double* p, double* q,
                           const double* r, const CgState* st, double* partials, int64_t* nblocks,
                           hipStream_t s, Shape sh = {});
-hipError_t launch_fcg_update(const Lvl<double>& L, double* u, double* r, const double* p,
-                             const double* q, float* rdown, const CgState* st, double* partials,
-                             int64_t* nblocks, hipStream_t s, Shape sh = {});
+// r -= alpha q (+ FP32 copy), ||r||^2
+hipError_t launch_fcg_update(const Lvl<double>& L, double* r, const double* q, float* rdown,
+                             const CgState* st, double* partials, int64_t* nblocks,
+                             hipStream_t s, Shape sh = {});
 // which: 0 beta, 1 alpha, 2 residual / convergence
 hipError_t launch_fcg_fin(int which, CgState* st, const double* partials, int64_t nblocks,
                           double* hist, hipStream_t s);

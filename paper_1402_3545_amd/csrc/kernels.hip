@@ -1500,6 +1500,8 @@ __global__ __launch_bounds__(64 * SR) void k_cg_p1(Lvl<double> L, double* __rest
 // direction kept):  beta = -<z, q_old>/<p_old, q_old>,  p = z + beta p,
 // q = A z + beta q  (= A p),  alpha = <p, r>/<p, q>,  u += alpha p,
 // r -= alpha q.  z may be FP32 (mixed precision); everything else is FP64.
+// u += alpha p is deferred to the next direction kernel, which reads p anyway
+// (so the update kernel does not), and the last one to a final update.
 // ---------------------------------------------------------------------------
 template <typename TZ>
 __global__ __launch_bounds__(NTHREADS) void k_fcg_zq(Lvl<double> L, const TZ* __restrict__ z,
@@ -1528,13 +1530,13 @@ __global__ __launch_bounds__(NTHREADS) void k_fcg_zq(Lvl<double> L, const TZ* __
 template <typename TZ, bool FULL>
 struct FcgDirPol {
   struct In {
-    double xp, xe, xw, xn, xs, p, q, r;
+    double xp, xe, xw, xn, xs, p, q, r, u;
   };
   ColumnOp<double, TZ> op;  // on z
-  char *rp, *rq;
+  char *rp, *rq, *ru;
   const char* rr;
   uint32_t oc, kb;
-  double beta, pq, pr;
+  double beta, aprev, pq, pr;
 
   __device__ __forceinline__ void load(int s, In& v) {
     const int k = op.k0 + s;
@@ -1544,11 +1546,13 @@ struct FcgDirPol {
     v.p = ldn<double>(rp, o);
     v.q = ldn<double>(rq, o);
     v.r = ldn<double>(rr, o);
+    v.u = ldn<double>(ru, o);
   }
   __device__ __forceinline__ void step(int s, const In& v) {
     const uint32_t o = oc + layer_off<FULL>(op.k0 + s, op.nz, kb);
     const double zc = op.xc;
     const double az = op.apply(s, v.xp, v.xe, v.xw, v.xn, v.xs);
+    sto<double>(ru, o, v.u + aprev * v.p);  // the previous step, with its direction
     const double pn = zc + beta * v.p;
     const double qn = az + beta * v.q;
     sto<double>(rp, o, pn);
@@ -1558,15 +1562,19 @@ struct FcgDirPol {
   }
 };
 
+// The previous iteration's update of the iterate, u += alpha p, is applied
+// here, where the old direction is read anyway (alpha = 0 before the first
+// step); the last one after the loop.
 template <typename TZ, int SR>
 __global__ __launch_bounds__(64 * SR) void k_fcg_dir(Lvl<double> L, const TZ* __restrict__ z,
+                                                     double* __restrict__ u,
                                                      double* __restrict__ p,
                                                      double* __restrict__ q,
                                                      const double* __restrict__ r,
                                                      const CgState* __restrict__ st,
                                                      double* __restrict__ partials, int nti,
                                                      int ntj, int group) {
-  const double beta = st->beta;
+  const double beta = st->beta, aprev = st->alpha;
   const Geo g =
       stencil_geo<SR>(L.nx, L.ny, L.nz, nti, ntj, group, xcd_remap(blockIdx.x, gridDim.x));
   __shared__ Prof<double> sp[KSEG];
@@ -1581,9 +1589,11 @@ __global__ __launch_bounds__(64 * SR) void k_fcg_dir(Lvl<double> L, const TZ* __
       P.rp = roww(p, g.j, jst);
       P.rq = roww(q, g.j, jst);
       P.rr = rowc(r, g.j, jst);
+      P.ru = roww(u, g.j, jst);
       P.oc = (uint32_t)g.ic * 8;
       P.kb = (uint32_t)L.ldx * 8;
       P.beta = beta;
+      P.aprev = aprev;
       P.pq = 0.0;
       P.pr = 0.0;
       walk<2, FL>(P, g.n);
@@ -1601,10 +1611,10 @@ __global__ __launch_bounds__(64 * SR) void k_fcg_dir(Lvl<double> L, const TZ* __
 template <bool FULL>
 struct FcgUpdPol {
   struct In {
-    double u, r, p, q;
+    double r, q;
   };
-  char *ru, *rr;
-  const char *rp, *rq;
+  char* rr;
+  const char* rq;
   char* rd;  // FP32 copy of r (mixed precision) or null
   uint32_t oc, kb, oc4, kb4;
   int nz, k0;
@@ -1612,15 +1622,12 @@ struct FcgUpdPol {
 
   __device__ __forceinline__ void load(int s, In& v) {
     const uint32_t o = oc + layer_off<FULL>(k0 + s, nz, kb);
-    v.u = ldn<double>(ru, o);
     v.r = ldn<double>(rr, o);
-    v.p = ldn<double>(rp, o);
     v.q = ldn<double>(rq, o);
   }
   __device__ __forceinline__ void step(int s, const In& v) {
     const int kc = FULL ? k0 + s : min(k0 + s, nz - 1);
     const uint32_t o = oc + (uint32_t)kc * kb;
-    sto<double>(ru, o, v.u + alpha * v.p);
     const double rn = v.r - alpha * v.q;
     sto<double>(rr, o, rn);
     if (rd) sto<float>(rd, oc4 + (uint32_t)kc * kb4, (float)rn);
@@ -1628,10 +1635,10 @@ struct FcgUpdPol {
   }
 };
 
+// r -= alpha q (and its FP32 copy), ||r||^2; u is updated by the next
+// direction kernel (or after the loop)
 template <int SR>
-__global__ __launch_bounds__(64 * SR) void k_fcg_update(Lvl<double> L, double* __restrict__ u,
-                                                        double* __restrict__ r,
-                                                        const double* __restrict__ p,
+__global__ __launch_bounds__(64 * SR) void k_fcg_update(Lvl<double> L, double* __restrict__ r,
                                                         const double* __restrict__ q,
                                                         float* __restrict__ rdown,
                                                         const CgState* __restrict__ st,
@@ -1646,9 +1653,7 @@ __global__ __launch_bounds__(64 * SR) void k_fcg_update(Lvl<double> L, double* _
     auto run = [&](auto full) {
       constexpr bool FL = decltype(full)::value;
       FcgUpdPol<FL> P;
-      P.ru = roww(u, g.j, jst);
       P.rr = roww(r, g.j, jst);
-      P.rp = rowc(p, g.j, jst);
       P.rq = rowc(q, g.j, jst);
       P.rd = rdown ? roww(rdown, g.j, jst) : nullptr;
       P.oc = (uint32_t)g.ic * 8;
@@ -2262,27 +2267,27 @@ hipError_t launch_fcg_zq(const Lvl<double>& L, const TZ* z, const double* q, dou
 }
 
 template <typename TZ>
-hipError_t launch_fcg_dir(const Lvl<double>& L, const TZ* z, double* p, double* q,
+hipError_t launch_fcg_dir(const Lvl<double>& L, const TZ* z, double* u, double* p, double* q,
                           const double* r, const CgState* st, double* partials, int64_t* nblocks,
                           hipStream_t s, Shape sh) {
   return with_rows(sh.rows, [&](auto R) {
     constexpr int SR = decltype(R)::value;
     const int nti = cdiv(L.nx, 64), ntj = cdiv(L.ny, SR), nkb = cdiv(L.nz, KSEG);
     *nblocks = (int64_t)nti * ntj * nkb;
-    hipLaunchKernelGGL((k_fcg_dir<TZ, SR>), dim3(nti * ntj * nkb), dim3(64 * SR), 0, s, L, z, p,
-                       q, r, st, partials, nti, ntj, sh.group);
+    hipLaunchKernelGGL((k_fcg_dir<TZ, SR>), dim3(nti * ntj * nkb), dim3(64 * SR), 0, s, L, z, u,
+                       p, q, r, st, partials, nti, ntj, sh.group);
   });
 }
 
-hipError_t launch_fcg_update(const Lvl<double>& L, double* u, double* r, const double* p,
-                             const double* q, float* rdown, const CgState* st, double* partials,
-                             int64_t* nblocks, hipStream_t s, Shape sh) {
+hipError_t launch_fcg_update(const Lvl<double>& L, double* r, const double* q, float* rdown,
+                             const CgState* st, double* partials, int64_t* nblocks,
+                             hipStream_t s, Shape sh) {
   return with_rows(sh.rows, [&](auto R) {
     constexpr int SR = decltype(R)::value;
     const int nti = cdiv(L.nx, 64), ntj = cdiv(L.ny, SR), nkb = cdiv(L.nz, KSEG);
     *nblocks = (int64_t)nti * ntj * nkb;
-    hipLaunchKernelGGL(k_fcg_update<SR>, dim3(nti * ntj * nkb), dim3(64 * SR), 0, s, L, u, r, p,
-                       q, rdown, st, partials, nti, ntj, sh.group);
+    hipLaunchKernelGGL(k_fcg_update<SR>, dim3(nti * ntj * nkb), dim3(64 * SR), 0, s, L, r, q,
+                       rdown, st, partials, nti, ntj, sh.group);
   });
 }
 
@@ -2303,11 +2308,11 @@ template hipError_t launch_fcg_zq<double>(const Lvl<double>&, const double*, con
 template hipError_t launch_fcg_zq<float>(const Lvl<double>&, const float*, const double*,
                                          double*, int64_t*, hipStream_t);
 template hipError_t launch_fcg_dir<double>(const Lvl<double>&, const double*, double*, double*,
-                                           const double*, const CgState*, double*, int64_t*,
-                                           hipStream_t, Shape);
+                                           double*, const double*, const CgState*, double*,
+                                           int64_t*, hipStream_t, Shape);
 template hipError_t launch_fcg_dir<float>(const Lvl<double>&, const float*, double*, double*,
-                                          const double*, const CgState*, double*, int64_t*,
-                                          hipStream_t, Shape);
+                                          double*, const double*, const CgState*, double*,
+                                          int64_t*, hipStream_t, Shape);
 
 hipError_t launch_cg_fin1(CgState* st, const double* partials, int64_t nblocks, hipStream_t s) {
   hipLaunchKernelGGL(k_cg_fin1, dim3(1), dim3(NTHREADS), 0, s, st, partials, nblocks);
