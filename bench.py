@@ -67,16 +67,16 @@ SOLVES = ("mg_f64", "pcg_f64", "mg_mixed", "fcg_mixed")
 # dispatches) scaled by what the same counters read for a plain copy of known
 # size.  Reported only while the kernel source hashes to the recorded value.
 MEASURED_TRAFFIC = {
-    # k_cg_p1, 64x16 workgroups, row-major tile order (the stored launch shape);
+    # k_cg_p1, 64x16 workgroups, tile groups of 8 (the stored launch shape);
     # profiles/cg_p1_1024x1024x128_pmc.md.  Plain-copy calibration: 2 GiB read
-    # + 2 GiB written read FETCH_SIZE 898800.6 KiB, WRITE_SIZE 2097235.2 KiB.
+    # + 2 GiB written read FETCH_SIZE 898801.8 KiB, WRITE_SIZE 2097233.4 KiB.
     ("cg_spmv", 0, "f64"): {
-        "fetch_kib": 2285109.4668,
-        "write_kib": 3145863.0866,
-        "copy_fetch_scale": 2097152.0 / 898800.6429,
-        "copy_write_scale": 2097152.0 / 2097235.1786,
-        "source_sha256": "a8aa98bca0a8260d996213cd0dccd185cdcbb0507644915a930fec25d2d62037",
-        "shape": [16, 0],
+        "fetch_kib": 2326928.1157,
+        "write_kib": 3145864.4022,
+        "copy_fetch_scale": 2097152.0 / 898801.8125,
+        "copy_write_scale": 2097152.0 / 2097233.3929,
+        "source_sha256": "92aaf1009f55de1f251835195f95a0e6fb9e035dd8e288e03e2bbae2541520fb",
+        "shape": [16, 8],
     },
 }
 KERNEL_SOURCE = os.path.join(ROOT, "paper_1402_3545_amd", "csrc", "kernels.hip")
