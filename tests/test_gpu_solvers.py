@@ -244,3 +244,22 @@ def test_mg_with_staged_smoother_on_every_level(prec_precond):
         assert it <= it_ref + 2
     u = ctx.from_device(ud)
     assert orc.residual_norm2_rows(f, u) ** 0.5 / np.linalg.norm(f) < 1e-8
+
+
+@pytest.mark.parametrize("precond", [1, 2])
+@pytest.mark.parametrize("maxit", [1, 2, 5])
+def test_flexible_cg_stopped_early_returns_its_last_iterate(precond, maxit):
+    """The flexible CG applies each step's u += alpha p one kernel later (and
+    the last one after the loop): stopped after `maxit` iterations, the
+    returned u must be the maxit-th iterate, whose true residual equals the
+    recursively updated one of the same iteration."""
+    import paper_1402_3545_amd as G
+    w, ctx, orc = _small()
+    f = w.rhs()
+    fd, ud = ctx.to_device(f), ctx.empty()
+    it, rel, hist, st = G.pcg_solve(ctx, fd, ud, rtol=1e-14, maxit=maxit, precond=precond,
+                                    check=False)
+    assert st == G.GMG_ENOCONV and it == maxit
+    true_rel = orc.residual_norm2_rows(f, ctx.from_device(ud)) ** 0.5 / np.linalg.norm(f)
+    assert true_rel == pytest.approx(hist[maxit], rel=1e-6)
+    assert true_rel == pytest.approx(rel, rel=1e-9)
