@@ -219,6 +219,15 @@ int gmg_timing_read(gmg_ctx *c, int kernel, int level, int prec, int64_t *count,
  * overhead to the others.  Takes effect for launches after the call. */
 int gmg_timing_filter(gmg_ctx *c, uint32_t kernel_mask);
 
+/* A plain streaming copy of `bytes` bytes (a multiple of 8) from src to dst,
+ * device arrays owned by the caller, 16-byte aligned and not overlapping:
+ * the achievable-copy ceiling that the kernels' HBM bandwidth is judged
+ * against (Sec. 5 reports bandwidth as a fraction of the hardware's; a copy
+ * shows what a read + write stream reaches on this GPU).  8-byte
+ * non-temporal loads and stores, grid-stride.  Asynchronous on `stream`.
+ * GMG_EINVAL for NULL or unaligned pointers, a bad size, or overlap. */
+int gmg_copy_probe(const void *src, void *dst, int64_t bytes, void *stream);
+
 /* Layout conversion of one field on the device between the canonical
  * z-contiguous order (j*nx + i)*nz + k -- the order of the caller's host data
  * and of the synthetic inputs -- and the x-contiguous order of

@@ -29,7 +29,7 @@ EXPORTS = ("gmg_default_params", "gmg_setup", "gmg_destroy", "gmg_field_layout",
            "gmg_batch_solve", "gmg_timing_enable", "gmg_timing_read", "gmg_timing_filter",
            "gmg_set_launch",
            "gmg_get_launch", "gmg_autotune", "gmg_transpose_in", "gmg_transpose_out",
-           "gmg_solve_host", "gmg_last_error")
+           "gmg_solve_host", "gmg_copy_probe", "gmg_last_error")
 
 # kernel ids of the timing facility (gmg_kernel in include/gmg.h)
 KERNELS = ("spmv", "residual", "line_solve", "smooth", "restrict_smooth", "prolongate",
@@ -98,6 +98,7 @@ def _load():
         "gmg_get_launch": (i32, [vp, i32, i32, i32, intp, intp]),
         "gmg_autotune": (i32, [vp, i32, vp]),
         "gmg_transpose_in": (i32, [vp, i32, i32, vp, vp, vp]),
+        "gmg_copy_probe": (i32, [vp, vp, C.c_int64, vp]),
         "gmg_transpose_out": (i32, [vp, i32, i32, vp, vp, vp]),
         "gmg_solve_host": (i32, [vp, i32, vp, vp, dbl, i32, intp, dblp, dblp, vp]),
         "gmg_last_error": (C.c_char_p, []),
@@ -507,6 +508,17 @@ def tuned(ctx, reps=3, path=LAUNCH_TABLE, stream=None):
 def _prec_of(t):
     import torch
     return GMG_F64 if t.dtype == torch.float64 else GMG_F32
+
+
+def gmg_copy_probe(src, dst, stream=None):
+    """Plain streaming copy of a device tensor into another of the same size
+    (the bandwidth ceiling the kernels are judged against)."""
+    if src.numel() * src.element_size() != dst.numel() * dst.element_size():
+        raise ValueError("src and dst must have the same size in bytes")
+    if src.numel() == 0:
+        return  # (empty tensors carry no device pointer)
+    _check(_lib.gmg_copy_probe(src.data_ptr(), dst.data_ptr(),
+                               src.numel() * src.element_size(), _stream(stream)))
 
 
 def gmg_transpose_in(ctx, level, src_z, dst_x, stream=None):

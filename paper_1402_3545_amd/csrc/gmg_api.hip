@@ -910,6 +910,17 @@ int gmg_timing_read(gmg_ctx* c, int kernel, int level, int prec, int64_t* count,
   return GMG_OK;
 }
 
+int gmg_copy_probe(const void* src, void* dst, int64_t bytes, void* stream) {
+  int st;
+  if ((st = check_ptrs({src, dst}))) return st;
+  if (bytes < 0 || bytes % 8) return fail(GMG_EINVAL, "copy: bytes must be a multiple of 8");
+  const char *a = static_cast<const char*>(src), *b = static_cast<const char*>(dst);
+  if (a < b + bytes && b < a + bytes) return fail(GMG_EINVAL, "copy: src and dst overlap");
+  HIP_TRY(gmg::launch_copy_probe(static_cast<const double*>(src), static_cast<double*>(dst),
+                                 bytes / 8, as_stream(stream)));
+  return GMG_OK;
+}
+
 int gmg_transpose_in(gmg_ctx* c, int level, int prec, const void* src_z, void* dst_x,
                      void* stream) {
   if (!level_ok(c, level)) return fail(GMG_EINVAL, "bad context or level %d", level);

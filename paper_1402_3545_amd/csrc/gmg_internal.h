@@ -247,6 +247,8 @@ hipError_t launch_fcg_fin(int which, CgState* st, const double* partials, int64_
 
 template <typename T>
 hipError_t launch_fill(T* p, int64_t n, T v, hipStream_t s);
+// streaming copy of n doubles (bandwidth measurement)
+hipError_t launch_copy_probe(const double* src, double* dst, int64_t n, hipStream_t s);
 // canonical z-contiguous (j*nx+i)*nz+k <-> x-contiguous (j*nz+k)*ldx+i
 template <typename T>
 hipError_t launch_transpose(const T* src, T* dst, int nx, int ny, int nz, int64_t ldx,

@@ -77,4 +77,21 @@ template hipError_t launch_transpose<double>(const double*, double*, int, int, i
 template hipError_t launch_transpose<float>(const float*, float*, int, int, int, int64_t, bool,
                                             hipStream_t);
 
+// Streaming copy for measuring the achievable HBM bandwidth: 8-byte
+// non-temporal loads and stores, grid-stride, 1024-thread workgroups (up to
+// 16384 of them), the fastest plain-copy form measured on gfx950.
+__global__ __launch_bounds__(1024) void k_copy_probe(const double* __restrict__ src,
+                                                     double* __restrict__ dst, int64_t n) {
+  const int64_t stride = (int64_t)gridDim.x * 1024;
+  for (int64_t g = (int64_t)blockIdx.x * 1024 + threadIdx.x; g < n; g += stride)
+    __builtin_nontemporal_store(__builtin_nontemporal_load(src + g), dst + g);
+}
+
+hipError_t launch_copy_probe(const double* src, double* dst, int64_t n, hipStream_t s) {
+  const int64_t blocks = std::min<int64_t>(16384, (n + 1023) / 1024);
+  if (blocks <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_copy_probe, dim3((unsigned)blocks), dim3(1024), 0, s, src, dst, n);
+  return hipGetLastError();
+}
+
 }  // namespace gmg

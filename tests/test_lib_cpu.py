@@ -80,3 +80,13 @@ def test_null_context_is_rejected():
     assert G._lib.gmg_autotune(None, 3, None) == G.GMG_EINVAL
     assert G._lib.gmg_timing_filter(None, 1) == G.GMG_EINVAL
     assert G._lib.gmg_destroy(None) == G.GMG_OK
+
+
+def test_copy_probe_validation():
+    import paper_1402_3545_amd as G
+    lib = G._lib
+    assert lib.gmg_copy_probe(None, None, 8, None) == -1
+    assert lib.gmg_copy_probe(C.c_void_p(0x1000), C.c_void_p(0x2000), 12, None) == -1  # not 8k
+    assert lib.gmg_copy_probe(C.c_void_p(0x1000), C.c_void_p(0x2000), -8, None) == -1
+    assert lib.gmg_copy_probe(C.c_void_p(0x1008), C.c_void_p(0x2000), 8, None) == -1  # align
+    assert lib.gmg_copy_probe(C.c_void_p(0x1000), C.c_void_p(0x1010), 64, None) == -1  # overlap
