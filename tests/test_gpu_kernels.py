@@ -228,21 +228,25 @@ def test_line_kernels_by_cyclic_reduction(shape, prec):
 
 @pytest.mark.parametrize("bc_h", [0, 1])
 @pytest.mark.parametrize("prec", [0, 1])
-@pytest.mark.parametrize("shape", SHAPES + [(1, 1, 8), (3, 3, 5), (65, 9, 3)])
+@pytest.mark.parametrize("shape", SHAPES + [(2, 2, 8), (3, 3, 5), (65, 9, 3)])
 def test_line_smooth_with_staged_neighbours(shape, prec, bc_h):
     """The smoother with its horizontal neighbours staged in LDS by the
     workgroup (launch shape rows = 2): same bars as the per-lane loads, also
-    on grids narrower than a tile and with walls."""
+    on grids narrower than a tile, with walls, and (2 x 2 grids) on a coarse
+    level of a single column."""
     import paper_1402_3545_amd as G
     nx, ny, nz = shape
-    if nx < 2 or ny < 2:
-        pytest.skip("the finest grid needs two columns per direction")
-    ctx, orc, _ = problem(nx, ny, nz, seed=7, bc_h=bc_h)
+    one_col = (nx, ny) == (2, 2)
+    L = 2 if one_col else 1
+    lvl = L - 1
+    ctx, orc, _ = problem(nx, ny, nz, nlevels=L, seed=7, bc_h=bc_h)
     for p in (G.GMG_F64, G.GMG_F32):
-        G.gmg_set_launch(ctx, "smooth", 0, p, 2, 0)
-    u, f = _inputs(nx * ny * nz, 14, prec)
-    ud, fd = ctx.to_device(u, dtype=_dtype(prec)), ctx.to_device(f, dtype=_dtype(prec))
-    G.line_smooth(ctx, 0, fd, ud, nsweeps=2)
-    ref = orc.smooth(f, orc.smooth(f, u))
+        G.gmg_set_launch(ctx, "smooth", lvl, p, 2, 0)
+    n = (nx >> lvl) * (ny >> lvl) * nz
+    u, f = _inputs(n, 14, prec)
+    ud = ctx.to_device(u, lvl, dtype=_dtype(prec))
+    fd = ctx.to_device(f, lvl, dtype=_dtype(prec))
+    G.line_smooth(ctx, lvl, fd, ud, nsweeps=2)
+    ref = orc.smooth(f, orc.smooth(f, u, depth=lvl), depth=lvl)
     bar = F64 if prec == 0 else f32_line_bar(nz)
-    assert max_rel(ctx.from_device(ud), ref, np.abs(ref).max()) < 2 * bar
+    assert max_rel(ctx.from_device(ud, lvl), ref, np.abs(ref).max()) < 2 * bar
