@@ -374,6 +374,57 @@ def test_prolongation_reproduces_bilinear_functions():
     assert np.allclose(one, 1.0, rtol=0, atol=1e-15)
 
 
+@pytest.mark.parametrize("nx,ny", [(12, 8), (8, 8), (4, 6)])
+def test_prolongation_is_translation_equivariant_on_periodic_grids(nx, ny):
+    """On a doubly periodic grid every coarse cell is like every other, so the
+    prolongation commutes with translations: shifting the coarse field by s
+    cells moves the fine output by 2s cells.  The check covers every fine cell,
+    in particular the first and last columns and rows whose coarse stencils
+    wrap round (Sec. 2.2, cell-centred interpolation; periodic grid of the
+    workloads).  The same weights meet the same values in the same order, so
+    the equality is bitwise."""
+    nz = 3
+    p = oracle.OracleProblem(nx, ny, nz, 2)
+    ncx, ncy = nx // 2, ny // 2
+    uc = W.uniform_pm1(5, 1, ncx * ncy * nz).reshape(ncy, ncx, nz)
+    zero = np.zeros(nx * ny * nz)
+    base = p.prolongate_add(uc.reshape(-1), zero).reshape(ny, nx, nz)
+    for sx, sy in [(1, 0), (0, 1), (1, 1), (ncx - 1, 0), (0, ncy - 1), (ncx - 1, ncy - 1)]:
+        moved = np.roll(uc, (sy, sx), axis=(0, 1))
+        out = p.prolongate_add(moved.reshape(-1), zero).reshape(ny, nx, nz)
+        assert np.array_equal(out, np.roll(base, (2 * sy, 2 * sx), axis=(0, 1))), (sx, sy)
+
+
+def test_prolongation_fourier_symbol_on_periodic_grids():
+    """Closed form of the periodic prolongation on a Fourier mode.  For the coarse
+    field Re exp(i(tx I + ty J + phi)) the 1D interpolation gives its child on the
+    side s = -1 (even fine index) or s = +1 (odd) the factor (3 + exp(i s t)) / 4,
+    and the 9/3/3/1 stencil over 16 is the product of the two 1D factors.  With
+    t = 2 pi m / n_c the mode is periodic, so the formula holds at every fine cell,
+    including those whose coarse neighbour lies across the wrap."""
+    nx, ny, nz = 16, 12, 2
+    p = oracle.OracleProblem(nx, ny, nz, 2)
+    ncx, ncy = nx // 2, ny // 2
+    I = np.arange(ncx)[None, :]
+    J = np.arange(ncy)[:, None]
+    i = np.arange(nx)[None, :]
+    j = np.arange(ny)[:, None]
+    zero = np.zeros(nx * ny * nz)
+    for mx, my in [(1, 0), (0, 1), (1, 1), (3, 2), (ncx - 1, 1), (ncx // 2, ncy // 2)]:
+        tx, ty = 2 * math.pi * mx / ncx, 2 * math.pi * my / ncy
+        phases = [0.3, 1.9]
+        uc = np.stack([np.cos(tx * I + ty * J + ph) for ph in phases], axis=-1)
+        out = p.prolongate_add(uc.reshape(-1), zero).reshape(ny, nx, nz)
+        sx = np.where(i % 2 == 1, 1.0, -1.0)
+        sy = np.where(j % 2 == 1, 1.0, -1.0)
+        gx = (3.0 + np.exp(1j * sx * tx)) / 4.0
+        gy = (3.0 + np.exp(1j * sy * ty)) / 4.0
+        for k, ph in enumerate(phases):
+            mode = np.exp(1j * (tx * (i // 2) + ty * (j // 2) + ph))
+            ref = np.real(mode * gx * gy)
+            assert np.allclose(out[..., k], ref, rtol=0, atol=1e-14), (mx, my, k)
+
+
 # ---------------------------------------------------------------------------
 # Smoothers, V-cycle, solvers
 # ---------------------------------------------------------------------------
