@@ -130,13 +130,50 @@ def _ptr(t):
     return C.c_void_p(t.data_ptr())
 
 
-def _prec(t) -> int:
+_DTYPE_NAME = {GMG_F64: "float64", GMG_F32: "float32"}
+
+
+def _field(ctx, t, name, level=0, prec=None, elems=None):
+    """Check one caller field before its pointer goes to the C ABI, which takes
+    no lengths: a torch tensor on the context's GPU, contiguous, of the expected
+    element type (prec; None = float64 or float32), holding at least the level's
+    padded element count (gmg_field_layout; or `elems`).  Raises ValueError, so
+    a misfit never reaches a kernel.  Returns the precision code."""
     import torch
+    if not isinstance(t, torch.Tensor):
+        raise ValueError(f"{name}: expected a torch tensor, got {type(t).__name__}")
     if t.dtype == torch.float64:
-        return GMG_F64
-    if t.dtype == torch.float32:
-        return GMG_F32
-    raise TypeError(f"fields must be float64 or float32, got {t.dtype}")
+        got = GMG_F64
+    elif t.dtype == torch.float32:
+        got = GMG_F32
+    else:
+        raise ValueError(f"{name}: must be float64 or float32, got {t.dtype}")
+    if prec is not None and got != prec:
+        raise ValueError(f"{name}: must be {_DTYPE_NAME[prec]}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name}: must be contiguous")
+    need = ctx.layout(level)[1] if elems is None else int(elems)
+    if t.numel() < need:
+        raise ValueError(f"{name}: holds {t.numel()} elements, level {level} needs {need} "
+                         "(the padded layout of gmg_field_layout)")
+    if not t.is_cuda:
+        raise ValueError(f"{name}: must be a GPU tensor (device {t.device})")
+    dev = getattr(ctx, "device", None)
+    if dev is not None and t.device.index != dev:
+        raise ValueError(f"{name}: on cuda:{t.device.index}, the context lives on cuda:{dev}")
+    return got
+
+
+def _fields(ctx, spec, prec=None):
+    """_field over (tensor, name, level) triples that must share one precision."""
+    for t, name, level in spec:
+        prec = _field(ctx, t, name, level, prec)
+    return prec
+
+
+def _distinct(a, b, what):
+    if a.data_ptr() == b.data_ptr():
+        raise ValueError(f"{what} must not be the same buffer")
 
 
 class GmgContext:
@@ -164,6 +201,8 @@ class GmgContext:
             keep.append(k)
             p.kh = k.ctypes.data_as(C.POINTER(C.c_double))
         h = C.c_void_p()
+        import torch
+        self.device = torch.cuda.current_device() if torch.cuda.is_available() else None
         _check(_lib.gmg_setup(C.byref(p), _stream(stream), C.byref(h)))
         self._h = h
         self.nx, self.ny, self.nz, self.nlevels = p.nx, p.ny, p.nz, p.nlevels
@@ -249,6 +288,8 @@ class GmgBatch:
         for q, kw in enumerate(instances):
             arr[q] = _params(keep=keep, **kw)
         h = C.c_void_p()
+        import torch
+        self.device = torch.cuda.current_device() if torch.cuda.is_available() else None
         _check(_lib.gmg_batch_setup(arr, len(instances), int(nrhs), _stream(stream),
                                     C.byref(h)))
         self._h = h
@@ -306,6 +347,11 @@ def gmg_batch_solve(batch, fs, us, rtol=1e-8, maxit=100, stream=None, check=True
     n = batch.ninst * batch.nrhs
     if len(fs) != n or len(us) != n:
         raise ValueError(f"need {n} right-hand sides and solutions")
+    for q in range(n):
+        inst = q // batch.nrhs
+        elems = batch.layout(inst)[1]
+        _field(batch, fs[q], f"f[{q}]", prec=GMG_F64, elems=elems)
+        _field(batch, us[q], f"u[{q}]", prec=GMG_F64, elems=elems)
     fp = (C.c_void_p * n)(*[t.data_ptr() for t in fs])
     up = (C.c_void_p * n)(*[t.data_ptr() for t in us])
     it = np.zeros(n, dtype=np.int32)
@@ -330,44 +376,66 @@ def gmg_field_layout(ctx: GmgContext, level=0):
     return ctx.layout(level)
 
 
+def _level(ctx, level, lo=0):
+    level = int(level)
+    if not lo <= level < ctx.nlevels:
+        raise ValueError(f"level {level} outside [{lo}, {ctx.nlevels - 1}]")
+    return level
+
+
 def spmv(ctx, level, x, y, stream=None):
-    _check(_lib.spmv(ctx.handle, int(level), _prec(x), _ptr(x), _ptr(y), _stream(stream)))
+    level = _level(ctx, level)
+    prec = _fields(ctx, [(x, "x", level), (y, "y", level)])
+    _distinct(x, y, "x and y")
+    _check(_lib.spmv(ctx.handle, level, prec, _ptr(x), _ptr(y), _stream(stream)))
 
 
 def line_solve(ctx, level, r, z, stream=None):
-    _check(_lib.line_solve(ctx.handle, int(level), _prec(r), _ptr(r), _ptr(z), _stream(stream)))
+    level = _level(ctx, level)
+    prec = _fields(ctx, [(r, "r", level), (z, "z", level)])
+    _check(_lib.line_solve(ctx.handle, level, prec, _ptr(r), _ptr(z), _stream(stream)))
 
 
 def line_smooth(ctx, level, f, u, nsweeps=1, rho=None, stream=None):
+    level = _level(ctx, level)
+    prec = _fields(ctx, [(f, "f", level), (u, "u", level)])
     rho = ctx.rho if rho is None else float(rho)
-    _check(_lib.line_smooth(ctx.handle, int(level), _prec(u), _ptr(f), _ptr(u), int(nsweeps), rho,
+    _check(_lib.line_smooth(ctx.handle, level, prec, _ptr(f), _ptr(u), int(nsweeps), rho,
                             _stream(stream)))
 
 
 def gmg_residual(ctx, level, f, u, r, norm=False, stream=None):
+    level = _level(ctx, level)
+    prec = _fields(ctx, [(f, "f", level), (u, "u", level), (r, "r", level)])
     out = C.c_double()
-    _check(_lib.gmg_residual(ctx.handle, int(level), _prec(u), _ptr(f), _ptr(u), _ptr(r),
+    _check(_lib.gmg_residual(ctx.handle, level, prec, _ptr(f), _ptr(u), _ptr(r),
                              C.byref(out) if norm else None, _stream(stream)))
     return out.value if norm else None
 
 
 def gmg_restrict_smooth(ctx, level, rf, fc, uc, rho=None, stream=None):
+    level = _level(ctx, level, lo=1)
+    prec = _fields(ctx, [(rf, "rf", level - 1), (fc, "fc", level), (uc, "uc", level)])
     rho = ctx.rho if rho is None else float(rho)
-    _check(_lib.gmg_restrict_smooth(ctx.handle, int(level), _prec(rf), _ptr(rf), _ptr(fc),
+    _check(_lib.gmg_restrict_smooth(ctx.handle, level, prec, _ptr(rf), _ptr(fc),
                                     _ptr(uc), rho, _stream(stream)))
 
 
 def gmg_prolongate(ctx, level, uc, uf, stream=None):
-    _check(_lib.gmg_prolongate(ctx.handle, int(level), _prec(uc), _ptr(uc), _ptr(uf),
+    level = _level(ctx, level, lo=1)
+    prec = _fields(ctx, [(uc, "uc", level), (uf, "uf", level - 1)])
+    _check(_lib.gmg_prolongate(ctx.handle, level, prec, _ptr(uc), _ptr(uf),
                                _stream(stream)))
 
 
 def gmg_vcycle(ctx, f, u, stream=None):
+    _fields(ctx, [(f, "f", 0), (u, "u", 0)], prec=ctx.prec_precond)
     _check(_lib.gmg_vcycle(ctx.handle, _ptr(f), _ptr(u), _stream(stream)))
 
 
 def gmg_solve(ctx, f, u, rtol=1e-8, maxit=100, stream=None, check=True):
     """Returns (iters, relres, history, status)."""
+    _fields(ctx, [(f, "f", 0), (u, "u", 0)], prec=GMG_F64)
     it, rel = C.c_int(), C.c_double()
     hist = np.zeros(maxit + 1)
     st = _lib.gmg_solve(ctx.handle, _ptr(f), _ptr(u), float(rtol), int(maxit), C.byref(it),
@@ -379,6 +447,7 @@ def gmg_solve(ctx, f, u, rtol=1e-8, maxit=100, stream=None, check=True):
 
 def pcg_solve(ctx, f, u, rtol=1e-8, maxit=1000, precond=0, stream=None, check=True):
     """Returns (iters, true relres, recursive history, status)."""
+    _fields(ctx, [(f, "f", 0), (u, "u", 0)], prec=GMG_F64)
     it, rel = C.c_int(), C.c_double()
     hist = np.zeros(maxit + 1)
     st = _lib.pcg_solve(ctx.handle, _ptr(f), _ptr(u), float(rtol), int(maxit), int(precond),
@@ -505,14 +574,13 @@ def tuned(ctx, reps=3, path=LAUNCH_TABLE, stream=None):
 # ---------------------------------------------------------------------------
 # Layout conversion and host-memory solves
 # ---------------------------------------------------------------------------
-def _prec_of(t):
-    import torch
-    return GMG_F64 if t.dtype == torch.float64 else GMG_F32
-
-
 def gmg_copy_probe(src, dst, stream=None):
     """Plain streaming copy of a device tensor into another of the same size
     (the bandwidth ceiling the kernels are judged against)."""
+    import torch
+    for t, name in ((src, "src"), (dst, "dst")):
+        if not isinstance(t, torch.Tensor) or not t.is_cuda or not t.is_contiguous():
+            raise ValueError(f"{name} must be a contiguous GPU tensor")
     if src.numel() * src.element_size() != dst.numel() * dst.element_size():
         raise ValueError("src and dst must have the same size in bytes")
     if src.numel() == 0:
@@ -521,15 +589,28 @@ def gmg_copy_probe(src, dst, stream=None):
                                src.numel() * src.element_size(), _stream(stream)))
 
 
+def _canonical_elems(ctx, level):
+    nx, ny, nz = ctx.shape(level)
+    return nx * ny * nz
+
+
 def gmg_transpose_in(ctx, level, src_z, dst_x, stream=None):
     """Device z-contiguous (j*nx+i)*nz+k -> x-contiguous field (same dtype)."""
-    _check(_lib.gmg_transpose_in(ctx.handle, int(level), _prec_of(src_z), src_z.data_ptr(),
+    level = _level(ctx, level)
+    prec = _field(ctx, src_z, "src_z", level, elems=_canonical_elems(ctx, level))
+    _field(ctx, dst_x, "dst_x", level, prec)
+    _distinct(src_z, dst_x, "src_z and dst_x")
+    _check(_lib.gmg_transpose_in(ctx.handle, level, prec, src_z.data_ptr(),
                                  dst_x.data_ptr(), _stream(stream)))
 
 
 def gmg_transpose_out(ctx, level, src_x, dst_z, stream=None):
     """Device x-contiguous field -> z-contiguous (j*nx+i)*nz+k (same dtype)."""
-    _check(_lib.gmg_transpose_out(ctx.handle, int(level), _prec_of(src_x), src_x.data_ptr(),
+    level = _level(ctx, level)
+    prec = _field(ctx, src_x, "src_x", level)
+    _field(ctx, dst_z, "dst_z", level, prec, elems=_canonical_elems(ctx, level))
+    _distinct(src_x, dst_z, "src_x and dst_z")
+    _check(_lib.gmg_transpose_out(ctx.handle, level, prec, src_x.data_ptr(),
                                   dst_z.data_ptr(), _stream(stream)))
 
 

@@ -1644,6 +1644,7 @@ __global__ __launch_bounds__(64 * SR) void k_fcg_update(Lvl<double> L, double* _
                                                         const CgState* __restrict__ st,
                                                         double* __restrict__ partials, int nti,
                                                         int ntj, int group) {
+  if (st->status == 3) return;  // breakdown: r stays the last residual
   const double alpha = st->alpha;
   const Geo g =
       stencil_geo<SR>(L.nx, L.ny, L.nz, nti, ntj, group, xcd_remap(blockIdx.x, gridDim.x));
@@ -1886,6 +1887,7 @@ __global__ __launch_bounds__(NTHREADS) void k_fcg_fin_alpha(CgState* st,
 __global__ __launch_bounds__(NTHREADS) void k_fcg_fin_res(CgState* st,
                                                           const double* __restrict__ partials,
                                                           int64_t n, double* __restrict__ hist) {
+  if (st->status == 3) return;  // breakdown: keep its status and the count
   double r[1];
   reduce_fixed<1>(partials, n, r);
   if (threadIdx.x == 0) {

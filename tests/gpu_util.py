@@ -50,3 +50,11 @@ def device_index(ctx, rows, level=0):
 
 def max_rel(got, ref, scale):
     return float(np.max(np.abs(got - ref) / scale))
+
+
+def f32_line_bar(nz):
+    """Bar of the FP32 line kernels against the FP64 oracle on FP32-rounded
+    inputs, relative to max|z|: about seven FP32 unit roundoffs per layer
+    (4e-7 nz), at least 2e-6.  tests/test_f32_line_bar.py shows that a textbook
+    FP32 Thomas sweep on these operators' columns stays well inside it."""
+    return max(2e-6, 4e-7 * nz)

@@ -84,3 +84,27 @@ def test_batched_pair_with_nan_fails_alone():
         u = b.from_device(us[pq], q)
         true_rel = orc.residual_norm2_rows(fh[pq], u) ** 0.5 / np.linalg.norm(fh[pq])
         assert true_rel < 1e-8, (pq, true_rel)
+
+
+@pytest.mark.parametrize("precond", [1, 2])
+def test_flexible_cg_breakdown_keeps_the_previous_iterate(precond):
+    """Right-hand-side values of 1e39 are finite in FP64 but overflow the FP32
+    copy of the residual that the FP32 preconditioner works on, so <p, Ap> of
+    the first direction is not finite: the flexible CG must stop with a
+    breakdown (GMG_ENOCONV, no iteration counted) and return its last iterate,
+    the initial guess, bit for bit."""
+    import paper_1402_3545_amd as G
+    nx, ny, nz = 32, 16, 8
+    ctx, _, _ = problem(nx, ny, nz, nlevels=3, prec_precond=1)
+    f = W.rhs(4, 0, nx, ny, nz)
+    f[::7] = 1e39
+    u0 = W.rhs(4, 1, nx, ny, nz)
+    fd, ud = ctx.to_device(f), ctx.to_device(u0)
+    before = ud.clone()
+    it, rel, hist, st = G.pcg_solve(ctx, fd, ud, rtol=1e-8, maxit=20, precond=precond,
+                                    check=False)
+    assert st == G.GMG_ENOCONV
+    assert it == 0
+    assert "breakdown" in G.gmg_last_error()
+    assert torch.equal(ud, before)
+    assert np.isfinite(rel)

@@ -15,11 +15,13 @@ n_z = 128 and 4e-6 at n_z = 64), so the bar is 4e-7 n_z (about seven FP32
 unit roundoffs per layer), at least 2e-6.
 """
 
+import ctypes as C
+
 import numpy as np
 import pytest
 
 import workloads as W
-from tests.gpu_util import abs_matvec, max_rel, problem
+from tests.gpu_util import abs_matvec, f32_line_bar, max_rel, problem
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
@@ -34,10 +36,6 @@ SHAPES = [
 ]
 F64 = 1e-12
 F32_STENCIL = 2e-6
-
-
-def f32_line_bar(nz):
-    return max(2e-6, 4e-7 * nz)
 
 
 @pytest.fixture(autouse=True, scope="module")
@@ -187,14 +185,23 @@ def test_invalid_arguments_raise():
     import paper_1402_3545_amd as G
     ctx, _, _ = problem(8, 8, 4, nlevels=2)
     x = ctx.empty()
-    with pytest.raises(G.GmgError):
-        G.spmv(ctx, 2, x, ctx.empty())            # no such level
-    with pytest.raises(G.GmgError):
+    y = ctx.empty()
+    # the binding rejects them before the call ...
+    with pytest.raises(ValueError):
+        G.spmv(ctx, 2, x, y)                      # no such level
+    with pytest.raises(ValueError):
         G.spmv(ctx, 0, x, x)                      # aliasing
-    with pytest.raises(G.GmgError):
+    with pytest.raises(ValueError):
         G.gmg_restrict_smooth(ctx, 0, x, x, x)    # level 0 is not coarse
+    with pytest.raises(ValueError):
+        G.gmg_solve(ctx, x.float(), y)            # FP32 field in an FP64 solve
     with pytest.raises(G.GmgError):
         G.gmg_solve(ctx, x, x)                    # f and u overlap
+    # ... and the C ABI itself validates what it can see
+    px, py, h = C.c_void_p(x.data_ptr()), C.c_void_p(y.data_ptr()), ctx.handle
+    assert G._lib.spmv(h, 2, G.GMG_F64, px, py, None) == G.GMG_EINVAL
+    assert G._lib.spmv(h, 0, G.GMG_F64, px, px, None) == G.GMG_EINVAL
+    assert G._lib.gmg_restrict_smooth(h, 0, G.GMG_F64, px, px, px, 0.5, None) == G.GMG_EINVAL
 
 
 def _pcr_everywhere(G, ctx):

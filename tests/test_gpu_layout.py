@@ -89,5 +89,7 @@ def test_host_solve_validation():
     with pytest.raises(G.GmgError):
         G.gmg_solve_host(ctx, f, np.zeros_like(f), method=5)
     x = ctx.empty()
-    with pytest.raises(G.GmgError):
+    with pytest.raises(ValueError):
         G.gmg_transpose_in(ctx, 0, x, x)
+    assert G._lib.gmg_transpose_in(ctx.handle, 0, G.GMG_F64, x.data_ptr(), x.data_ptr(),
+                                   None) == G.GMG_EINVAL

@@ -9,7 +9,7 @@ import numpy as np
 import pytest
 
 import workloads as W
-from tests.gpu_util import abs_matvec, max_rel, problem
+from tests.gpu_util import abs_matvec, f32_line_bar, max_rel, problem
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
@@ -18,10 +18,6 @@ SHAPES = [(4, 4, 8), (40, 6, 37), (64, 64, 64), (96, 32, 2), (34, 10, 128)]
 MULTI = [((8, 8, 4), 2), ((40, 24, 37), 3), ((64, 64, 64), 4), ((32, 96, 128), 2)]
 F64 = 1e-12
 F32_STENCIL = 2e-6
-
-
-def f32_line_bar(nz):
-    return max(2e-6, 4e-7 * nz)
 
 
 @pytest.fixture(autouse=True, scope="module")

@@ -90,3 +90,69 @@ def test_copy_probe_validation():
     assert lib.gmg_copy_probe(C.c_void_p(0x1000), C.c_void_p(0x2000), -8, None) == -1
     assert lib.gmg_copy_probe(C.c_void_p(0x1008), C.c_void_p(0x2000), 8, None) == -1  # align
     assert lib.gmg_copy_probe(C.c_void_p(0x1000), C.c_void_p(0x1010), 64, None) == -1  # overlap
+
+
+class _StubCtx:
+    """Stands in for a context on a machine without a GPU: the binding checks
+    every field against the layout before any call reaches the library."""
+    nlevels, prec_precond, rho, device, handle = 2, 0, 2.0 / 3.0, None, None
+
+    def layout(self, level=0):
+        return (32, 16 * 8 * 32) if level == 0 else (32, 8 * 8 * 32)
+
+    def shape(self, level=0):
+        return 16 >> level, 16 >> level, 8
+
+
+def _misuse_cases():
+    import torch
+    n0, n1 = 16 * 8 * 32, 8 * 8 * 32
+    ok = torch.zeros(n0, dtype=torch.float64)
+    return [
+        ("float32 f in an FP64 solve", "gmg_solve",
+         (torch.zeros(n0, dtype=torch.float32), ok)),
+        ("integer field", "spmv", (0, torch.zeros(n0, dtype=torch.int64), ok)),
+        ("mixed precisions", "spmv", (0, ok, torch.zeros(n0, dtype=torch.float32))),
+        ("unpadded nx*ny*nz field", "gmg_solve", (torch.zeros(16 * 16 * 8), ok)),
+        ("non-contiguous field", "line_solve",
+         (0, torch.zeros(2 * n0, dtype=torch.float64)[::2], ok)),
+        ("coarse field on the fine level", "line_smooth",
+         (0, torch.zeros(n1, dtype=torch.float64), ok)),
+        ("level out of range", "spmv", (2, ok, ok)),
+        ("restriction onto level 0", "gmg_restrict_smooth", (0, ok, ok, ok)),
+        ("vcycle field in the wrong precision", "gmg_vcycle",
+         (torch.zeros(n0, dtype=torch.float32), torch.zeros(n0, dtype=torch.float32))),
+        ("host tensor", "gmg_residual", (0, ok, ok, ok)),
+        ("not a tensor", "pcg_solve", (None, ok)),
+    ]
+
+
+@pytest.mark.parametrize("case", range(11))
+def test_binding_rejects_misfit_fields_before_any_launch(case):
+    """The C ABI takes no lengths, so the binding checks type, precision,
+    contiguity, the padded element count and the device of every field first;
+    each misuse raises ValueError (the stub context has no library handle, so
+    reaching the library would fail differently)."""
+    import paper_1402_3545_amd as G
+    what, fn, args = _misuse_cases()[case]
+    with pytest.raises(ValueError):
+        getattr(G, fn)(_StubCtx(), *args)
+
+
+def test_binding_rejects_misfit_batched_fields():
+    import torch
+    import paper_1402_3545_amd as G
+
+    class _StubBatch:
+        ninst, nrhs, device, handle = 1, 2, None, None
+
+        def layout(self, instance):
+            return 32, 512
+
+    ok = torch.zeros(512, dtype=torch.float64)
+    with pytest.raises(ValueError):
+        G.gmg_batch_solve(_StubBatch(), [ok, torch.zeros(100, dtype=torch.float64)], [ok, ok])
+    with pytest.raises(ValueError):
+        G.gmg_batch_solve(_StubBatch(), [ok, ok], [ok, ok.float()])
+    with pytest.raises(ValueError):  # host tensors
+        G.gmg_batch_solve(_StubBatch(), [ok, ok], [ok, ok])
