@@ -124,6 +124,26 @@ int line_smooth(gmg_ctx *c, int level, int prec, const void *f, void *u, int nsw
 int gmg_residual(gmg_ctx *c, int level, int prec, const void *f, const void *u, void *r,
                  double *norm2, void *stream);
 
+/* Allocation-free variant of gmg_residual, for callers that cannot allocate
+ * device memory or synchronise: code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc.  r = f - A u as gmg_residual (same
+ * kernels and launch shape, so r and the norm are bitwise those of
+ * gmg_residual); if norm2 is not NULL it is a DEVICE pointer (8-byte aligned,
+ * caller-owned) that receives ||r||_2^2 accumulated in FP64, written on
+ * `stream` -- the call never synchronises and never allocates.  The
+ * per-workgroup partial sums go to a static 1 MiB device array, one per GPU,
+ * held until the process ends (its address is taken once per device at
+ * gmg_setup or at the first call on a device).  Every call on a GPU shares
+ * that array: calls that overlap on one GPU (two streams, two host threads)
+ * race and must be serialised by the caller; nothing in it needs clearing,
+ * since each launch writes all the partials it reads.  With norm2 set,
+ * GMG_EINVAL for a level whose residual launch has more than 131072
+ * workgroups (64 x 4 columns x 32 layers each, i.e. above about 1.07e9 cells
+ * of a level whose sizes are multiples of those).  Launches are not recorded
+ * by gmg_timing_*. */
+int gmg_residual_noalloc(gmg_ctx *c, int level, int prec, const void *f, const void *u, void *r,
+                         double *norm2, void *stream);
+
 /* Kernel "ResSmooth" (Sec. 3.1, Algorithm 1): fc = R rf, the sum over the four
  * horizontal children, then uc = rho M^{-1} fc (one smoothing step from a zero
  * initial guess).  level is the COARSE level (>= 1); rf lives on level-1. */

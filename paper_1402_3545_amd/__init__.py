@@ -24,7 +24,8 @@ GMG_OK, GMG_EINVAL, GMG_ENOMEM, GMG_EHIP, GMG_ENOCONV, GMG_EUNSUPPORTED = 0, -1,
 GMG_F64, GMG_F32 = 0, 1
 
 EXPORTS = ("gmg_default_params", "gmg_setup", "gmg_destroy", "gmg_field_layout", "spmv",
-           "line_solve", "line_smooth", "gmg_residual", "gmg_restrict_smooth", "gmg_prolongate",
+           "line_solve", "line_smooth", "gmg_residual", "gmg_residual_noalloc",
+           "gmg_restrict_smooth", "gmg_prolongate",
            "gmg_vcycle", "gmg_solve", "pcg_solve", "gmg_batch_setup", "gmg_batch_layout",
            "gmg_batch_solve", "gmg_timing_enable", "gmg_timing_read", "gmg_timing_filter",
            "gmg_set_launch",
@@ -82,6 +83,7 @@ def _load():
         "line_solve": (i32, [vp, i32, i32, vp, vp, vp]),
         "line_smooth": (i32, [vp, i32, i32, vp, vp, i32, dbl, vp]),
         "gmg_residual": (i32, [vp, i32, i32, vp, vp, vp, dblp, vp]),
+        "gmg_residual_noalloc": (i32, [vp, i32, i32, vp, vp, vp, vp, vp]),
         "gmg_restrict_smooth": (i32, [vp, i32, i32, vp, vp, vp, dbl, vp]),
         "gmg_prolongate": (i32, [vp, i32, i32, vp, vp, vp]),
         "gmg_vcycle": (i32, [vp, vp, vp, vp]),
@@ -411,6 +413,31 @@ def gmg_residual(ctx, level, f, u, r, norm=False, stream=None):
     _check(_lib.gmg_residual(ctx.handle, level, prec, _ptr(f), _ptr(u), _ptr(r),
                              C.byref(out) if norm else None, _stream(stream)))
     return out.value if norm else None
+
+
+def gmg_residual_noalloc(ctx, level, f, u, r, norm2=None, stream=None):
+    """r = f - A u like gmg_residual, allocating nothing and never
+    synchronising: ||r||^2 (FP64) goes to the device tensor `norm2` (float64,
+    at least one element) when given, the partial sums to the library's static
+    per-GPU scratch.  Calls that overlap on one GPU race."""
+    import torch
+    level = _level(ctx, level)
+    prec = _fields(ctx, [(f, "f", level), (u, "u", level), (r, "r", level)])
+    _distinct(r, u, "r and u")
+    _distinct(r, f, "r and f")
+    out = None
+    if norm2 is not None:
+        if not isinstance(norm2, torch.Tensor) or norm2.dtype != torch.float64 \
+                or not norm2.is_cuda or not norm2.is_contiguous() or norm2.numel() < 1:
+            raise ValueError("norm2: expected a contiguous float64 GPU tensor of at least one "
+                             "element")
+        dev = getattr(ctx, "device", None)
+        if dev is not None and norm2.device.index != dev:
+            raise ValueError(f"norm2: on cuda:{norm2.device.index}, the context lives on "
+                             f"cuda:{dev}")
+        out = _ptr(norm2)
+    _check(_lib.gmg_residual_noalloc(ctx.handle, level, prec, _ptr(f), _ptr(u), _ptr(r), out,
+                                     _stream(stream)))
 
 
 def gmg_restrict_smooth(ctx, level, rf, fc, uc, rho=None, stream=None):

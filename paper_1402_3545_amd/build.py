@@ -9,7 +9,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libgmg.so")
-SOURCES = ["kernels.hip", "gmg_api.hip", "batch.hip", "layout.hip"]
+SOURCES = ["kernels.hip", "gmg_api.hip", "batch.hip", "layout.hip", "noalloc.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",

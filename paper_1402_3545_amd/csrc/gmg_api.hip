@@ -315,6 +315,8 @@ int gmg::setup_impl(const gmg_params* p, void* stream, gmg_ctx** out, bool field
     if (q && (e = hipMemsetAsync(q, 0, (size_t)n0 * 4, s)) != hipSuccess)
       return cleanup(hip_fail(e, "hipMemsetAsync"));
   if ((e = hipStreamSynchronize(s)) != hipSuccess) return cleanup(hip_fail(e, "setup sync"));
+  // this device's static scratch of the allocation-free residual (once per device)
+  if ((st = gmg::scratch_address(nullptr))) return cleanup(st);
   *out = c;
   return GMG_OK;
 }

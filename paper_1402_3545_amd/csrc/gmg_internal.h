@@ -163,6 +163,9 @@ template <typename T>
 Lvl<T> view(const gmg_ctx* c, int d);
 
 int setup_impl(const gmg_params* p, void* stream, gmg_ctx** out, bool fields);
+// device address of the current device's static scratch array of the
+// allocation-free entry point (looked up once per device; noalloc.hip)
+int scratch_address(double** out);
 int set_error(int code, const char* msg);
 int validate_params(const gmg_params* p);
 void batch_free(Batch* b);

@@ -79,6 +79,7 @@ def test_null_context_is_rejected():
     assert G._lib.gmg_get_launch(None, 0, 0, 0, None, None) == G.GMG_EINVAL
     assert G._lib.gmg_autotune(None, 3, None) == G.GMG_EINVAL
     assert G._lib.gmg_timing_filter(None, 1) == G.GMG_EINVAL
+    assert G._lib.gmg_residual_noalloc(None, 0, 0, None, None, None, None, None) == G.GMG_EINVAL
     assert G._lib.gmg_destroy(None) == G.GMG_OK
 
 
