@@ -58,6 +58,12 @@ WORDS_PER_CELL = {
     "correct": 4.0,          # read u, f (8 B), e (4 B), write u (8 B), r (4 B): 32 B
     "residual_restrict": 2.25,  # per FINE cell: read u, f, write 1/4 f_c
     "prolong_smooth": 3.25,  # read u, f, write u', read 1/4 u_c (u + P u_c not stored)
+    # the three vector kernels of a flexible-CG iteration with an FP32
+    # preconditioner move 100 B per cell together: <z,q> reads z (4 B) and q;
+    # the direction kernel reads z, u, p, q, r and writes u, p, q (60 B); the
+    # update reads r, q and writes r and its FP32 copy (28 B).  They share one
+    # timing kind, so each launch counts as a third of the iteration.
+    "fcg": 100.0 / 3.0 / 8.0,
 }
 
 SOLVES = ("mg_f64", "pcg_f64", "mg_mixed", "fcg_mixed")
@@ -89,7 +95,7 @@ def log(*a):
 
 def algorithmic_bytes(kernel, level, prec, w):
     nx, ny, nz = w.nx >> level, w.ny >> level, w.nz
-    esize = 8 if prec == "f64" else 4
+    esize = 8 if prec == "f64" or kernel == "fcg" else 4
     cells = nx * ny * nz
     if kernel == "prolongate":          # timed under the coarse level
         cells = (nx * 2) * (ny * 2) * nz
@@ -160,11 +166,29 @@ def copy_ceiling(torch, G, reps=5):
     return 2 * COPY_PROBE_BYTES / (ms / 1e3) / 1e9
 
 
-def cpu_baseline(w, f, kh, zf, mg_cycles=10, cg_iters=36):
-    """The FP64 oracle (CSR, OpenMP rows) on a bounded sample of the same
-    workload: `mg_cycles` multigrid V-cycles and `cg_iters` line-PCG
-    iterations from u = 0 on the full grid (a few seconds of each); value =
-    unknowns x (cycles + iterations) / time, as for the GPU line."""
+ORACLE_REF_RTOL = 1e-10   # tolerance of the oracle solves the GPU solutions are compared with
+
+
+def _rel(a, b):
+    import numpy as np
+    nb = float(np.linalg.norm(b))
+    return float(np.linalg.norm(a - b)) / nb if nb > 0 else float(np.linalg.norm(a))
+
+
+def cpu_baseline(w, f, kh, zf, mg_cycles=10, cg_iters=36, share=None, largest=None,
+                 batch=None):
+    """The CPU leg: the FP64 oracle (CSR, OpenMP rows) timed on a bounded
+    sample of the same workload -- `mg_cycles` multigrid V-cycles and
+    `cg_iters` line-PCG iterations from u = 0 on the full grid; value =
+    unknowns x (cycles + iterations) / time, as for the GPU line -- and the
+    oracle's verdict on the GPU solutions the run produced:
+      share:   {solve: u} on the same grid: the error against one oracle FP64
+               multigrid solve to ORACLE_REF_RTOL, and the true FP64 residual;
+      largest: (workload, f, kh, {solve: u}) on 2048^2 x 128: the true FP64
+               residual by the matrix-free oracle (its CSR does not fit);
+      batch:   [(workload, rhs index, f, u)]: per sampled pair, the error
+               against an oracle FP64 multigrid solve and the true residual.
+    Returns (baseline object, checks)."""
     import numpy as np
 
     import oracle
@@ -178,8 +202,7 @@ def cpu_baseline(w, f, kh, zf, mg_cycles=10, cg_iters=36):
     t0 = time.perf_counter()
     _, it_cg, _, _, _ = p.pcg_solve(f, rtol=1e-300, maxit=cg_iters)
     t_cg = time.perf_counter() - t0
-    del p
-    return {
+    base = {
         "value": w.unknowns * (it_mg + it_cg) / (t_mg + t_cg),
         "unit": "unknowns*iterations/s",
         "cores": oracle.num_threads(),
@@ -189,6 +212,59 @@ def cpu_baseline(w, f, kh, zf, mg_cycles=10, cg_iters=36):
                    f"on the full {w.nx}x{w.ny}x{w.nz} workload; CSR assembly {t_asm:.1f} s "
                    f"excluded"),
     }
+    checks = {}
+    nf = float(np.linalg.norm(f))
+    if share:
+        log(f"[bench] oracle reference solve of {w.name} to {ORACLE_REF_RTOL:g}")
+        t0 = time.perf_counter()
+        u_ref, it_ref, hist_ref, st_ref = p.mg_solve(f, rtol=ORACLE_REF_RTOL, maxit=80)
+        t_ref = time.perf_counter() - t0
+        out = {"reference": {"solver": "oracle FP64 multigrid (CSR)", "rtol": ORACLE_REF_RTOL,
+                             "iters": it_ref, "relres": float(hist_ref[-1]), "status": st_ref,
+                             "s": round(t_ref, 1)}}
+        for name, u in share.items():
+            r = p.residual(f, u)
+            out[name] = {"err_vs_oracle": _rel(u, u_ref),
+                         "max_err_vs_oracle": float(np.abs(u - u_ref).max() /
+                                                    np.abs(u_ref).max()),
+                         "oracle_relres": float(np.linalg.norm(r)) / nf}
+            log(f"[bench] {name}: error vs oracle {out[name]['err_vs_oracle']:.2e}, oracle "
+                f"relres {out[name]['oracle_relres']:.2e}")
+        checks[w.name] = out
+        del u_ref
+    del p
+    if largest:
+        lw, lf, lkh, sols = largest
+        log(f"[bench] oracle true residuals on {lw.name} (matrix-free rows)")
+        q = oracle.OracleProblem(lw.nx, lw.ny, lw.nz, lw.nlevels, kv=lw.kv, sigma=lw.sigma,
+                                 zfaces=lw.zfaces(), kh=lkh, matfree=True)
+        lnf = float(np.linalg.norm(lf))
+        out = {}
+        for name, u in sols.items():
+            out[name] = {"oracle_relres": q.residual_norm2_rows(lf, u) ** 0.5 / lnf}
+            log(f"[bench] {name}: oracle relres {out[name]['oracle_relres']:.2e}")
+        if "mg_f64" in sols and "mg_mixed" in sols:
+            out["mg_mixed"]["err_vs_fp64_mg"] = _rel(sols["mg_mixed"], sols["mg_f64"])
+        checks[lw.name] = out
+        del q
+    if batch:
+        log(f"[bench] oracle reference solves of {len(batch)} batched pairs")
+        out = {}
+        for bw, r, bf, u in batch:
+            q = oracle.OracleProblem(bw.nx, bw.ny, bw.nz, bw.nlevels, kv=bw.kv, sigma=bw.sigma,
+                                     zfaces=bw.zfaces(), kh=bw.kh())
+            u_ref, it_ref, hist_ref, _ = q.mg_solve(bf, rtol=ORACLE_REF_RTOL, maxit=80)
+            out[f"{bw.name}/rhs{r}"] = {
+                "err_vs_oracle": _rel(u, u_ref),
+                "oracle_relres": float(np.linalg.norm(q.residual(bf, u)) / np.linalg.norm(bf)),
+                "oracle_iters": it_ref}
+            del q, u_ref
+        checks["batched"] = {"pairs": out,
+                             "max_err_vs_oracle": max(v["err_vs_oracle"] for v in out.values()),
+                             "max_oracle_relres": max(v["oracle_relres"] for v in out.values())}
+        log(f"[bench] batched sample: max error vs oracle "
+            f"{checks['batched']['max_err_vs_oracle']:.2e}")
+    return base, checks
 
 
 def cfl_sweep(args, torch):
@@ -328,10 +404,62 @@ def paper_table(args, torch):
         torch.cuda.synchronize()
 
 
-def batched_run(args, torch):
+def _timed(torch, fn):
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    res = fn()
+    b.record()
+    b.synchronize()
+    return res, a.elapsed_time(b)
+
+
+def largest_comparison(torch, reps=2):
+    """The largest single-GPU grid (2048^2 x 128, K_v = 1e5, lognormal K, 7
+    levels): FP64 multigrid against FP32 V-cycles inside FP64 refinement, each
+    from u = 0 to 1e-8 on the resident input, one untimed and `reps` timed
+    solves (median).  Returns (record, f, kh, {solve: solution on the host})."""
+    import numpy as np
+
+    import paper_1402_3545_amd as G
+    import workloads as W
+    w = W.LARGEST
+    log(f"[bench] generating inputs for {w.name}")
+    kh, zf, f = w.kh(), w.zfaces(), w.rhs()
+    rec = {"workload": w.name, "unknowns": w.unknowns, "levels": w.nlevels, "rtol": w.rtol}
+    sols = {}
+    for tag, prec in (("mg_f64", G.GMG_F64), ("mg_mixed", G.GMG_F32)):
+        ctx = G.GmgContext(w.nx, w.ny, w.nz, w.nlevels, kv=w.kv, sigma=w.sigma, zfaces=zf, kh=kh,
+                           prec_precond=prec)
+        _, stored = G.tuned(ctx, reps=3)
+        fd, ud = ctx.to_device(f), ctx.empty()
+        times = []
+        for q in range(1 + reps):
+            ud.zero_()
+            (it, rel, _, st), ms = _timed(torch, lambda: G.gmg_solve(ctx, fd, ud, w.rtol, 100,
+                                                                      check=False))
+            if q:
+                times.append(ms)
+        ms = float(np.median(times))
+        rec[tag] = {"iters": it, "ms": round(ms, 3), "relres": rel, "status": st,
+                    "unknowns_iterations_per_s": w.unknowns * it / (ms / 1e3),
+                    "launch_shapes": "stored" if stored else "autotuned"}
+        log(f"[bench] {w.name} {tag}: {it} it, {ms:.1f} ms, relres {rel:.2e}")
+        sols[tag] = ctx.from_device(ud)
+        del fd, ud
+        ctx.close()
+        torch.cuda.empty_cache()
+    rec["mixed_vs_fp64_mg_speedup"] = rec["mg_f64"]["ms"] / rec["mg_mixed"]["ms"]
+    return rec, f, kh, sols
+
+
+def batched_comparison(torch, sample_every=8):
     """The batched workload (64 instances of seeded sizes, 4 right-hand sides
-    each, FP32 V-cycles in FP64 refinement to 1e-8): one untimed and one
-    timed batched solve on resident inputs.  Prints one JSON object."""
+    each, FP32 V-cycles in FP64 refinement to 1e-8): one untimed and one timed
+    batched solve on resident inputs, against the same pairs solved one at a
+    time by single-instance contexts -- plain FP64 multigrid, and FP32-cycle
+    refinement -- with default launch shapes, one untimed solve per instance
+    first, every solve timed with HIP events and the times summed.  Returns
+    (record, sampled pairs for the oracle: [(workload, rhs, f, u)])."""
     import numpy as np
 
     import paper_1402_3545_amd as G
@@ -353,12 +481,9 @@ def batched_run(args, torch):
         for u in us:
             u.zero_()
         torch.cuda.synchronize()
-        a, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        a.record()
-        it, rel, st = G.gmg_batch_solve(b, fs, us, rtol=1e-8, maxit=60)
-        e.record()
-        e.synchronize()
-        times.append(a.elapsed_time(e))
+        (it, rel, st), ms = _timed(torch, lambda: G.gmg_batch_solve(b, fs, us, rtol=1e-8,
+                                                                     maxit=60))
+        times.append(ms)
     sizes = np.repeat([w.unknowns for w in insts], nrhs)
     work = float((sizes * it).sum())
     rec = {"workload": f"batched-{len(insts)}x{nrhs}", "unknown_rhs": int(sizes.sum()),
@@ -366,10 +491,56 @@ def batched_run(args, torch):
            "iters_max": int(it.max()), "iters_mean": round(float(it.mean()), 2),
            "max_relres": float(rel.max()),
            "unknowns_iterations_per_s": work / (times[-1] / 1e3)}
-    print(json.dumps(rec), flush=True)
     log(f"[batched] {times[-1]:.1f} ms, cycles {it.min()}-{it.max()}, "
         f"{rec['unknowns_iterations_per_s']:.3e} unknowns*it/s")
+    picks = [(q, (q // sample_every) % nrhs) for q in range(0, len(insts), sample_every)]
+    sample = [(insts[q], r, None, b.from_device(us[q * nrhs + r], q)) for q, r in picks]
+    # the same pairs one at a time; the FP64 solutions also give every
+    # batched pair's distance to the plain FP64 solve
+    errs = []
+    for tag, prec in (("fp64_single", G.GMG_F64), ("mixed_single", G.GMG_F32)):
+        total, its, rels, bad = 0.0, [], [], 0
+        for q, w in enumerate(insts):
+            ctx = G.GmgContext(w.nx, w.ny, w.nz, w.nlevels, kv=w.kv, sigma=w.sigma,
+                               zfaces=kws[q]["zfaces"], kh=kws[q]["kh"], prec_precond=prec)
+            if ctx.layout(0) != b.layout(q):
+                raise RuntimeError("single-instance and batched layouts differ")
+            ud = torch.zeros(b.layout(q)[1], dtype=torch.float64, device="cuda")
+            G.gmg_solve(ctx, fs[q * nrhs], ud, 1e-8, 60, check=False)
+            for r in range(nrhs):
+                ud.zero_()
+                (i1, r1, _, s1), ms = _timed(torch, lambda: G.gmg_solve(
+                    ctx, fs[q * nrhs + r], ud, 1e-8, 60, check=False))
+                total += ms
+                its.append(i1)
+                rels.append(r1)
+                bad += s1 != 0
+                if prec == G.GMG_F64:
+                    ub = us[q * nrhs + r]
+                    errs.append(float(torch.linalg.vector_norm(ub - ud) /
+                                      torch.linalg.vector_norm(ud)))
+            del ud
+            ctx.close()
+        work1 = float((sizes * np.array(its)).sum())
+        rec[tag] = {"ms": round(total, 3), "iters_mean": round(float(np.mean(its)), 2),
+                    "max_relres": float(np.max(rels)), "failed": int(bad),
+                    "unknowns_iterations_per_s": work1 / (total / 1e3)}
+        rec[f"batched_vs_{tag}_speedup"] = total / times[-1]
+        log(f"[batched] {tag}: {total:.1f} ms summed over {len(its)} solves "
+            f"(batched is {total / times[-1]:.2f}x faster)")
+        torch.cuda.empty_cache()
+    rec["max_err_vs_fp64_single"] = max(errs)
     b.close()
+    del fs, us
+    torch.cuda.empty_cache()
+    sample = [(w, r, w.rhs(r), u) for w, r, _, u in sample]
+    return rec, sample
+
+
+def batched_run(args, torch):
+    """`--batched`: the batched comparison alone (one JSON object)."""
+    rec, _ = batched_comparison(torch)
+    print(json.dumps(rec), flush=True)
 
 
 def main():
@@ -394,6 +565,9 @@ def main():
                          "object per solver and size)")
     ap.add_argument("--batched", action="store_true",
                     help="only run the batched workload (one JSON object)")
+    ap.add_argument("--no-comparisons", action="store_true",
+                    help="skip the largest-grid and batched comparisons after the step "
+                         "(for profiler runs)")
     ap.add_argument("--workload", choices=("share", "small", "largest"), default="share",
                     help="share: 1024^2 x 128 (the default line); small: 64^3 (cache "
                          "resident); largest: 2048^2 x 128 (no CPU baseline: its CSR "
@@ -466,13 +640,13 @@ def main():
         with open(args.tune_out, "w") as fh:
             json.dump(store, fh, indent=1, sort_keys=True)
 
-    def step():
+    def step(which=None):
         out = {}
         runs = {"mg_f64": lambda: G.gmg_solve(ctx64, fd, ud, w.rtol, 100),
                 "pcg_f64": lambda: G.pcg_solve(ctx64, fd, ud, w.rtol, 2000),
                 "mg_mixed": lambda: G.gmg_solve(ctx32, fd, ud, w.rtol, 100),
                 "fcg_mixed": lambda: G.pcg_solve(ctx32, fd, ud, w.rtol, 100, precond=1)}
-        for name in solves:
+        for name in (which or solves):
             fn = runs[name]
             ud.zero_()
             a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -495,15 +669,23 @@ def main():
                 table[key] = (cn + n, cms + ms)
         return table
 
-    # one untimed step with every kernel timed: the per-kernel breakdown, and
-    # the dominant kernel whose roofline the line reports
-    for c in (ctx64, ctx32):
-        G.gmg_timing_filter(c, None)
-        G.gmg_timing_enable(c, True)
-    step()
-    full = timing_table()
-    for c in (ctx64, ctx32):
-        G.gmg_timing_enable(c, False)
+    # one untimed step with every kernel timed, solve by solve: the per-kernel
+    # breakdown, each solve's algorithmic bytes, and the dominant kernel whose
+    # roofline the line reports
+    per_solve = {}
+    for name in solves:
+        for c in (ctx64, ctx32):
+            G.gmg_timing_filter(c, None)
+            G.gmg_timing_enable(c, True)
+        step([name])
+        per_solve[name] = timing_table()
+        for c in (ctx64, ctx32):
+            G.gmg_timing_enable(c, False)
+    full = {}
+    for tab in per_solve.values():
+        for key, (n, ms) in tab.items():
+            cn, cms = full.get(key, (0, 0.0))
+            full[key] = (cn + n, cms + ms)
     dom = max((k for k in full if algorithmic_bytes(*k, w) is not None),
               key=lambda k: full[k][1])
     breakdown = {f"{k[0]}@L{k[1]}/{k[2]}": {"launches": n, "ms": round(ms, 3)}
@@ -579,10 +761,59 @@ def main():
     traffic = (measured_traffic(dom, G.gmg_get_launch(ctx64, dom[0], dom[1], prec_id))
                if w is W.SHARE else None)
 
-    base = None
-    if not args.no_cpu_baseline and w is not W.LARGEST:
+    # each solve's algorithmic traffic: the kernels' algorithmic bytes
+    # (WORDS_PER_CELL) summed over its launches in the fully timed step, over
+    # its median time in the timed steps (reductions, fills and the final
+    # update of the CG iterate are left out: a few words per solve)
+    solve_rates = {}
+    for name, v in last.items():
+        ms_med = float(np.median([r[name]["ms"] for r in runs]))
+        nbytes = sum(n * algorithmic_bytes(*k, w) for k, (n, _) in per_solve[name].items()
+                     if algorithmic_bytes(*k, w) is not None)
+        gbs = nbytes / (ms_med / 1e3) / 1e9
+        solve_rates[name] = {
+            "unknowns_iterations_per_s": w.unknowns * v["iters"] / (ms_med / 1e3),
+            "algorithmic_gb": nbytes / 1e9,
+            "algorithmic_gbs": gbs,
+            "frac_of_peak": gbs / HBM_PEAK_GBS,
+            "words_per_cell_iteration": nbytes / (8.0 * w.unknowns * max(v["iters"], 1)),
+        }
+
+    # the final solutions of the four solves (one more untimed solve each),
+    # for the oracle's verdict in the CPU leg
+    share_sols = None
+    want_oracle = not args.no_cpu_baseline and w is not W.LARGEST
+    if want_oracle:
+        share_sols = {}
+        runs_final = {"mg_f64": lambda: G.gmg_solve(ctx64, fd, ud, w.rtol, 100),
+                      "pcg_f64": lambda: G.pcg_solve(ctx64, fd, ud, w.rtol, 2000),
+                      "mg_mixed": lambda: G.gmg_solve(ctx32, fd, ud, w.rtol, 100),
+                      "fcg_mixed": lambda: G.pcg_solve(ctx32, fd, ud, w.rtol, 100, precond=1)}
+        for name in solves:
+            ud.zero_()
+            runs_final[name]()
+            share_sols[name] = ctx64.from_device(ud)
+
+    # the other configurations of the metric, on the same GPU: the largest
+    # grid (FP64 multigrid against FP32-cycle refinement) and the batched
+    # workload against the same pairs solved one at a time in plain FP64
+    largest = batched = largest_host = batch_sample = None
+    if w is W.SHARE and not args.no_comparisons:
+        del fd, ud
+        ctx64.close()
+        ctx32.close()
+        torch.cuda.empty_cache()
+        largest, lf, lkh, lsols = largest_comparison(torch)
+        largest_host = (W.LARGEST, lf, lkh, lsols) if want_oracle else None
+        batched, batch_sample = batched_comparison(torch)
+        if not want_oracle:
+            batch_sample = None
+
+    base = checks = None
+    if want_oracle:
         log("[bench] timing the CPU oracle sample")
-        base = cpu_baseline(w, f, kh, zf)
+        base, checks = cpu_baseline(w, f, kh, zf, share=share_sols, largest=largest_host,
+                                    batch=batch_sample)
         log(f"[bench] oracle: {base['value']:.3e} unknowns*it/s on {base['cores']} threads")
 
     def speedup(a, b):
@@ -614,7 +845,10 @@ def main():
         },
         "solves": {n: {"iters": v["iters"], "ms": round(v["ms"], 3),
                        "ms_median": round(float(np.median([r[n]["ms"] for r in runs])), 3),
-                       "relres": v["relres"]} for n, v in last.items()},
+                       "relres": v["relres"], **solve_rates[n]} for n, v in last.items()},
+        "solves_note": ("algorithmic_gbs: the solve's kernels' algorithmic bytes (words per "
+                        "cell of each kernel x launches) over its median time; relres is the "
+                        "library's FP64 true relative residual"),
         "mixed_vs_fp64_mg_speedup": speedup("mg_f64", "mg_mixed"),
         "fcg_mixed_vs_fp64_mg_speedup": speedup("mg_f64", "fcg_mixed"),
         "roofline": {
@@ -625,6 +859,9 @@ def main():
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
             "traffic": traffic,
+            "traffic_source": ("stored: rocprofv3 FETCH_SIZE/WRITE_SIZE of this kernel source "
+                               "and launch shape, copy-calibrated (profiles/)"
+                               if traffic is not None else None),
             "copy_ceiling_gbs": copy_gbs,
             "frac_of_copy": achieved / copy_gbs,
             "torch_copy_gbs": torch_copy_gbs,
@@ -639,6 +876,9 @@ def main():
         "host_solution": host,
         "fcg_line_mixed": line_fcg,
         "cpu_baseline": base,
+        "oracle_checks": checks,
+        "largest": largest,
+        "batched": batched,
     }
     print(json.dumps(line), flush=True)
 

@@ -44,10 +44,40 @@ def test_cpu_baseline_times_the_oracle_on_a_sample():
     kh = W.kh_uniform(3, nx, ny)
     zf = W.quadratic_faces(nz)
     f = W.uniform_pm1(3, 1, nx * ny * nz)
-    out = b.cpu_baseline(w, f, kh, zf, mg_cycles=2, cg_iters=3)
+    out, checks = b.cpu_baseline(w, f, kh, zf, mg_cycles=2, cg_iters=3)
     assert out["kind"] == "oracle" and out["unit"] == "unknowns*iterations/s"
     assert out["value"] > 0 and out["cores"] >= 1
     assert "2 FP64 V(1,1) cycles" in out["sample"] and "3 FP64 line-PCG" in out["sample"]
+    assert checks == {}
+
+
+def test_cpu_leg_judges_solutions_by_the_oracle():
+    """The oracle checks of the CPU leg: a solution to 1e-8 is close to the
+    reference solve and has a true residual below 1e-8; a perturbed one is
+    reported as such (on a tiny instance, with the oracle's own solutions
+    standing in for the GPU's)."""
+    import oracle
+    b = _bench_module()
+    w = W.Workload("tiny-16x16x8", 16, 16, 8, 2, 1e3, 1.0, 3, "uniform", 1e-8)
+    kh, zf, f = w.kh(), w.zfaces(), w.rhs()
+    p = oracle.OracleProblem(w.nx, w.ny, w.nz, w.nlevels, kv=w.kv, sigma=w.sigma, zfaces=zf,
+                             kh=kh)
+    u8, _, _, _ = p.mg_solve(f, rtol=1e-8, maxit=60)
+    bad = u8 * (1.0 + 1e-3)
+    w2 = W.Workload("tiny-matfree", 16, 16, 8, 2, 1e3, 1.0, 3, "uniform", 1e-8)
+    _, checks = b.cpu_baseline(w, f, kh, zf, mg_cycles=1, cg_iters=1,
+                               share={"good": u8, "bad": bad},
+                               largest=(w2, f, kh, {"mg_f64": u8, "mg_mixed": bad}),
+                               batch=[(w, 0, f, u8)])
+    share = checks[w.name]
+    assert share["reference"]["relres"] < b.ORACLE_REF_RTOL
+    assert share["good"]["oracle_relres"] < 1e-8 and share["good"]["err_vs_oracle"] < 1e-6
+    assert share["bad"]["err_vs_oracle"] == __import__("pytest").approx(1e-3, rel=1e-3)
+    big = checks[w2.name]
+    assert big["mg_f64"]["oracle_relres"] < 1e-8
+    assert big["mg_mixed"]["err_vs_fp64_mg"] == __import__("pytest").approx(1e-3, rel=1e-6)
+    pair = checks["batched"]["pairs"][f"{w.name}/rhs0"]
+    assert pair["err_vs_oracle"] < 1e-6 and pair["oracle_relres"] < 1e-8
 
 
 def test_roofline_tables():
