@@ -319,6 +319,28 @@ int gmg_set_launch(gmg_ctx *c, int kernel, int level, int prec, int rows, int gr
 int gmg_get_launch(const gmg_ctx *c, int kernel, int level, int prec, int *rows, int *group);
 int gmg_autotune(gmg_ctx *c, int reps, void *stream);
 
+/* Launch mode of the iterative solvers (gmg_solve, pcg_solve, and the solve
+ * inside gmg_solve_host).  Their scalars and stopping test live on the device
+ * and every kernel of an iteration returns at once after the solve has
+ * stopped, so the host enqueues predicted batches of iterations and reads the
+ * solver state only between batches (Algorithm 1's loop of Sec. 2.2 without a
+ * host round trip per cycle).  enable = 1 (the default): each batch of the
+ * multigrid, refinement and flexible-CG solves is replayed from a hipGraph of
+ * one iteration (two for the refinement, whose iterate alternates between two
+ * buffers; line-PCG's four-kernel iteration is always launched directly),
+ * captured on the context's own
+ * stream at the first solve with a given pair of caller fields and kept until
+ * gmg_destroy, a launch-shape change (gmg_set_launch, gmg_autotune) or
+ * gmg_set_graphs(c, 0); at most 8 graphs per context.  enable = 0: the same
+ * kernels launched one by one (iterations with a kernel kind being timed by
+ * gmg_timing_* always are).  Results are bitwise identical either way. */
+int gmg_set_graphs(gmg_ctx *c, int enable);
+
+/* The number of times the last gmg_solve or pcg_solve on the context waited
+ * for device scalars (a synchronisation of the stream), its final wait
+ * included; GMG_EINVAL for a NULL or batched context. */
+int gmg_solver_polls(const gmg_ctx *c);
+
 /* Message describing the calling thread's last non-OK status. */
 const char *gmg_last_error(void);
 

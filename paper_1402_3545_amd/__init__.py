@@ -29,7 +29,9 @@ EXPORTS = ("gmg_default_params", "gmg_setup", "gmg_destroy", "gmg_field_layout",
            "gmg_vcycle", "gmg_solve", "pcg_solve", "gmg_batch_setup", "gmg_batch_layout",
            "gmg_batch_solve", "gmg_timing_enable", "gmg_timing_read", "gmg_timing_filter",
            "gmg_set_launch",
-           "gmg_get_launch", "gmg_autotune", "gmg_transpose_in", "gmg_transpose_out",
+           "gmg_get_launch", "gmg_autotune", "gmg_set_graphs", "gmg_solver_polls",
+           "gmg_transpose_in",
+           "gmg_transpose_out",
            "gmg_solve_host", "gmg_copy_probe", "gmg_last_error")
 
 # kernel ids of the timing facility (gmg_kernel in include/gmg.h)
@@ -99,6 +101,8 @@ def _load():
         "gmg_set_launch": (i32, [vp, i32, i32, i32, i32, i32]),
         "gmg_get_launch": (i32, [vp, i32, i32, i32, intp, intp]),
         "gmg_autotune": (i32, [vp, i32, vp]),
+        "gmg_set_graphs": (i32, [vp, i32]),
+        "gmg_solver_polls": (i32, [vp]),
         "gmg_transpose_in": (i32, [vp, i32, i32, vp, vp, vp]),
         "gmg_copy_probe": (i32, [vp, vp, C.c_int64, vp]),
         "gmg_transpose_out": (i32, [vp, i32, i32, vp, vp, vp]),
@@ -548,6 +552,17 @@ def gmg_get_launch(ctx, kernel, level, prec):
     _check(_lib.gmg_get_launch(ctx.handle, _kid(kernel), int(level), int(prec), C.byref(rows),
                                C.byref(group)))
     return rows.value, group.value
+
+
+def gmg_set_graphs(ctx, enable=True):
+    """Iterations of the solvers as hipGraph replays (True, the default) or
+    as direct launches (False); results are identical."""
+    _check(_lib.gmg_set_graphs(ctx.handle, 1 if enable else 0))
+
+
+def gmg_solver_polls(ctx):
+    """Host waits for device scalars in the context's last solve."""
+    return _check(_lib.gmg_solver_polls(ctx.handle))
 
 
 def gmg_autotune(ctx, reps=3, stream=None):

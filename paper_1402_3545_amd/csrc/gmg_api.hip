@@ -115,14 +115,14 @@ template <>
 Lvl<double> view<double>(const gmg_ctx* c, int d) {
   const LevelBuf& L = c->lev[d];
   return Lvl<double>{L.nx,    L.ny,    L.nz,  L.ldx,    L.cx64,    L.cy64,
-                     L.sub64, L.sup64, L.dg64, c->dz64, L.wall64, c->p.bc_h};
+                     L.sub64, L.sup64, L.dg64, c->dz64, L.wall64, c->p.bc_h, c->gate};
 }
 
 template <>
 Lvl<float> view<float>(const gmg_ctx* c, int d) {
   const LevelBuf& L = c->lev[d];
   return Lvl<float>{L.nx,    L.ny,    L.nz,  L.ldx,    L.cx32,    L.cy32,
-                    L.sub32, L.sup32, L.dg32, c->dz32, L.wall32, c->p.bc_h};
+                    L.sub32, L.sup32, L.dg32, c->dz32, L.wall32, c->p.bc_h, c->gate};
 }
 
 }  // namespace gmg
@@ -160,9 +160,12 @@ int gmg_destroy(gmg_ctx* c) {
   dfree(c->partials);
   dfree(c->state);
   dfree(c->dhist);
+  if (c->hhist) (void)hipHostFree(c->hhist);
   if (c->hstate) (void)hipHostFree(c->hstate);
   if (c->hscal) (void)hipHostFree(c->hscal);
   for (hipEvent_t e : c->evpool) (void)hipEventDestroy(e);
+  for (gmg_graph& g : c->graphs) (void)hipGraphExecDestroy(g.exec);
+  if (c->cap) (void)hipStreamDestroy(c->cap);
   delete c;
   return GMG_OK;
 }
@@ -451,8 +454,8 @@ int vcycle_impl(gmg_ctx* c, const T* f0, T* u0, hipStream_t s, bool zero_guess =
     T* other = pre_done ? u0 : ualt0;
     HIP_TRY(smooth_steps<T>(c, 0, f0, from, other, c->p.ncoarse - pre_done, rho, s, &res));
     if (res != u0)
-      HIP_TRY(hipMemcpyAsync(u0, res, (size_t)c->lev[0].elems * sizeof(T),
-                             hipMemcpyDeviceToDevice, s));
+      HIP_TRY(timed(c, GMG_K_AUX, 0, P, s,
+                    [&] { return gmg::launch_copy_level<T>(V0, res, u0, s); }));
     return GMG_OK;
   }
   if (!pre_done)
@@ -523,17 +526,6 @@ int line_smooth_t(gmg_ctx* c, int level, const T* f, T* u, int nsweeps, T rho, h
   return GMG_OK;
 }
 
-// Sum nb per-workgroup partials on the device and read the scalar back.
-int reduce_read(gmg_ctx* c, int64_t nb, double* out, hipStream_t s) {
-  double* dst = c->partials + c->max_partials;
-  HIP_TRY(timed(c, GMG_K_REDUCE, 0, GMG_F64, s,
-                [&] { return gmg::launch_reduce(c->partials, nb, 1, dst, s); }));
-  HIP_TRY(hipMemcpyAsync(c->hscal, dst, sizeof(double), hipMemcpyDeviceToHost, s));
-  HIP_TRY(hipStreamSynchronize(s));
-  *out = c->hscal[0];
-  return GMG_OK;
-}
-
 // r = f - A u on level 0 with ||r||^2 into *out (host), synchronising.  With
 // rdown the residual is also written as FP32.
 template <typename T>
@@ -551,29 +543,154 @@ int residual_norm2(gmg_ctx* c, const T* f, const T* u, T* r, float* rdown, doubl
                 [&] { return gmg::launch_reduce(c->partials, nb, 1, dst, s); }));
   HIP_TRY(hipMemcpyAsync(c->hscal, dst, sizeof(double), hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
+  ++c->polls;
   *out = c->hscal[0];
   return GMG_OK;
 }
 
-// How many CG iterations to launch before the host reads the device state
-// again: the count still needed at the mean decay rate of ||r||^2 so far,
-// clamped to [1, 32] (doubling from the previous chunk until two iterations
-// have run).  Launches past convergence return at once, so a low guess costs
-// one more poll and a high one a few empty launches.
-int predicted_chunk(const CgState& h, int prev) {
+// How many iterations to enqueue before the host reads the device state
+// again: the count still needed at the slower of the mean decay rate of
+// ||r||^2 so far and its rate since the previous read (multigrid converges
+// faster in its first cycles), plus one, clamped to [1, 32]; doubling from
+// the previous batch until two iterations have run.  Iterations enqueued past
+// convergence return at once, so a low guess costs one more read and a high
+// one a few empty launches.
+int predicted_chunk(const CgState& h, int it_prev, double rr_prev, int prev) {
   if (h.iter < 2 || !(h.rr > 0.0) || !(h.rr < h.rr0)) return std::min(2 * prev, 32);
-  const double rate = log(h.rr / h.rr0) / h.iter;  // < 0
   const double need = log(h.thresh2 / h.rr);       // < 0 until converged
   if (!(need < 0.0)) return 1;
-  return (int)std::min(32.0, std::max(1.0, ceil(need / rate)));
+  double rate = log(h.rr / h.rr0) / h.iter;        // < 0
+  if (it_prev >= 1 && h.iter > it_prev && rr_prev > 0.0 && h.rr < rr_prev)
+    rate = std::max(rate, log(h.rr / rr_prev) / (h.iter - it_prev));
+  return (int)std::min(32.0, std::max(1.0, ceil(need / rate) + 1.0));
 }
 
 int ensure_hist(gmg_ctx* c, int maxit) {
   if (c->dhist_len < maxit + 1) {
     dfree(c->dhist);
+    if (c->hhist) (void)hipHostFree(c->hhist);
+    c->hhist = nullptr;
     c->dhist_len = 0;
     HIP_TRY(dmalloc(&c->dhist, (size_t)maxit + 1));
+    HIP_TRY(hipHostMalloc((void**)&c->hhist, ((size_t)maxit + 1) * sizeof(double),
+                          hipHostMallocDefault));
     c->dhist_len = maxit + 1;
+  }
+  return GMG_OK;
+}
+
+// ---- device-side iteration loops --------------------------------------------
+// The iterative solvers keep their scalars and stopping test on the device
+// (CgState) and every kernel of an iteration is gated on its "done" flag, so
+// iterations enqueued past convergence return at once.  The host enqueues
+// predicted batches of iterations -- one hipGraph replay per `per`
+// iterations, unless graphs are off or one of the iteration's kernel kinds is
+// being timed -- and reads the state only after each batch.
+
+enum GraphKind { GK_MG = 0, GK_IR = 1, GK_FCG = 2, GK_FCG_LINE = 3, GK_PCG = 4 };
+
+constexpr uint32_t kbit(int k) { return 1u << k; }
+// kernel kinds one iteration of each loop launches
+constexpr uint32_t kVcycleKinds = kbit(GMG_K_LINE_SOLVE) | kbit(GMG_K_SMOOTH) |
+                                  kbit(GMG_K_RESIDUAL_RESTRICT) | kbit(GMG_K_PROLONGATE) |
+                                  kbit(GMG_K_PROLONG_SMOOTH) | kbit(GMG_K_REDUCE) |
+                                  kbit(GMG_K_AUX);
+constexpr uint32_t kIrKinds = kVcycleKinds | kbit(GMG_K_CORRECT);
+constexpr uint32_t kFcgKinds = kVcycleKinds | kbit(GMG_K_FCG);
+constexpr uint32_t kPcgKinds = kbit(GMG_K_CG_SPMV) | kbit(GMG_K_CG_TRIDIAG) | kbit(GMG_K_REDUCE);
+
+// Views built while this lives carry the solver state's "done" flag as gate.
+struct GateScope {
+  gmg_ctx* c;
+  explicit GateScope(gmg_ctx* cc) : c(cc) { c->gate = &c->state->done; }
+  ~GateScope() { c->gate = nullptr; }
+};
+
+void drop_graphs(gmg_ctx* c) {
+  for (gmg_graph& g : c->graphs) (void)hipGraphExecDestroy(g.exec);
+  c->graphs.clear();
+}
+
+// The cached graph of `per` iterations of solver `kind` on the caller's
+// fields (fk, uk), captured on the context's own stream at first use.
+template <typename U>
+int graph_for(gmg_ctx* c, int kind, const void* fk, const void* uk, int per, U&& unit,
+              hipGraphExec_t* out) {
+  for (const gmg_graph& g : c->graphs)
+    if (g.kind == kind && g.f == fk && g.u == uk) {
+      *out = g.exec;
+      return GMG_OK;
+    }
+  if (!c->cap) HIP_TRY(hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking));
+  HIP_TRY(hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal));
+  const bool timing = c->timing;
+  c->timing = false;  // no event records inside a graph
+  int st = GMG_OK;
+  for (int r = 0; r < per && !st; ++r) st = unit(c->cap, r);
+  c->timing = timing;
+  hipGraph_t g = nullptr;
+  const hipError_t e = hipStreamEndCapture(c->cap, &g);
+  if (st || e != hipSuccess) {
+    if (g) (void)hipGraphDestroy(g);
+    return st ? st : hip_fail(e, "hipStreamEndCapture");
+  }
+  hipGraphExec_t x = nullptr;
+  const hipError_t ei = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (ei != hipSuccess) return hip_fail(ei, "hipGraphInstantiate");
+  if (c->graphs.size() >= 8) {
+    (void)hipGraphExecDestroy(c->graphs.front().exec);
+    c->graphs.erase(c->graphs.begin());
+  }
+  c->graphs.push_back({kind, fk, uk, x});
+  *out = x;
+  return GMG_OK;
+}
+
+// Enqueue iterations (unit(stream, r) enqueues one; r = index within a group
+// of `per`, for solvers whose iterate alternates between two buffers) in
+// predicted batches until the device state is done or `maxit` iterations
+// have been enqueued; `first` iterations go before the first read.  The
+// caller has enqueued the initialisation (which may already set done).  On
+// return c->hstate holds the final state.
+template <typename U>
+int run_iterations(gmg_ctx* c, hipStream_t s, int kind, const void* fk, const void* uk,
+                   uint32_t kinds, int maxit, int per, int first, U&& unit) {
+  hipGraphExec_t exec = nullptr;
+  // line-PCG's iteration is four kernels: replaying it from a graph measured
+  // slower than launching them (0.50 against 0.46 ms for the ten iterations
+  // of the 64^3 workload, the same at 1024^2 x 128)
+  const bool eager = !c->graphs_on || kind == GK_PCG || (c->timing && (c->timing_mask & kinds));
+  if (!eager && maxit > 0) {
+    const int st = graph_for(c, kind, fk, uk, per, unit, &exec);
+    if (st) return st;
+  }
+  int launched = 0, chunk = first, it_prev = 0;
+  double rr_prev = 0.0;
+  for (;;) {
+    const int nq = (std::min(chunk, maxit - launched) + per - 1) / per * per;
+    for (int q = 0; q < nq; q += per) {
+      if (exec) {
+        HIP_TRY(hipGraphLaunch(exec, s));
+      } else {
+        for (int r = 0; r < per; ++r) {
+          const int st = unit(s, r);
+          if (st) return st;
+        }
+      }
+    }
+    launched += std::max(nq, 0);
+    HIP_TRY(hipMemcpyAsync(c->hstate, c->state, sizeof(CgState), hipMemcpyDeviceToHost, s));
+    // the history so far rides along (pinned mirror), so reading it at the
+    // end needs no further wait
+    HIP_TRY(hipMemcpyAsync(c->hhist, c->dhist, (size_t)(std::max(maxit, 0) + 1) * sizeof(double),
+                           hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    ++c->polls;
+    if (c->hstate->done || launched >= maxit) break;
+    chunk = predicted_chunk(*c->hstate, it_prev, rr_prev, chunk);
+    it_prev = c->hstate->iter;
+    rr_prev = c->hstate->rr;
   }
   return GMG_OK;
 }
@@ -585,7 +702,6 @@ template <typename TZ>
 int fcg_impl(gmg_ctx* c, const double* f, double* u, double rtol, int maxit, int* iters,
              double* relres, double* history, hipStream_t s, bool line_only = false) {
   const bool mixed = sizeof(TZ) == 4;
-  const Lvl<TZ> VZ = gmg::view<TZ>(c, 0);
   const Lvl<double> V = gmg::view<double>(c, 0);
   const int64_t n0 = c->lev[0].elems;
   int st;
@@ -612,45 +728,54 @@ int fcg_impl(gmg_ctx* c, const double* f, double* u, double rtol, int maxit, int
                 [&] { return gmg::launch_fill<double>(c->vq, n0, 0.0, s); }));
   TZ* z = mixed ? reinterpret_cast<TZ*>(c->eu32) : reinterpret_cast<TZ*>(c->vz);
   const TZ* rin = mixed ? reinterpret_cast<const TZ*>(c->er32) : reinterpret_cast<const TZ*>(c->vr);
-  for (int it = 1; it <= maxit; ++it) {
-    if (line_only) {
-      // the vertical line preconditioner alone, in the preconditioner's
-      // precision: z = M^-1 r (on the FP32 copy of r in mixed precision)
-      HIP_TRY(timed(c, GMG_K_LINE_SOLVE, 0, prec_of<TZ>(), s, [&](gmg::Shape sh) {
-        return gmg::launch_line_solve_scaled<TZ>(VZ, rin, z, TZ(1), s, sh);
+  {
+    GateScope gate(c);
+    // one iteration; every kernel returns at once once the state is done
+    auto unit = [&](hipStream_t q, int) -> int {
+      const Lvl<TZ> VZg = gmg::view<TZ>(c, 0);
+      const Lvl<double> Vg = gmg::view<double>(c, 0);
+      if (line_only) {
+        // the vertical line preconditioner alone, in the preconditioner's
+        // precision: z = M^-1 r (on the FP32 copy of r in mixed precision)
+        HIP_TRY(timed(c, GMG_K_LINE_SOLVE, 0, prec_of<TZ>(), q, [&](gmg::Shape sh) {
+          return gmg::launch_line_solve_scaled<TZ>(VZg, rin, z, TZ(1), q, sh);
+        }));
+      } else {
+        const int sv = vcycle_impl<TZ>(c, rin, z, q, true, false);
+        if (sv) return sv;
+      }
+      int64_t nb = 0;
+      HIP_TRY(timed(c, GMG_K_FCG, 0, GMG_F64, q,
+                    [&] { return gmg::launch_fcg_zq<TZ>(Vg, z, c->vq, c->partials, &nb, q); }));
+      HIP_TRY(timed(c, GMG_K_REDUCE, 0, GMG_F64, q, [&] {
+        return gmg::launch_fcg_fin(0, c->state, c->partials, nb, nullptr, q);
       }));
-    } else if ((st = vcycle_impl<TZ>(c, rin, z, s, true, false))) {
+      HIP_TRY(timed(c, GMG_K_FCG, 0, GMG_F64, q, [&](gmg::Shape sh) {
+        return gmg::launch_fcg_dir<TZ>(Vg, z, u, c->vp, c->vq, c->vr, c->state, c->partials, &nb,
+                                       q, sh);
+      }));
+      HIP_TRY(timed(c, GMG_K_REDUCE, 0, GMG_F64, q, [&] {
+        return gmg::launch_fcg_fin(1, c->state, c->partials, nb, nullptr, q);
+      }));
+      HIP_TRY(timed(c, GMG_K_FCG, 0, GMG_F64, q, [&](gmg::Shape sh) {
+        return gmg::launch_fcg_update(Vg, c->vr, c->vq, mixed ? c->er32 : nullptr, c->state,
+                                      c->partials, &nb, q, sh);
+      }));
+      HIP_TRY(timed(c, GMG_K_REDUCE, 0, GMG_F64, q, [&] {
+        return gmg::launch_fcg_fin(2, c->state, c->partials, nb, c->dhist, q);
+      }));
+      return GMG_OK;
+    };
+    if ((st = run_iterations(c, s, line_only ? GK_FCG_LINE : GK_FCG, f, u, kFcgKinds, maxit, 1,
+                             4, unit)))
       return st;
-    }
-    int64_t nb = 0;
-    HIP_TRY(timed(c, GMG_K_FCG, 0, GMG_F64, s,
-                  [&] { return gmg::launch_fcg_zq<TZ>(V, z, c->vq, c->partials, &nb, s); }));
-    HIP_TRY(timed(c, GMG_K_REDUCE, 0, GMG_F64, s,
-                  [&] { return gmg::launch_fcg_fin(0, c->state, c->partials, nb, nullptr, s); }));
-    HIP_TRY(timed(c, GMG_K_FCG, 0, GMG_F64, s, [&](gmg::Shape sh) {
-      return gmg::launch_fcg_dir<TZ>(V, z, u, c->vp, c->vq, c->vr, c->state, c->partials, &nb, s,
-                                     sh);
-    }));
-    HIP_TRY(timed(c, GMG_K_REDUCE, 0, GMG_F64, s,
-                  [&] { return gmg::launch_fcg_fin(1, c->state, c->partials, nb, nullptr, s); }));
-    HIP_TRY(timed(c, GMG_K_FCG, 0, GMG_F64, s, [&](gmg::Shape sh) {
-      return gmg::launch_fcg_update(V, c->vr, c->vq, mixed ? c->er32 : nullptr, c->state,
-                                    c->partials, &nb, s, sh);
-    }));
-    HIP_TRY(timed(c, GMG_K_REDUCE, 0, GMG_F64, s,
-                  [&] { return gmg::launch_fcg_fin(2, c->state, c->partials, nb, c->dhist, s); }));
-    HIP_TRY(hipMemcpyAsync(c->hstate, c->state, sizeof(CgState), hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipStreamSynchronize(s));
-    if (c->hstate->done) break;
   }
   // the last step (the direction kernels apply each earlier one); skipped
   // after a breakdown before the step
   HIP_TRY(timed(c, GMG_K_AUX, 0, GMG_F64, s,
                 [&] { return gmg::launch_cg_final_update(V, u, c->vp, c->state, s); }));
   const CgState hs = *c->hstate;
-  if (history)
-    HIP_TRY(hipMemcpyAsync(history, c->dhist, (size_t)(hs.iter + 1) * sizeof(double),
-                           hipMemcpyDeviceToHost, s));
+  if (history) memcpy(history, c->hhist, (size_t)(hs.iter + 1) * sizeof(double));
   double rr = 0.0;
   if ((st = residual_norm2<double>(c, f, u, c->vt, nullptr, &rr, s))) return st;
   if (iters) *iters = hs.iter;
@@ -1043,6 +1168,19 @@ int gmg_set_launch(gmg_ctx* c, int kernel, int level, int prec, int rows, int gr
   }
   if (group < 0 || group > 4096) return fail(GMG_EINVAL, "group must be in [0, 4096]");
   c->shape[gmg::tslot(kernel, level, prec)] = gmg::Shape{rows, group};
+  drop_graphs(c);  // captured launches carry the old shape
+  return GMG_OK;
+}
+
+int gmg_solver_polls(const gmg_ctx* c) {
+  if (!c || c->batch) return fail(GMG_EINVAL, "context is NULL or batched");
+  return c->polls;
+}
+
+int gmg_set_graphs(gmg_ctx* c, int enable) {
+  if (!c || c->batch) return fail(GMG_EINVAL, "context is NULL or batched");
+  c->graphs_on = enable != 0;
+  if (!c->graphs_on) drop_graphs(c);
   return GMG_OK;
 }
 
@@ -1068,6 +1206,7 @@ int gmg_autotune(gmg_ctx* c, int reps, void* stream) {
     (void)hipEventDestroy(ea);
     return fail(GMG_EHIP, "hipEventCreate failed");
   }
+  drop_graphs(c);
   int st = c->p.prec_precond == GMG_F32 ? tune_levels<float>(c, reps, s, ea, eb)
                                          : tune_levels<double>(c, reps, s, ea, eb);
   if (!st) st = tune_solver(c, reps, s, ea, eb);
@@ -1219,6 +1358,7 @@ int gmg_vcycle(gmg_ctx* c, const void* f, void* u, void* stream) {
 int gmg_solve(gmg_ctx* c, const double* f, double* u, double rtol, int maxit, int* iters,
               double* relres, double* history, void* stream) {
   if (!c || c->batch) return fail(GMG_EINVAL, "context is NULL or batched");
+  c->polls = 0;
   int st;
   if ((st = check_ptrs({f, u}))) return st;
   if (!(rtol > 0.0)) return fail(GMG_EINVAL, "rtol must be > 0");
@@ -1226,83 +1366,104 @@ int gmg_solve(gmg_ctx* c, const double* f, double* u, double rtol, int maxit, in
   if (f == u) return fail(GMG_EINVAL, "f and u must not overlap");
   hipStream_t s = as_stream(stream);
   if (iters) *iters = 0;
+  if (relres) *relres = 0.0;
   if (history) history[0] = 1.0;
-  const Lvl<double> V0 = gmg::view<double>(c, 0);
-  double rr0 = 0.0, rr = 0.0;
-  if (c->p.prec_precond == GMG_F64) {
-    // The first smoothing step of every cycle computes f - A u of the current
-    // iterate in its forward sweep; its norm is the convergence test of the
-    // previous cycle, so no separate residual pass is needed.  The step writes
-    // lev[0].ualt, so u still holds the tested iterate when the loop stops.
-    double* ualt0 = static_cast<double*>(c->lev[0].ualt);
-    const double rho = c->p.rho;
-    for (int it = 0;; ++it) {
-      int64_t nb = 0;
-      HIP_TRY(timed(c, GMG_K_SMOOTH, 0, GMG_F64, s, [&](gmg::Shape sh) {
-        return gmg::launch_smooth_norm<double>(V0, f, u, ualt0, rho, c->partials, &nb, s, sh);
-      }));
-      if ((st = reduce_read(c, nb, &rr, s))) return st;
-      if (it == 0) {
-        rr0 = rr;
-        if (relres) *relres = rr0 > 0.0 ? 1.0 : 0.0;
-        if (!isfinite(rr0)) return fail(GMG_ENOCONV, "initial residual is not finite");
-        if (rr0 == 0.0) return GMG_OK;
-      } else {
-        const double rel = sqrt(rr / rr0);
-        if (history) history[it] = rel;
-        if (iters) *iters = it;
-        if (relres) *relres = rel;
-        if (!isfinite(rel)) return fail(GMG_ENOCONV, "residual became non-finite at cycle %d", it);
-        if (rel < rtol) return GMG_OK;
+  if ((st = ensure_hist(c, maxit))) return st;
+  const bool f64 = c->p.prec_precond == GMG_F64;
+  CgState init{};
+  init.maxit = maxit;
+  init.rtol = rtol;
+  HIP_TRY(hipMemcpyAsync(c->state, &init, sizeof(CgState), hipMemcpyHostToDevice, s));
+  const double rho = c->p.rho;
+  double* ualt0 = static_cast<double*>(c->lev[0].ualt);
+  {
+    GateScope gate(c);
+    if (f64) {
+      // The first smoothing step of every cycle computes f - A u of the
+      // current iterate in its forward sweep; its norm is the stopping test
+      // of the previous cycle, so no separate residual pass is needed.  The
+      // step writes lev[0].ualt, so u still holds the tested iterate when
+      // the solve stops (the next cycle's kernels are gated off).
+      auto smooth_test = [&](hipStream_t q, int init_) -> int {
+        const Lvl<double> V0 = gmg::view<double>(c, 0);
+        int64_t nb = 0;
+        HIP_TRY(timed(c, GMG_K_SMOOTH, 0, GMG_F64, q, [&](gmg::Shape sh) {
+          return gmg::launch_smooth_norm<double>(V0, f, u, ualt0, rho, c->partials, &nb, q, sh);
+        }));
+        HIP_TRY(timed(c, GMG_K_REDUCE, 0, GMG_F64, q, [&] {
+          return gmg::launch_mg_fin(c->state, c->partials, nb, init_, c->dhist, q);
+        }));
+        return GMG_OK;
+      };
+      if ((st = smooth_test(s, 1))) return st;
+      auto unit = [&](hipStream_t q, int) -> int {
+        const int sv = vcycle_impl<double>(c, f, u, q, false, true);
+        return sv ? sv : smooth_test(q, 0);
+      };
+      if ((st = run_iterations(c, s, GK_MG, f, u, kVcycleKinds, maxit, 1, 4, unit))) return st;
+    } else {
+      // FP64 iterative refinement with FP32 cycles: e = V32(r32) from a zero
+      // guess, then u' = u + e, r = f - A u', r32 and ||r||^2 in one fused
+      // pass.  The iterate alternates between the caller's u (before odd
+      // steps) and an internal buffer (before even steps).
+      {
+        const Lvl<double> V0 = gmg::view<double>(c, 0);
+        int64_t nb = 0;
+        HIP_TRY(timed(c, GMG_K_RESIDUAL, 0, GMG_F64, s, [&](gmg::Shape sh) {
+          return gmg::launch_stencil<double>(V0, Stencil::RESIDUAL_NORM_DOWN, u, f, c->vr,
+                                             c->er32, c->partials, &nb, s, sh);
+        }));
+        HIP_TRY(timed(c, GMG_K_REDUCE, 0, GMG_F64, s, [&] {
+          return gmg::launch_mg_fin(c->state, c->partials, nb, 1, c->dhist, s);
+        }));
       }
-      if (it == maxit) break;
-      if ((st = vcycle_impl<double>(c, f, u, s, false, true))) return st;
-    }
-    return fail(GMG_ENOCONV, "no convergence to %g in %d cycles", rtol, maxit);
-  }
-  // FP64 iterative refinement with FP32 cycles: e = V32(r32) from a zero guess,
-  // then u' = u + e, r = f - A u', r32 and ||r||^2 in one fused pass.  The
-  // iterate alternates between the caller's u and an internal buffer.
-  if ((st = residual_norm2<double>(c, f, u, c->vr, c->er32, &rr0, s))) return st;
-  if (relres) *relres = rr0 > 0.0 ? 1.0 : 0.0;
-  if (!isfinite(rr0)) return fail(GMG_ENOCONV, "initial residual is not finite");
-  if (rr0 == 0.0) return GMG_OK;
-  double* ucur = u;
-  double* unext = c->vt;
-  int status = GMG_ENOCONV;
-  for (int it = 1; it <= maxit; ++it) {
-    if ((st = vcycle_impl<float>(c, c->er32, c->eu32, s, true, false))) return st;
-    int64_t nb = 0;
-    HIP_TRY(timed(c, GMG_K_CORRECT, 0, GMG_F64, s, [&](gmg::Shape sh) {
-      return gmg::launch_correct_residual(V0, ucur, c->eu32, f, unext, c->er32, c->partials, &nb, s, sh);
-    }));
-    std::swap(ucur, unext);
-    if ((st = reduce_read(c, nb, &rr, s))) return st;
-    const double rel = sqrt(rr / rr0);
-    if (history) history[it] = rel;
-    if (iters) *iters = it;
-    if (relres) *relres = rel;
-    if (!isfinite(rel)) {
-      status = GMG_EINVAL;  // marker: non-finite
-      break;
-    }
-    if (rel < rtol) {
-      status = GMG_OK;
-      break;
+      auto unit = [&](hipStream_t q, int r) -> int {
+        double* ucur = r == 0 ? u : c->vt;
+        double* unext = r == 0 ? c->vt : u;
+        const int sv = vcycle_impl<float>(c, c->er32, c->eu32, q, true, false);
+        if (sv) return sv;
+        const Lvl<double> V0 = gmg::view<double>(c, 0);
+        int64_t nb = 0;
+        HIP_TRY(timed(c, GMG_K_CORRECT, 0, GMG_F64, q, [&](gmg::Shape sh) {
+          return gmg::launch_correct_residual(V0, ucur, c->eu32, f, unext, c->er32, c->partials,
+                                              &nb, q, sh);
+        }));
+        HIP_TRY(timed(c, GMG_K_REDUCE, 0, GMG_F64, q, [&] {
+          return gmg::launch_mg_fin(c->state, c->partials, nb, 0, c->dhist, q);
+        }));
+        return GMG_OK;
+      };
+      if ((st = run_iterations(c, s, GK_IR, f, u, kIrKinds, maxit, 2, 4, unit))) return st;
     }
   }
-  if (ucur != u)
-    HIP_TRY(hipMemcpyAsync(u, ucur, (size_t)c->lev[0].elems * sizeof(double),
+  const CgState hs = *c->hstate;
+  // refinement: after an odd number of steps the iterate is in the internal buffer
+  bool pending = false;
+  if (!f64 && (hs.iter & 1)) {
+    HIP_TRY(hipMemcpyAsync(u, c->vt, (size_t)c->lev[0].elems * sizeof(double),
                            hipMemcpyDeviceToDevice, s));
-  HIP_TRY(hipStreamSynchronize(s));
-  if (status == GMG_OK) return GMG_OK;
-  if (status == GMG_EINVAL) return fail(GMG_ENOCONV, "residual became non-finite");
-  return fail(GMG_ENOCONV, "no convergence to %g in %d cycles", rtol, maxit);
+    pending = true;
+  }
+  if (history && hs.iter >= 0) memcpy(history, c->hhist, (size_t)(hs.iter + 1) * sizeof(double));
+  if (pending) {
+    HIP_TRY(hipStreamSynchronize(s));
+    ++c->polls;
+  }
+  if (iters) *iters = hs.iter;
+  if (relres) *relres = hs.rr0 > 0.0 ? sqrt(hs.rr / hs.rr0) : (hs.rr0 == 0.0 ? 0.0 : NAN);
+  if (hs.status == 2) {
+    if (hs.iter == 0) return fail(GMG_ENOCONV, "initial residual is not finite");
+    return fail(GMG_ENOCONV, "residual became non-finite at cycle %d", hs.iter);
+  }
+  if (!hs.done || hs.status == 1)
+    return fail(GMG_ENOCONV, "no convergence to %g in %d cycles", rtol, maxit);
+  return GMG_OK;
 }
 
 int pcg_solve(gmg_ctx* c, const double* f, double* u, double rtol, int maxit, int precond,
               int* iters, double* relres, double* history, void* stream) {
   if (!c || c->batch) return fail(GMG_EINVAL, "context is NULL or batched");
+  c->polls = 0;
   int st;
   if ((st = check_ptrs({f, u}))) return st;
   if (!(rtol > 0.0)) return fail(GMG_EINVAL, "rtol must be > 0");
@@ -1338,38 +1499,32 @@ int pcg_solve(gmg_ctx* c, const double* f, double* u, double rtol, int maxit, in
                 [&] { return gmg::launch_fill<double>(c->vp, n0, 0.0, s); }));
   HIP_TRY(timed(c, GMG_K_AUX, 0, GMG_F64, s,
                 [&] { return gmg::launch_fill<double>(c->vq, n0, 0.0, s); }));
-  // the host polls the device state only every `chunk` iterations; kernels of
-  // iterations after convergence return at once
-  int done_iters = 0;
-  int chunk = 4;
-  while (true) {
-    HIP_TRY(hipMemcpyAsync(c->hstate, c->state, sizeof(CgState), hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipStreamSynchronize(s));
-    if (c->hstate->done || done_iters >= maxit) break;
-    if (done_iters > 0) chunk = predicted_chunk(*c->hstate, chunk);
-    const int nq = std::min(chunk, maxit - done_iters);
-    for (int q = 0; q < nq; ++q) {
+  // iterations in predicted batches; kernels of iterations after convergence
+  // return at once
+  {
+    GateScope gate(c);
+    auto unit = [&](hipStream_t q, int) -> int {
+      const Lvl<double> Vg = gmg::view<double>(c, 0);
       int64_t nb1 = 0, nb2 = 0;
-      HIP_TRY(timed(c, GMG_K_CG_SPMV, 0, GMG_F64, s, [&](gmg::Shape sh) {
-        return gmg::launch_cg_p1(V, u, c->vp, c->vz, c->vq, c->state, c->partials, &nb1, s, sh);
+      HIP_TRY(timed(c, GMG_K_CG_SPMV, 0, GMG_F64, q, [&](gmg::Shape sh) {
+        return gmg::launch_cg_p1(Vg, u, c->vp, c->vz, c->vq, c->state, c->partials, &nb1, q, sh);
       }));
-      HIP_TRY(timed(c, GMG_K_REDUCE, 0, GMG_F64, s,
-                    [&] { return gmg::launch_cg_fin1(c->state, c->partials, nb1, s); }));
-      HIP_TRY(timed(c, GMG_K_CG_TRIDIAG, 0, GMG_F64, s, [&](gmg::Shape sh) {
-        return gmg::launch_cg_p2(V, c->vr, c->vq, c->vz, c->state, 0, c->partials, &nb2, s, sh);
+      HIP_TRY(timed(c, GMG_K_REDUCE, 0, GMG_F64, q,
+                    [&] { return gmg::launch_cg_fin1(c->state, c->partials, nb1, q); }));
+      HIP_TRY(timed(c, GMG_K_CG_TRIDIAG, 0, GMG_F64, q, [&](gmg::Shape sh) {
+        return gmg::launch_cg_p2(Vg, c->vr, c->vq, c->vz, c->state, 0, c->partials, &nb2, q, sh);
       }));
-      HIP_TRY(timed(c, GMG_K_REDUCE, 0, GMG_F64, s, [&] {
-        return gmg::launch_cg_fin2(c->state, c->partials, nb2, 0, c->dhist, s);
+      HIP_TRY(timed(c, GMG_K_REDUCE, 0, GMG_F64, q, [&] {
+        return gmg::launch_cg_fin2(c->state, c->partials, nb2, 0, c->dhist, q);
       }));
-    }
-    done_iters += nq;
+      return GMG_OK;
+    };
+    if ((st = run_iterations(c, s, GK_PCG, f, u, kPcgKinds, maxit, 1, 4, unit))) return st;
   }
   HIP_TRY(timed(c, GMG_K_AUX, 0, GMG_F64, s,
                 [&] { return gmg::launch_cg_final_update(V, u, c->vp, c->state, s); }));
   const CgState hs = *c->hstate;
-  if (history && hs.iter >= 0)
-    HIP_TRY(hipMemcpyAsync(history, c->dhist, (size_t)(hs.iter + 1) * sizeof(double),
-                           hipMemcpyDeviceToHost, s));
+  if (history && hs.iter >= 0) memcpy(history, c->hhist, (size_t)(hs.iter + 1) * sizeof(double));
   double rr = 0.0;
   if ((st = residual_norm2<double>(c, f, u, c->vt, nullptr, &rr, s))) return st;
   if (iters) *iters = hs.iter;

@@ -34,6 +34,10 @@ struct Lvl {
   // faces, added to the diagonal (all zero with periodic boundaries)
   const T* __restrict__ wall;
   int bch;  // 0 doubly periodic, 1 Dirichlet side walls (prolongation reflects)
+  // device flag (a solver's "done"): kernels given a view with a gate return
+  // at once while it is set, so iterations enqueued past convergence cost
+  // only their launches and the host reads the solver state rarely
+  const int* gate = nullptr;
 };
 
 // Scalars shared between the kernels of one CG solve; lives in device memory
@@ -41,7 +45,9 @@ struct Lvl {
 struct CgState {
   double alpha, beta, kappa, sigma;  // step, direction update, <r,z>, <p,Ap>
   double rr, rr0, thresh2;           // ||r||^2, ||r_0||^2, rtol^2 ||r_0||^2
-  int iter, done, maxit, status;     // status: 0 running/converged, 2 breakdown
+  int iter, done, maxit, status;     // status: 0 running/converged, 1 maxit,
+                                     // 2 non-finite, 3 breakdown
+  double rtol;                       // multigrid / refinement stopping test
 };
 
 // One work item of a grouped launch: one kernel applied to one level of one
@@ -121,8 +127,26 @@ namespace gmg {
 struct Batch;
 }
 
+// An instantiated hipGraph of a batch of one solver's iterations, for one
+// pair of caller fields (their addresses are in the kernels' arguments).
+struct gmg_graph {
+  int kind;
+  const void *f, *u;
+  hipGraphExec_t exec;
+};
+
 struct gmg_ctx {
   gmg_params p;
+  // the iterative solvers' iterations are enqueued as hipGraph replays
+  // (gmg_set_graphs); graphs are cached per solver and caller fields and
+  // dropped when a launch shape changes
+  bool graphs_on = true;
+  std::vector<gmg_graph> graphs;
+  hipStream_t cap = nullptr;         // capture stream (non-blocking, default priority)
+  // set while a solver enqueues its iterations: views then carry it as their
+  // gate (the device "done" flag of the solver state)
+  const int* gate = nullptr;
+  int polls = 0;                     // host waits for device scalars in the last solve
   // launch shape per [kind][level][prec] (gmg::tslot), set by gmg_set_launch
   // or gmg_autotune; every context starts with the default shapes
   std::vector<gmg::Shape> shape =
@@ -150,6 +174,7 @@ struct gmg_ctx {
   gmg::CgState* state = nullptr;     // device
   gmg::CgState* hstate = nullptr;    // pinned host mirror
   double* dhist = nullptr;           // device history buffer
+  double* hhist = nullptr;           // its pinned host mirror (dhist_len values)
   int dhist_len = 0;
   double* hscal = nullptr;           // pinned host scalars
   // gmg_solve_host: z-contiguous staging and x-contiguous f, u (FP64, level
@@ -231,6 +256,10 @@ hipError_t launch_cg_final_update(const Lvl<double>& L, double* u, const double*
                                   const CgState* st, hipStream_t s);
 hipError_t launch_reduce(const double* partials, int64_t nblocks, int ncomp, double* out,
                          hipStream_t s);
+// multigrid / refinement: ||f - A u||^2 from the partials -> relative
+// residual, history, stopping test (init: the initial residual)
+hipError_t launch_mg_fin(CgState* st, const double* partials, int64_t nblocks, int init,
+                         double* hist, hipStream_t s);
 // flexible CG (variable preconditioner)
 template <typename TZ>
 hipError_t launch_fcg_zq(const Lvl<double>& L, const TZ* z, const double* q, double* partials,
@@ -250,6 +279,9 @@ hipError_t launch_fcg_fin(int which, CgState* st, const double* partials, int64_
 
 template <typename T>
 hipError_t launch_fill(T* p, int64_t n, T v, hipStream_t s);
+// dst = src over the field of level L (gated by L.gate)
+template <typename T>
+hipError_t launch_copy_level(const Lvl<T>& L, const T* src, T* dst, hipStream_t s);
 // streaming copy of n doubles (bandwidth measurement)
 hipError_t launch_copy_probe(const double* src, double* dst, int64_t n, hipStream_t s);
 // canonical z-contiguous (j*nx+i)*nz+k <-> x-contiguous (j*nz+k)*ldx+i

@@ -41,6 +41,13 @@ __device__ __forceinline__ int xcd_remap(int b, int n) {
   return x * q + min(x, r) + (b >> 3);
 }
 
+// A gated launch (a solver's iteration enqueued past its convergence)
+// returns at once; the flag is uniform, so whole workgroups leave together.
+template <typename T>
+__device__ __forceinline__ bool gated(const Lvl<T>& L) {
+  return L.gate && *L.gate;
+}
+
 template <typename T>
 struct Col {
   int64_t base;              // index of (i, j, 0)
@@ -359,6 +366,7 @@ __global__ __launch_bounds__(64 * SR) void k_stencil(Lvl<T> L, const T* __restri
                                                      double* __restrict__ partials, int nti,
                                                      int ntj, int group) {
   constexpr int CH = sizeof(T) == 8 ? 4 : 8;
+  if (gated(L)) return;
   const Geo g =
       stencil_geo<SR>(L.nx, L.ny, L.nz, nti, ntj, group, xcd_remap(blockIdx.x, gridDim.x));
   __shared__ Prof<T> sp[KSEG];
@@ -930,6 +938,7 @@ __device__ __forceinline__ void line_body(const Lvl<T>& L, const LineArgs<T>& a,
 template <typename T, int HALF, int MODE, bool NB = false>
 __global__ __launch_bounds__(NTHREADS) void k_line(Lvl<T> L, LineArgs<T> a, int nti, int ntj,
                                                    int group) {
+  if (gated(L)) return;
   if constexpr (MODE == LINE_CG) {
     if (a.st->done) return;  // uniform: the solve has already stopped
   }
@@ -979,6 +988,7 @@ __device__ __forceinline__ PcrRow<T> pcr_step(const PcrRow<T>& r, const PcrRow<T
 
 template <typename T, int MODE>  // LINE_SOLVE or LINE_SMOOTH
 __global__ __launch_bounds__(NTHREADS) void k_line_pcr(Lvl<T> L, LineArgs<T> a, int ncols) {
+  if (gated(L)) return;
   constexpr int NR = 128;
   __shared__ T s_sub[NR], s_sup[NR], s_dg[NR], s_dz[NR];
   const int nz = L.nz;
@@ -1207,6 +1217,7 @@ __global__ __launch_bounds__(64 * SR) void k_resrestrict(Lvl<T> F, Lvl<T> C,
                                                          const T* __restrict__ f,
                                                          T* __restrict__ fc, int nti, int ntj,
                                                          int group) {
+  if (gated(F)) return;
   resrestrict_body<T, SR>(F, C, u, f, fc, nti, ntj, group, xcd_remap(blockIdx.x, gridDim.x));
 }
 
@@ -1320,6 +1331,7 @@ __global__ __launch_bounds__(64 * SR) void k_correct_residual(
     Lvl<double> L, const double* __restrict__ u, const float* __restrict__ e,
     const double* __restrict__ f, double* __restrict__ uout, float* __restrict__ r32,
     double* __restrict__ partials, int nti, int ntj, int group) {
+  if (gated(L)) return;
   correct_residual_body<SR>(L, u, e, f, uout, r32, partials, nti, ntj, group,
                             xcd_remap(blockIdx.x, gridDim.x));
 }
@@ -1415,6 +1427,7 @@ __global__ __launch_bounds__(64 * SR) void k_prolongate(Lvl<T> C, Lvl<T> F,
                                                         const T* __restrict__ uc,
                                                         T* __restrict__ uf, int nti, int ntj,
                                                         int group) {
+  if (gated(F)) return;
   prolongate_body<T, SR>(C, F, uc, uf, nti, ntj, group, xcd_remap(blockIdx.x, gridDim.x));
 }
 
@@ -1461,7 +1474,7 @@ __global__ __launch_bounds__(64 * SR) void k_cg_p1(Lvl<double> L, double* __rest
                                                    const CgState* __restrict__ st,
                                                    double* __restrict__ partials, int nti,
                                                    int ntj, int group) {
-  if (st->done) return;  // uniform: the solve has already stopped
+  if (st->done || gated(L)) return;  // uniform: the solve has already stopped
   constexpr int CH = 2;
   const double alpha = st->alpha, beta = st->beta;
   const Geo g =
@@ -1508,6 +1521,7 @@ __global__ __launch_bounds__(NTHREADS) void k_fcg_zq(Lvl<double> L, const TZ* __
                                                      const double* __restrict__ q,
                                                      double* __restrict__ partials, int nti,
                                                      int ntj) {
+  if (gated(L)) return;
   const int b = xcd_remap(blockIdx.x, gridDim.x);
   const int ti = b % nti;
   const int r1 = b / nti;
@@ -1574,6 +1588,7 @@ __global__ __launch_bounds__(64 * SR) void k_fcg_dir(Lvl<double> L, const TZ* __
                                                      const CgState* __restrict__ st,
                                                      double* __restrict__ partials, int nti,
                                                      int ntj, int group) {
+  if (st->done || gated(L)) return;
   const double beta = st->beta, aprev = st->alpha;
   const Geo g =
       stencil_geo<SR>(L.nx, L.ny, L.nz, nti, ntj, group, xcd_remap(blockIdx.x, gridDim.x));
@@ -1644,7 +1659,8 @@ __global__ __launch_bounds__(64 * SR) void k_fcg_update(Lvl<double> L, double* _
                                                         const CgState* __restrict__ st,
                                                         double* __restrict__ partials, int nti,
                                                         int ntj, int group) {
-  if (st->status == 3) return;  // breakdown: r stays the last residual
+  // stopped (a breakdown included: r stays the last residual)
+  if (st->done || gated(L)) return;
   const double alpha = st->alpha;
   const Geo g =
       stencil_geo<SR>(L.nx, L.ny, L.nz, nti, ntj, group, xcd_remap(blockIdx.x, gridDim.x));
@@ -1860,6 +1876,7 @@ __global__ __launch_bounds__(NTHREADS) void k_cg_fin2(CgState* st,
 __global__ __launch_bounds__(NTHREADS) void k_fcg_fin_beta(CgState* st,
                                                            const double* __restrict__ partials,
                                                            int64_t n) {
+  if (st->done) return;
   double r[1];
   reduce_fixed<1>(partials, n, r);
   if (threadIdx.x == 0) st->beta = st->iter == 0 ? 0.0 : -r[0] / st->sigma;
@@ -1869,6 +1886,7 @@ __global__ __launch_bounds__(NTHREADS) void k_fcg_fin_beta(CgState* st,
 __global__ __launch_bounds__(NTHREADS) void k_fcg_fin_alpha(CgState* st,
                                                             const double* __restrict__ partials,
                                                             int64_t n) {
+  if (st->done) return;
   double r[2];
   reduce_fixed<2>(partials, n, r);
   if (threadIdx.x == 0) {
@@ -1887,7 +1905,7 @@ __global__ __launch_bounds__(NTHREADS) void k_fcg_fin_alpha(CgState* st,
 __global__ __launch_bounds__(NTHREADS) void k_fcg_fin_res(CgState* st,
                                                           const double* __restrict__ partials,
                                                           int64_t n, double* __restrict__ hist) {
-  if (st->status == 3) return;  // breakdown: keep its status and the count
+  if (st->done) return;  // stopped (a breakdown: keep its status and the count)
   double r[1];
   reduce_fixed<1>(partials, n, r);
   if (threadIdx.x == 0) {
@@ -1900,6 +1918,55 @@ __global__ __launch_bounds__(NTHREADS) void k_fcg_fin_res(CgState* st,
       st->status = 2;
       st->done = 1;
     } else if (rr < st->thresh2) {
+      st->done = 1;
+    } else if (it >= st->maxit) {
+      st->status = 1;
+      st->done = 1;
+    }
+  }
+}
+
+// Multigrid and iterative refinement (Sec. 2.2, stopping test): ||f - A u||^2
+// of the current iterate from the partials.  init: the initial residual (the
+// reference of the relative residual; a zero one ends the solve, a
+// non-finite one fails it).  Otherwise the cycle is counted, its relative
+// residual goes to the history, and the solve stops below rtol, at maxit or
+// on a non-finite norm.  thresh2 = rtol^2 ||r_0||^2 serves the host's
+// prediction of the iterations still needed.
+__global__ __launch_bounds__(NTHREADS) void k_mg_fin(CgState* st,
+                                                     const double* __restrict__ partials,
+                                                     int64_t n, int init,
+                                                     double* __restrict__ hist) {
+  if (st->done) return;
+  double r[1];
+  reduce_fixed<1>(partials, n, r);
+  if (threadIdx.x == 0) {
+    const double rr = r[0];
+    st->rr = rr;
+    if (init) {
+      st->rr0 = rr;
+      st->thresh2 = st->rtol * st->rtol * rr;
+      st->iter = 0;
+      hist[0] = 1.0;
+      if (!isfinite(rr)) {
+        st->status = 2;
+        st->done = 1;
+      } else if (rr == 0.0) {
+        st->done = 1;
+      } else if (st->maxit <= 0) {
+        st->status = 1;
+        st->done = 1;
+      }
+      return;
+    }
+    const int it = st->iter + 1;
+    st->iter = it;
+    const double rel = sqrt(rr / st->rr0);
+    hist[it] = rel;
+    if (!isfinite(rel)) {
+      st->status = 2;
+      st->done = 1;
+    } else if (rel < st->rtol) {
       st->done = 1;
     } else if (it >= st->maxit) {
       st->status = 1;
@@ -1948,6 +2015,18 @@ __global__ __launch_bounds__(NTHREADS) void k_cg_final_update(Lvl<double> L,
   for (int64_t g = (int64_t)blockIdx.x * NTHREADS + threadIdx.x; g < n;
        g += (int64_t)gridDim.x * NTHREADS)
     u[g] += alpha * p[g];
+}
+
+// dst = src over a level's field (both in its layout), gated like the
+// iteration it belongs to
+template <typename T>
+__global__ __launch_bounds__(NTHREADS) void k_copy_level(Lvl<T> L, const T* __restrict__ src,
+                                                         T* __restrict__ dst) {
+  if (gated(L)) return;
+  const int64_t n = (int64_t)L.ny * L.nz * L.ldx;
+  for (int64_t g = (int64_t)blockIdx.x * NTHREADS + threadIdx.x; g < n;
+       g += (int64_t)gridDim.x * NTHREADS)
+    dst[g] = src[g];
 }
 
 template <typename T>
@@ -2336,9 +2415,23 @@ hipError_t launch_cg_final_update(const Lvl<double>& L, double* u, const double*
   return hipGetLastError();
 }
 
+hipError_t launch_mg_fin(CgState* st, const double* partials, int64_t nblocks, int init,
+                         double* hist, hipStream_t s) {
+  hipLaunchKernelGGL(k_mg_fin, dim3(1), dim3(NTHREADS), 0, s, st, partials, nblocks, init, hist);
+  return hipGetLastError();
+}
+
 hipError_t launch_reduce(const double* partials, int64_t nblocks, int ncomp, double* out,
                          hipStream_t s) {
   hipLaunchKernelGGL(k_reduce, dim3(1), dim3(NTHREADS), 0, s, partials, nblocks, ncomp, out);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_copy_level(const Lvl<T>& L, const T* src, T* dst, hipStream_t s) {
+  const int64_t n = (int64_t)L.ny * L.nz * L.ldx;
+  hipLaunchKernelGGL((k_copy_level<T>), dim3(grid_stride_blocks(n)), dim3(NTHREADS), 0, s, L,
+                     src, dst);
   return hipGetLastError();
 }
 
@@ -2367,6 +2460,7 @@ hipError_t launch_add_f32_to_f64(double* u, const float* e, int64_t n, hipStream
   template hipError_t launch_prolongate<T>(const Lvl<T>&, const Lvl<T>&, const T*, T*,        \
                                            hipStream_t, Shape);                               \
   template hipError_t launch_fill<T>(T*, int64_t, T, hipStream_t);                            \
+  template hipError_t launch_copy_level<T>(const Lvl<T>&, const T*, T*, hipStream_t);         \
   template hipError_t launch_line_solve_scaled<T>(const Lvl<T>&, const T*, T*, T, hipStream_t, \
                                                   Shape);                                     \
   template hipError_t launch_smooth_norm<T>(const Lvl<T>&, const T*, const T*, T*, T, double*, \
