@@ -490,7 +490,8 @@ int vcycle_impl(gmg_ctx* c, const T* f0, T* u0, hipStream_t s, bool zero_guess =
     T* other = (d == 0) ? u0
                         : (cur[d] == c->lev[d].u ? static_cast<T*>(c->lev[d].ualt)
                                                  : static_cast<T*>(c->lev[d].u));
-    if (c->shape[gmg::tslot(GMG_K_PROLONG_SMOOTH, d, P)].rows == 2) {
+    const int fold = c->shape[gmg::tslot(GMG_K_PROLONG_SMOOTH, d, P)].rows;
+    if (fold == 2 || fold == 3) {
       // one kernel: smooth u + P u_c without storing it
       HIP_TRY(timed(c, GMG_K_PROLONG_SMOOTH, d, P, s, [&](gmg::Shape sh) {
         return gmg::launch_prolong_smooth<T>(V, C, fl[d], cur[d], cur[d + 1], other, rho, s, sh);
@@ -793,11 +794,12 @@ int fcg_impl(gmg_ctx* c, const double* f, double* u, double rtol, int maxit, int
 // group (0 = row-major).  Stencil kernels: 4, 8 or 16 rows; line kernels: the
 // twisted elimination (4) and, for the line solve and the smoother, one
 // wavefront per column by cyclic reduction (1, tile order irrelevant); the
-// smoother also with its neighbours staged in LDS (2).
+// smoother also with its neighbours staged in LDS (2), and staged with two
+// wavefronts per column by direct loads (3).
 constexpr int kStencilRows[] = {4, 8, 16};
 constexpr int kLineRows[] = {4};
 constexpr int kLinePcrRows[] = {4, 1};
-constexpr int kSmoothRows[] = {4, 1, 2};
+constexpr int kSmoothRows[] = {4, 1, 2, 3};
 constexpr int kTuneGroups[] = {0, 1, 2, 4, 8};
 
 enum class Cand { STENCIL, LINE, LINE_PCR, SMOOTH };
@@ -819,7 +821,7 @@ int tune_kind(gmg_ctx* c, int kind, int level, int prec, Cand cand, int nti, int
   const int nrows = cand == Cand::STENCIL    ? 3
                     : cand == Cand::LINE     ? 1
                     : cand == Cand::LINE_PCR ? 2
-                                             : 3;
+                                             : 4;
   for (int q0 = 0; q0 < nrows; ++q0) {
     const int rows = rows_c[q0];
     for (int group : kTuneGroups) {
@@ -912,9 +914,11 @@ int tune_levels(gmg_ctx* c, int reps, hipStream_t s, hipEvent_t ea, hipEvent_t e
       // the two kernels
       Shape fused{4, 0};
       float best_ms = ms_smooth + ms_prol;
-      for (int group : kTuneGroups) {
+      for (int q0 = 0; q0 < 2 * (int)(sizeof(kTuneGroups) / sizeof(int)); ++q0) {
+        // rows 2: one wavefront per column; rows 3: two (where the level fits)
+        const int group = kTuneGroups[q0 >> 1];
         if (group >= ntl) continue;
-        const Shape sh{2, group};
+        const Shape sh{(q0 & 1) ? 3 : 2, group};
         auto go = [&] { return gmg::launch_prolong_smooth<T>(V, C, x2, x0, uc, x1, rho, s, sh); };
         HIP_TRY(go());  // warm-up
         HIP_TRY(hipEventRecord(ea, s));
@@ -1156,13 +1160,13 @@ int gmg_set_launch(gmg_ctx* c, int kernel, int level, int prec, int rows, int gr
   if ((st = check_prec(prec))) return st;
   const bool pcr_ok = kernel == GMG_K_LINE_SOLVE || kernel == GMG_K_SMOOTH;
   if (kernel == GMG_K_PROLONG_SMOOTH) {
-    if (rows != 4 && rows != 2)
-      return fail(GMG_EINVAL, "rows of the folded prolongation must be 4 (off) or 2, got %d",
-                  rows);
+    if (rows != 4 && rows != 2 && rows != 3)
+      return fail(GMG_EINVAL,
+                  "rows of the folded prolongation must be 4 (off), 2 or 3, got %d", rows);
   } else if (!(rows == 4 || rows == 8 || rows == 16 || (rows == 1 && pcr_ok) ||
-               (rows == 2 && kernel == GMG_K_SMOOTH))) {
+               ((rows == 2 || rows == 3) && kernel == GMG_K_SMOOTH))) {
     return fail(GMG_EINVAL,
-                "rows must be 4, 8 or 16 (1 for the line solve and smoother, 2 for the "
+                "rows must be 4, 8 or 16 (1 for the line solve and smoother, 2 or 3 for the "
                 "smoother), got %d",
                 rows);
   }

@@ -465,9 +465,12 @@ __device__ __forceinline__ float rcp_nr(float p) {
 }
 
 // One elimination step: pivot, its reciprocal and the new c' of this row.
+// The line kernels spell out every fused multiply-add, so that each kernel
+// (and the back sweep's recomputation of the forward sweep) rounds the same
+// way whatever the compiler would contract.
 template <typename T>
 __device__ __forceinline__ void elim_step(T diag, T cpv, T cnx, T cprev, T& piv, T& inv, T& c) {
-  piv = diag - cpv * cprev;
+  piv = fma(-cpv, cprev, diag);
   inv = rcp_nr(piv);
   c = cnx * inv;
 }
@@ -492,6 +495,12 @@ struct StepNb { T un, f, ex; };
 // ... and, with the prolongation folded in, one value of the coarse tile (cv).
 template <typename T>
 struct StepNbP { T un, f, ex, cv; };
+// Two wavefronts per column (W2): lanes 0 and 1 also bring the value left or
+// right of the tile in the wavefront's row (ew).
+template <typename T>
+struct StepNb2 { T un, f, ex, ew; };
+template <typename T>
+struct StepNbP2 { T un, f, ex, cv, ew; };
 
 // Body of the line kernels for tile b of a level (tiles of 32 columns x LROWS
 // rows, nti tiles across; wavefront w of the workgroup owns grid row
@@ -509,7 +518,19 @@ struct StepNbP { T un, f, ex, cv; };
 // ahead (double buffer) so that memory latency overlaps the elimination.  The
 // back sweep recomputes c' (and the pivots) of each G-row segment from its
 // checkpoint and substitutes backwards.
-template <typename T, int HALF, int MODE, bool NB = false>
+//
+// EX (nz == 2*HALF, the column heights of the workloads): no virtual rows, so
+// no clamped addresses and no masks; every stream advances by a running byte
+// offset per step instead of recomputing its address from the row.
+//
+// W2 (staged smoothers, EX): the two halves of a column go to two wavefronts
+// instead of two lanes of one: wavefront w owns tile row w >> 1 and half
+// w & 1 of 64 consecutive columns (tiles of 64 columns x 2 rows), so that
+// every load and store instruction covers 64 consecutive values of one layer
+// (512 bytes in FP64) instead of two 32-value runs of two layers, which the
+// memory system serves measurably faster; the halves swap their last
+// elimination coefficients through LDS.  Same arithmetic: the same iterate.
+template <typename T, int HALF, int MODE, bool NB = false, bool EX = false, bool W2 = false>
 __device__ __forceinline__ void line_body(const Lvl<T>& L, const LineArgs<T>& a, int nti,
                                           int ntj, int group, int b) {
   constexpr int NR = 2 * HALF;
@@ -520,6 +541,9 @@ __device__ __forceinline__ void line_body(const Lvl<T>& L, const LineArgs<T>& a,
   // smoothers only: horizontal neighbours through LDS instead of per-lane loads
   constexpr bool NBL = NB && kSmooth;
   static_assert(!NBL || LROWS == 4, "the staged halo assumes four rows per workgroup");
+  static_assert(!W2 || (NBL && EX), "two wavefronts per column: staged smoothers, exact heights");
+  constexpr int TROWS = W2 ? 2 : LROWS;   // grid rows of a tile
+  constexpr int TCOLS = W2 ? 64 : 32;     // columns of a tile
   constexpr int G = HALF < 8 ? HALF : 8;                       // back-sweep segment
   constexpr int NG = HALF / G;
   // prefetch chunk: bounded by the registers the buffered loads take
@@ -532,24 +556,40 @@ __device__ __forceinline__ void line_body(const Lvl<T>& L, const LineArgs<T>& a,
   constexpr int NCH = HALF / CH;
   constexpr uint32_t ES = sizeof(T);
   using V2 = typename Vec2<T>::type;
-  __shared__ T s_sub[NR], s_sup[NR], s_dg[NR], s_dz[NR];
+  // vertical profiles in each half's elimination order: step s of half h is
+  // row k = s (h = 0) or NR-1-s (h = 1), and holds the coupling to the
+  // previously eliminated row, the coupling to the next one, the diagonal
+  // and dz (identity rows beyond nz), so that a step reads them at a
+  // compile-time offset from its half's base, with no selects
+  // (the two halves' tables are 4 values apart from 2 HALF x 4, so that the
+  // lanes of the two halves, reading step s at once, hit different banks)
+  constexpr int PSH = HALF * 4 + 4;
+  __shared__ T s_ps[2 * PSH];
   const int nz = L.nz;
-  for (int k = threadIdx.x; k < NR; k += blockDim.x) {
+  for (int q = threadIdx.x; q < 2 * HALF; q += blockDim.x) {
+    const int h = q / HALF, st = q - h * HALF;
+    const int k = h ? NR - 1 - st : st;
     const bool real = k < nz;
-    s_sub[k] = real ? L.sub[k] : T(0);
-    s_sup[k] = real ? L.sup[k] : T(0);
-    s_dg[k] = real ? L.dg[k] : T(1);
-    s_dz[k] = real ? L.dz[k] : T(0);
+    const T sub = real ? L.sub[k] : T(0), sup = real ? L.sup[k] : T(0);
+    T* pq = s_ps + h * PSH + 4 * st;
+    pq[0] = h ? sup : sub;
+    pq[1] = h ? sub : sup;
+    pq[2] = real ? L.dg[k] : T(1);
+    pq[3] = real ? L.dz[k] : T(0);
   }
   __syncthreads();
   int ti, tj, kb_unused;
   tile_coords(b, nti, ntj, group, ti, tj, kb_unused);
   const int lane = threadIdx.x & 63;
-  const int half = lane >> 5;
-  const int i = ti * 32 + (lane & 31);
+  const int wv = (int)(threadIdx.x >> 6);
+  // W2: the half is the wavefront's (uniform); otherwise the lane's
+  const int half = W2 ? __builtin_amdgcn_readfirstlane(wv & 1) : lane >> 5;
+  const int xl = W2 ? lane : (lane & 31);
+  const int rt = W2 ? (wv >> 1) : wv;  // tile row of the wavefront
+  const int i = ti * TCOLS + xl;
   // the row of the wavefront, made visibly uniform so that row bases live in
   // SGPRs
-  const int j = tj * LROWS + __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const int j = tj * TROWS + __builtin_amdgcn_readfirstlane(rt);
   const bool active = (i < L.nx) && (j < L.ny);
   // inactive lanes compute on a valid column and store nothing; they still
   // take part in the cross-lane exchange.  With the staged neighbours they
@@ -573,16 +613,24 @@ __device__ __forceinline__ void line_body(const Lvl<T>& L, const LineArgs<T>& a,
   // wave contributes its own row (the lanes' current rows) and one halo value
   // per lane and step (wave 0 the row below, wave 3 the row above, waves 1
   // and 2 the side columns of the two halves' layers).
-  const int wv = (int)(threadIdx.x >> 6);
-  const int xl = lane & 31;
   const char* exbase = nullptr;
+  const char* ewbase = nullptr;  // W2: the value left (lane 0) or right (lane 1) of the tile
   int exh = half;
   if constexpr (NBL) {
-    const int i0 = ti * 32, j0 = tj * LROWS;
+    const int i0 = ti * TCOLS, j0 = tj * TROWS;
     auto wrapx = [&](int q) { q %= L.nx; return q < 0 ? q + L.nx : q; };
     auto wrapy = [&](int q) { q %= L.ny; return q < 0 ? q + L.ny : q; };
     int exrow, excol;
-    if (wv == 0) {
+    if (W2) {
+      // every lane: its column in the row below (tile row 0) or above
+      // (tile row 1) the tile
+      exrow = rt == 0 ? wrapy(j0 - 1) : wrapy(j0 + 2);
+      excol = ic;
+      // lanes 0 and 1: the value left and right of the tile in the row; the
+      // others load their own column (a cache hit) so that no lane branches
+      const int ewcol = lane == 0 ? wrapx(i0 - 1) : (lane == 1 ? wrapx(i0 + 64) : ic);
+      ewbase = reinterpret_cast<const char*>(a.a + (int64_t)jc * jstride + ewcol);
+    } else if (wv == 0) {
       exrow = wrapy(j0 - 1);
       excol = ic;
     } else if (wv == LROWS - 1) {
@@ -596,7 +644,7 @@ __device__ __forceinline__ void line_body(const Lvl<T>& L, const LineArgs<T>& a,
     }
     exbase = reinterpret_cast<const char*>(a.a + (int64_t)exrow * jstride + excol);
   }
-  constexpr int NBW = 34, NBR = LROWS + 2;  // staged tile: rows x columns
+  constexpr int NBW = TCOLS + 2, NBR = TROWS + 2;  // staged tile: rows x columns
   constexpr int NBSTEP = 2 * NBR * NBW;      // one step, both halves
   auto nbi = [&](int buf, int t, int h, int r, int x) {
     return ((buf * CH + t) * 2 + h) * NBR * NBW + r * NBW + x;
@@ -604,9 +652,13 @@ __device__ __forceinline__ void line_body(const Lvl<T>& L, const LineArgs<T>& a,
   // + 64 slots that the lanes without a halo value write to (no branch)
   __shared__ T s_nb[NBL ? 2 * CH * NBSTEP + 64 : 1];
   // LDS slot of the lane's halo value at step 0 of buffer 0 (or its spare)
-  int exslot = 0;
+  int exslot = 0, ewslot = 0;
   bool exreal = true;
-  if constexpr (NBL) {
+  if constexpr (W2) {
+    exslot = nbi(0, 0, half, rt == 0 ? 0 : NBR - 1, xl + 1);
+    // lanes 2.. write their value to a spare slot
+    ewslot = lane < 2 ? nbi(0, 0, half, rt + 1, lane == 1 ? NBW - 1 : 0) : 2 * CH * NBSTEP + lane;
+  } else if constexpr (NBL) {
     const bool rowhalo = wv == 0 || wv == LROWS - 1;
     exreal = rowhalo || lane < 12;
     const int r = wv == 0 ? 0 : (wv == LROWS - 1 ? NBR - 1 : (lane >> 1));
@@ -625,7 +677,7 @@ __device__ __forceinline__ void line_body(const Lvl<T>& L, const LineArgs<T>& a,
   // Fine indices stay unwrapped (F.nx = 2 C.nx, so periodic images of fine
   // and coarse columns line up with the wrapped coarse loads); behind a wall
   // the coarse neighbour is the parent's mirror image with opposite sign.
-  constexpr int CNW = 18, CNR = 4, CNS = 2 * CNR * CNW;
+  constexpr int CNW = W2 ? 34 : 18, CNR = W2 ? 3 : 4, CNS = 2 * CNR * CNW;
   constexpr int CST = CH + 1;
   __shared__ T s_cs[PRO ? CST * CNS + NTHREADS : 1];
   const char* cbase = nullptr;
@@ -636,13 +688,14 @@ __device__ __forceinline__ void line_body(const Lvl<T>& L, const LineArgs<T>& a,
   // parent, x neighbour, y neighbour, diagonal; each < 72), with the mirror
   // signs of the x and y neighbours in bits 15 and 23
   uint32_t po = 0, pe = 0;  // own column (at the lane's half), halo value (at half exh)
+  uint32_t pw2 = 0;         // W2: the value left or right of the tile (lanes 0, 1)
   if constexpr (PRO) {
     const int q = (int)threadIdx.x;
     creal = q < CNS;
     const int qq = creal ? q : 0;
     chh = qq / (CNR * CNW);
     const int cr = (qq / CNW) % CNR, cx = qq % CNW;
-    const int ib = ti * 16 - 1, jb = tj * (LROWS / 2) - 1;
+    const int ib = ti * (TCOLS / 2) - 1, jb = tj * (TROWS / 2) - 1;
     auto wrapn = [](int v, int n) { v %= n; return v < 0 ? v + n : v; };
     const int I = wrapn(ib + cx, a.C.nx), J = wrapn(jb + cr, a.C.ny);
     cbase = reinterpret_cast<const char*>(a.uc + (int64_t)J * a.C.nz * a.C.ldx + I);
@@ -666,10 +719,13 @@ __device__ __forceinline__ void line_body(const Lvl<T>& L, const LineArgs<T>& a,
       return (uint32_t)(y0 * CNW + x0) | ((uint32_t)(y0 * CNW + x2) << 8) | (mx << 15) |
              ((uint32_t)(y2 * CNW + x0) << 16) | (my << 23) | ((uint32_t)(y2 * CNW + x2) << 24);
     };
-    const int i0 = ti * 32, j0 = tj * LROWS;
+    const int i0 = ti * TCOLS, j0 = tj * TROWS;
     po = slots(i, j);
     int hi = i, hj = j;  // lanes without a halo value: any cell of the tile
-    if (wv == 0) {
+    if (W2) {
+      hj = rt == 0 ? j0 - 1 : j0 + 2;
+      pw2 = lane < 2 ? slots(lane == 1 ? i0 + 64 : i0 - 1, j) : po;
+    } else if (wv == 0) {
       hj = j0 - 1;
     } else if (wv == LROWS - 1) {
       hj = j0 + LROWS;
@@ -722,8 +778,74 @@ __device__ __forceinline__ void line_body(const Lvl<T>& L, const LineArgs<T>& a,
   };
   auto kcl = [&](int k) { return (uint32_t)min(k, nz - 1); };
   auto off = [&](int k, int col) { return (uint32_t)col * ES + kcl(k) * kbytes; };
-  using SI = std::conditional_t<NBL, std::conditional_t<PRO, StepNbP<T>, StepNb<T>>,
-                                StepIn<T, MODE>>;
+  using SI = std::conditional_t<
+      W2, std::conditional_t<PRO, StepNbP2<T>, StepNb2<T>>,
+      std::conditional_t<NBL, std::conditional_t<PRO, StepNbP<T>, StepNb<T>>,
+                                StepIn<T, MODE>>>;
+  // EX: running byte offsets of the next row each stream loads, and their
+  // per-step increments (the halo and coarse values may walk their layers in
+  // the other half's direction)
+  const int32_t dkb = dir * (int32_t)kbytes;
+  const uint32_t xo0 = (uint32_t)ic * ES + (uint32_t)k0 * kbytes;
+  uint32_t xo = xo0, xe = 0, xc = 0, xf = 0, xw = 0;
+  int32_t dex = 0, dcv = 0, dfk = 0;
+  [[maybe_unused]] const int32_t dE = (ie - ic) * (int32_t)ES, dW = (iw - ic) * (int32_t)ES;
+  if constexpr (EX) {
+    if constexpr (NBL) {
+      const bool same = exh == half;
+      xe = (uint32_t)(same ? k0 : NR - 1 - k0) * kbytes;
+      xw = (uint32_t)k0 * kbytes;
+      dex = same ? dkb : -dkb;
+    }
+    if constexpr (PRO) {
+      const bool same = chh == half;
+      xc = (uint32_t)(same ? k0 : NR - 1 - k0) * ckb;
+      dcv = (same ? dir : -dir) * (int32_t)ckb;
+    }
+    if constexpr (MODE == LINE_RESTRICT_SMOOTH) {
+      xf = (uint32_t)(2 * ic) * ES + (uint32_t)k0 * fkbytes;
+      dfk = dir * (int32_t)fkbytes;
+    }
+  }
+  // advance a running offset; opaque to the scheduler, like the row
+  // counters, so that the unrolled sweep keeps one live offset per stream
+  auto adv = [](uint32_t& o, int32_t d) {
+    o += (uint32_t)d;
+    asm volatile("" : "+v"(o));
+  };
+  auto load_step_ex = [&](SI& v) {
+    if constexpr (NBL) {
+      v.un = ldo<T>(rA, xo + (uint32_t)dkb);
+      v.f = ldn<T>(rB, xo);
+      v.ex = ldo<T>(exbase, xe);
+      adv(xe, dex);
+      if constexpr (W2) {
+        v.ew = ldo<T>(ewbase, xw);
+        adv(xw, dkb);
+      }
+      if constexpr (PRO) {
+        v.cv = ldo<T>(cbase, xc);
+        adv(xc, dcv);
+      }
+    } else if constexpr (MODE == LINE_SOLVE) {
+      v.r = ldn<T>(rA, xo);
+    } else if constexpr (kSmooth) {
+      v.un = ldo<T>(rA, xo + (uint32_t)dkb);
+      v.ue = ldo<T>(rA, xo + (uint32_t)dE);
+      v.uw = ldo<T>(rA, xo + (uint32_t)dW);
+      v.unn = ldo<T>(rAn, xo);
+      v.us = ldo<T>(rAs, xo);
+      v.f = ldn<T>(rB, xo);
+    } else if constexpr (MODE == LINE_RESTRICT_SMOOTH) {
+      v.lo = ldn2<V2>(rF0, xf);
+      v.hi = ldn2<V2>(rF1, xf);
+      adv(xf, dfk);
+    } else {
+      v.r = ldn<T>(rW, xo);
+      v.q = ldn<T>(rA, xo);
+    }
+    adv(xo, dkb);
+  };
   auto load_step = [&](int k, SI& v) {
     const uint32_t o = off(k, ic);
     if constexpr (NBL) {
@@ -755,16 +877,28 @@ __device__ __forceinline__ void line_body(const Lvl<T>& L, const LineArgs<T>& a,
   T ckpt[NG];
   T cprev = T(0), dprev = T(0);
   T uprv = T(0), ucur = T(0);
-  if constexpr (kSmooth) ucur = ldo<T>(rA, off(k0, ic));
+  if constexpr (kSmooth) ucur = ldo<T>(rA, EX ? xo0 : off(k0, ic));
 
   SI buf[2][CH];
+  int pfo = 0;                // offset of the next step's profiles in the half's table
   T cnext[2] = {T(0), T(0)};  // PRO: coarse value of the next chunk's first step
   int kl = k0, kf = k0;  // next row to load, next row to eliminate
   auto load_cnext = [&](T& cv) {
-    if constexpr (PRO) cv = ldo<T>(cbase, kcl(chh == half ? kl : NR - 1 - kl) * ckb);
+    if constexpr (PRO) {
+      if constexpr (EX)
+        cv = ldo<T>(cbase, xc);
+      else
+        cv = ldo<T>(cbase, kcl(chh == half ? kl : NR - 1 - kl) * ckb);
+    }
+  };
+  auto load_next = [&](SI& v) {
+    if constexpr (EX)
+      load_step_ex(v);
+    else
+      load_step(next_row(kl), v);
   };
 #pragma unroll
-  for (int t = 0; t < CH; ++t) load_step(next_row(kl), buf[0][t]);
+  for (int t = 0; t < CH; ++t) load_next(buf[0][t]);
   load_cnext(cnext[0]);
 #pragma unroll
   for (int ch = 0; ch < NCH; ++ch) {
@@ -781,6 +915,7 @@ __device__ __forceinline__ void line_body(const Lvl<T>& L, const LineArgs<T>& a,
       for (int t = 0; t < CH; ++t) {
         buf[ch & 1][t].un = corr(po, t + 1, half, buf[ch & 1][t].un);
         buf[ch & 1][t].ex = corr(pe, t, exh, buf[ch & 1][t].ex);
+        if constexpr (W2) buf[ch & 1][t].ew = corr(pw2, t, half, buf[ch & 1][t].ew);
       }
     }
     if constexpr (NBL) {
@@ -789,27 +924,34 @@ __device__ __forceinline__ void line_body(const Lvl<T>& L, const LineArgs<T>& a,
 #pragma unroll
       for (int t = 0; t < CH; ++t) {
         const T ctr = t == 0 ? ucur : buf[ch & 1][t - 1].un;
-        s_nb[nbi(ch & 1, t, half, wv + 1, xl + 1)] = ctr;
+        s_nb[nbi(ch & 1, t, half, rt + 1, xl + 1)] = ctr;
         const int step_off = ((ch & 1) * CH + t) * NBSTEP;
         s_nb[exreal ? exslot + step_off : exslot] = buf[ch & 1][t].ex;
+        if constexpr (W2) s_nb[lane < 2 ? ewslot + step_off : ewslot] = buf[ch & 1][t].ew;
       }
       __syncthreads();
     }
     if (ch + 1 < NCH) {
 #pragma unroll
-      for (int t = 0; t < CH; ++t) load_step(next_row(kl), buf[(ch + 1) & 1][t]);
+      for (int t = 0; t < CH; ++t) load_next(buf[(ch + 1) & 1][t]);
       load_cnext(cnext[(ch + 1) & 1]);
     }
 #pragma unroll
     for (int t = 0; t < CH; ++t) {
       const int s = ch * CH + t;
       const SI& v = buf[ch & 1][t];
-      const int k = next_row(kf);
-      const bool real = k < nz;
-      const T sub = s_sub[k], sup = s_sup[k], dzk = s_dz[k];
-      const T cpv = half ? sup : sub;  // coupling to the previously eliminated row
-      const T cnx = half ? sub : sup;  // coupling to the next row in this lane's order
-      const T diag = s_dg[k] + dzk * c.S;
+      bool real = true;
+      if constexpr (!EX) real = next_row(kf) < nz;
+      // the step's profiles through an offset that the scheduler cannot see
+      // ahead of the step (otherwise it hoists the reads of the whole
+      // unrolled sweep and runs out of registers)
+      const T* ps = s_ps + half * PSH + pfo;
+      pfo += 4;
+      asm volatile("" : "+v"(pfo));
+      const T cpv = ps[0];  // coupling to the previously eliminated row
+      const T cnx = ps[1];  // coupling to the next row in this lane's order
+      const T dzk = ps[3];
+      const T diag = fma(dzk, c.S, ps[2]);
       T rhs;
       if constexpr (MODE == LINE_SOLVE) {
         rhs = real ? v.r : T(0);
@@ -820,22 +962,23 @@ __device__ __forceinline__ void line_body(const Lvl<T>& L, const LineArgs<T>& a,
         // the elimination directly and u is not read again.
         T ue, uw, unn, us;
         if constexpr (NBL) {
-          ue = s_nb[nbi(ch & 1, t, half, wv + 1, xl + 2)];
-          uw = s_nb[nbi(ch & 1, t, half, wv + 1, xl)];
-          unn = s_nb[nbi(ch & 1, t, half, wv + 2, xl + 1)];
-          us = s_nb[nbi(ch & 1, t, half, wv, xl + 1)];
+          ue = s_nb[nbi(ch & 1, t, half, rt + 1, xl + 2)];
+          uw = s_nb[nbi(ch & 1, t, half, rt + 1, xl)];
+          unn = s_nb[nbi(ch & 1, t, half, rt + 2, xl + 1)];
+          us = s_nb[nbi(ch & 1, t, half, rt, xl + 1)];
         } else {
           ue = v.ue;
           uw = v.uw;
           unn = v.unn;
           us = v.us;
         }
-        const T h = c.ce * ue + c.cw * uw + c.cn * unn + c.cs * us;
-        const T mu = diag * ucur + cpv * uprv + cnx * v.un;
-        const T g = v.f + dzk * h;
-        rhs = real ? g + wmu * mu : T(0);
+        const T h = fma(c.cs, us, fma(c.cn, unn, fma(c.cw, uw, c.ce * ue)));
+        const T mu = fma(cnx, v.un, fma(cpv, uprv, diag * ucur));
+        const T g = fma(dzk, h, v.f);
+        rhs = real ? fma(wmu, mu, g) : T(0);
         if constexpr (MODE == LINE_SMOOTH_NORM) {
-          const double r = (active && real) ? (double)(g - mu) : 0.0;
+          // EX: every row is real; an inactive lane's sum is dropped at the end
+          const double r = (EX || (active && real)) ? (double)(g - mu) : 0.0;
           // pin the running sum to a register at each step: otherwise the
           // scheduler stretches the sum's dependence chain across the sweep
           // and the kernel needs twice the registers (one wave per SIMD)
@@ -848,11 +991,11 @@ __device__ __forceinline__ void line_body(const Lvl<T>& L, const LineArgs<T>& a,
       } else if constexpr (MODE == LINE_RESTRICT_SMOOTH) {
         rhs = real ? v.lo.x + v.lo.y + v.hi.x + v.hi.y : T(0);
       } else {  // LINE_CG
-        rhs = real ? v.r - alpha * v.q : T(0);
+        rhs = real ? fma(-alpha, v.q, v.r) : T(0);
       }
       T piv, inv, cn;
       elim_step(diag, cpv, cnx, cprev, piv, inv, cn);
-      dprev = (rhs - cpv * dprev) * inv;
+      dprev = fma(-cpv, dprev, rhs) * inv;
       cprev = cn;
       dp[s] = dprev;
       if (s % G == G - 1) ckpt[s / G] = cprev;
@@ -864,10 +1007,24 @@ __device__ __forceinline__ void line_body(const Lvl<T>& L, const LineArgs<T>& a,
 
   // interface between the two halves: lane's last row x_a = d_a - c_a x_b,
   // partner's last row x_b = d_b - c_b x_a
-  const T cq = __shfl_xor(cprev, 32);
-  const T dq = __shfl_xor(dprev, 32);
-  T x = (dprev - cprev * dq) / (T(1) - cprev * cq);
+  T cq, dq;
+  if constexpr (W2) {
+    // the partner half is the other wavefront of the tile row
+    __shared__ T s_if[W2 ? 2 : 1][2][64][2];
+    s_if[rt][half][xl][0] = cprev;
+    s_if[rt][half][xl][1] = dprev;
+    __syncthreads();
+    cq = s_if[rt][half ^ 1][xl][0];
+    dq = s_if[rt][half ^ 1][xl][1];
+  } else {
+    cq = __shfl_xor(cprev, 32);
+    dq = __shfl_xor(dprev, 32);
+  }
+  T x = fma(-cprev, dq, dprev) / fma(-cprev, cq, T(1));
 
+  // EX: byte offset of the row the back sweep stores next (it walks the
+  // lane's rows from the last one back to k0)
+  uint32_t bo = xo0 + (uint32_t)((HALF - 1) * dkb);
 #pragma unroll
   for (int g = NG - 1; g >= 0; --g) {
     // rows of this segment: k_t = kseg + dir t
@@ -876,40 +1033,42 @@ __device__ __forceinline__ void line_body(const Lvl<T>& L, const LineArgs<T>& a,
     // recompute c' (and the pivots) of the segment from its checkpoint
     T cseg[G], pseg[G];
     T cc = g == 0 ? T(0) : ckpt[g - 1];
+    int pbo = g * G * 4;  // the segment's profiles (opaque, as in the forward sweep)
+    asm volatile("" : "+v"(pbo));
+    const T* pseg_p = s_ps + half * PSH + pbo;
 #pragma unroll
     for (int t = 0; t < G; ++t) {
-      const int k = kseg + dir * t;
-      const T sub = s_sub[k], sup = s_sup[k];
-      const T cpv = half ? sup : sub, cnx = half ? sub : sup;
-      const T diag = s_dg[k] + s_dz[k] * c.S;
+      const T* ps = pseg_p + 4 * t;
+      const T diag = fma(ps[3], c.S, ps[2]);
       T inv;
-      elim_step(diag, cpv, cnx, cc, pseg[t], inv, cseg[t]);
+      elim_step(diag, ps[0], ps[1], cc, pseg[t], inv, cseg[t]);
       cc = cseg[t];
     }
 #pragma unroll
     for (int t = G - 1; t >= 0; --t) {
       const int s = g * G + t;
-      if (s < HALF - 1) x = dp[s] - cseg[t] * x;
+      if (s < HALF - 1) x = fma(-cseg[t], x, dp[s]);
       const int k = kseg + dir * t;
-      const bool st = active && k < nz;
+      const bool st = active && (EX || k < nz);
       // modes that need the right-hand side again rebuild it from the
       // elimination: rhs_k = d'_k piv_k + (coupling to the previous row) d'_{k-1}
       // (accurate to a few units of roundoff of the column's largest entry)
       T rk = T(0);
       if constexpr (MODE == LINE_CG || MODE == LINE_RESTRICT_SMOOTH) {
-        const T cpv = half ? s_sup[k] : s_sub[k];
-        rk = dp[s] * pseg[t] + (s > 0 ? cpv * dp[s > 0 ? s - 1 : 0] : T(0));
+        const T cpv = pseg_p[4 * t];
+        rk = s > 0 ? fma(cpv, dp[s > 0 ? s - 1 : 0], dp[s] * pseg[t]) : dp[s] * pseg[t];
       }
       if constexpr (MODE == LINE_CG) {
         // pin both running sums to registers at each step (as in the
-        // norm-computing smoother's forward sweep)
+        // norm-computing smoother's forward sweep); EX: every row is real,
+        // and an inactive lane's sums are dropped at the end
         asm volatile("" : "+v"(acc_rr), "+v"(acc_rz));
-        acc_rr += st ? (double)rk * (double)rk : 0.0;
-        acc_rz += st ? (double)rk * (double)x : 0.0;
+        acc_rr += (EX || st) ? (double)rk * (double)rk : 0.0;
+        acc_rz += (EX || st) ? (double)rk * (double)x : 0.0;
         asm volatile("" : "+v"(acc_rr), "+v"(acc_rz));
       }
       if (st) {
-        const uint32_t o = off(k, ic);
+        const uint32_t o = EX ? bo : off(k, ic);
         if constexpr (MODE == LINE_SOLVE) {
           sto<T>(rO0, o, a.rho * x);
         } else if constexpr (MODE == LINE_RESTRICT_SMOOTH) {
@@ -922,8 +1081,12 @@ __device__ __forceinline__ void line_body(const Lvl<T>& L, const LineArgs<T>& a,
           sto<T>(rO0, o, x);
         }
       }
+      if constexpr (EX) adv(bo, -dkb);
     }
     __builtin_amdgcn_sched_barrier(0);
+  }
+  if constexpr (EX) {
+    if (!active) acc_rr = acc_rz = 0.0;
   }
   if constexpr (MODE == LINE_CG) {
     double v[2] = {acc_rr, acc_rz};
@@ -935,14 +1098,21 @@ __device__ __forceinline__ void line_body(const Lvl<T>& L, const LineArgs<T>& a,
   }
 }
 
-template <typename T, int HALF, int MODE, bool NB = false>
-__global__ __launch_bounds__(NTHREADS) void k_line(Lvl<T> L, LineArgs<T> a, int nti, int ntj,
-                                                   int group) {
+// Occupancy floor of the line kernels: three wavefronts per SIMD in FP32 (at
+// most 168 registers), two in FP64 and in the two-wavefront form (at most
+// 256): the register allocator keeps the kernels there, where its own choice
+// would cross the line by a few registers and lose a wavefront.
+template <typename T, int HALF, int MODE, bool NB = false, bool EX = false, bool W2 = false>
+__global__ __launch_bounds__(NTHREADS)
+__attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 && !W2 ? 3 : 2))) void k_line(Lvl<T> L, LineArgs<T> a,
+                                                                         int nti, int ntj,
+                                                                         int group) {
   if (gated(L)) return;
   if constexpr (MODE == LINE_CG) {
     if (a.st->done) return;  // uniform: the solve has already stopped
   }
-  line_body<T, HALF, MODE, NB>(L, a, nti, ntj, group, xcd_remap(blockIdx.x, gridDim.x));
+  line_body<T, HALF, MODE, NB, EX, W2>(L, a, nti, ntj, group,
+                                       xcd_remap(blockIdx.x, gridDim.x));
 }
 
 // ---------------------------------------------------------------------------
@@ -2051,6 +2221,13 @@ inline int grid_stride_blocks(int64_t n) {
   return (int)(b < 8192 ? (b > 0 ? b : 1) : 8192);
 }
 
+// The two-wavefront staged smoother (launch shape rows = 3) needs columns of
+// exactly 32, 64 or 128 layers and whole tiles of 64 columns x 2 rows.
+template <typename T>
+bool line_w2_fits(const Lvl<T>& L) {
+  return L.nx % 64 == 0 && L.ny % 2 == 0 && (L.nz == 32 || L.nz == 64 || L.nz == 128);
+}
+
 template <typename T, int MODE>
 hipError_t line_dispatch(const Lvl<T>& L, const LineArgs<T>& a, hipStream_t s, int group,
                          int rows = 4) {
@@ -2066,9 +2243,36 @@ hipError_t line_dispatch(const Lvl<T>& L, const LineArgs<T>& a, hipStream_t s, i
   const int nti = cdiv(L.nx, 32), ntj = cdiv(L.ny, LROWS);
   const dim3 grid(nti * ntj), block(NTHREADS);
   const int half = (L.nz + 1) / 2;
+  if constexpr (MODE == LINE_SMOOTH || MODE == LINE_SMOOTH_NORM || MODE == LINE_PROLONG_SMOOTH) {
+    // staged smoothers with two wavefronts per column where the level fits
+    if (rows == 3 && line_w2_fits(L)) {
+      const int nti2 = L.nx / 64, ntj2 = L.ny / 2;
+      const dim3 grid2(nti2 * ntj2);
+      if (L.nz == 128)
+        hipLaunchKernelGGL((k_line<T, 64, MODE, true, true, true>), grid2, block, 0, s, L, a,
+                           nti2, ntj2, group);
+      else if (L.nz == 64)
+        hipLaunchKernelGGL((k_line<T, 32, MODE, true, true, true>), grid2, block, 0, s, L, a,
+                           nti2, ntj2, group);
+      else
+        hipLaunchKernelGGL((k_line<T, 16, MODE, true, true, true>), grid2, block, 0, s, L, a,
+                           nti2, ntj2, group);
+      return hipGetLastError();
+    }
+  }
   auto go = [&](auto nb) -> hipError_t {
     constexpr bool NB = decltype(nb)::value;
-    if (half <= 4)
+    // columns of exactly 32, 64 or 128 layers take the exact-height form
+    if (L.nz == 32)
+      hipLaunchKernelGGL((k_line<T, 16, MODE, NB, true>), grid, block, 0, s, L, a, nti, ntj,
+                         group);
+    else if (L.nz == 64)
+      hipLaunchKernelGGL((k_line<T, 32, MODE, NB, true>), grid, block, 0, s, L, a, nti, ntj,
+                         group);
+    else if (L.nz == 128)
+      hipLaunchKernelGGL((k_line<T, 64, MODE, NB, true>), grid, block, 0, s, L, a, nti, ntj,
+                         group);
+    else if (half <= 4)
       hipLaunchKernelGGL((k_line<T, 4, MODE, NB>), grid, block, 0, s, L, a, nti, ntj, group);
     else if (half <= 8)
       hipLaunchKernelGGL((k_line<T, 8, MODE, NB>), grid, block, 0, s, L, a, nti, ntj, group);
@@ -2085,9 +2289,10 @@ hipError_t line_dispatch(const Lvl<T>& L, const LineArgs<T>& a, hipStream_t s, i
   if constexpr (MODE == LINE_PROLONG_SMOOTH) {
     return go(std::true_type{});  // staged form only
   } else {
-    // smoothers: horizontal neighbours staged in LDS when asked for (rows = 2)
+    // smoothers: horizontal neighbours staged in LDS when asked for (rows = 2,
+    // and rows = 3 where the two-wavefront form does not fit the level)
     if constexpr (MODE == LINE_SMOOTH || MODE == LINE_SMOOTH_NORM) {
-      if (rows == 2) return go(std::true_type{});
+      if (rows == 2 || rows == 3) return go(std::true_type{});
     }
     return go(std::false_type{});
   }
@@ -2239,7 +2444,7 @@ hipError_t launch_prolong_smooth(const Lvl<T>& F, const Lvl<T>& C, const T* f, c
   a.rho = rho;
   a.C = C;
   a.uc = uc;
-  return line_dispatch<T, LINE_PROLONG_SMOOTH>(F, a, s, sh.group, 2);
+  return line_dispatch<T, LINE_PROLONG_SMOOTH>(F, a, s, sh.group, sh.rows == 3 ? 3 : 2);
 }
 
 template <typename T>
@@ -2273,7 +2478,8 @@ hipError_t launch_smooth_norm(const Lvl<T>& L, const T* f, const T* uin, T* uout
   a.o0 = uout;
   a.rho = rho;
   a.partials = partials;
-  *nblocks = line_blocks(L.nx, L.ny);
+  *nblocks = (sh.rows == 3 && line_w2_fits(L)) ? (int64_t)(L.nx / 64) * (L.ny / 2)
+                                                : line_blocks(L.nx, L.ny);
   return line_dispatch<T, LINE_SMOOTH_NORM>(L, a, s, sh.group, sh.rows);
 }
 

@@ -22,15 +22,18 @@ def _need_gpu():
 
 
 def _fold(G, ctx, on, group=0):
+    """on: False (two kernels), True or 2 (folded, one wavefront per column),
+    3 (folded, two wavefronts per column where the level fits)."""
+    rows = 4 if not on else (3 if on == 3 else 2)
     for lvl in range(ctx.nlevels):
         for prec in (G.GMG_F64, G.GMG_F32):
-            G.gmg_set_launch(ctx, "prolong_smooth", lvl, prec, 2 if on else 4, group if on else 0)
+            G.gmg_set_launch(ctx, "prolong_smooth", lvl, prec, rows, group if on else 0)
 
 
 # grids: full 32-column tiles, ragged tiles and odd n_z, n_x below one tile,
 # a coarsest level of one column, and the 128-layer columns of the benchmark
 GRIDS = [((64, 64, 64), 3), ((96, 40, 37), 3), ((136, 12, 20), 3), ((8, 8, 9), 3),
-         ((2, 2, 9), 2), ((32, 64, 128), 4)]
+         ((2, 2, 9), 2), ((32, 64, 128), 4), ((256, 12, 128), 3), ((128, 64, 32), 2)]
 
 
 @pytest.mark.parametrize("prec", [0, 1])
@@ -48,7 +51,7 @@ def test_vcycle_folded_equals_separate_and_oracle(grid, bc_h, prec):
         u = u.astype(np.float32).astype(np.float64)
     fd = ctx.to_device(f, dtype=dt)
     outs = []
-    for on, group in ((False, 0), (True, 0), (True, 2)):
+    for on, group in ((False, 0), (True, 0), (True, 2), (3, 0), (3, 4)):
         _fold(G, ctx, on, group)
         ud = ctx.to_device(u, dtype=dt)
         G.gmg_vcycle(ctx, fd, ud)

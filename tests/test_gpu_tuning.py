@@ -63,15 +63,18 @@ def test_kernels_bitwise_identical_across_shapes(grid, prec):
 
 
 @pytest.mark.parametrize("prec", [0, 1])
-@pytest.mark.parametrize("grid", [(40, 6, 37), (64, 64, 64), (34, 10, 128), (2, 2, 9)])
+@pytest.mark.parametrize("grid", [(40, 6, 37), (64, 64, 64), (34, 10, 128), (2, 2, 9),
+                                  (128, 6, 128), (192, 2, 32), (64, 4, 64)])
 def test_staged_smoother_bitwise_equal_to_per_lane_loads(grid, prec):
-    """Staging the neighbours in LDS changes where the values come from, not
-    the arithmetic: the smoother's output is bitwise identical."""
+    """Staging the neighbours in LDS (rows = 2), also with the two halves of a
+    column in two wavefronts (rows = 3: nx a multiple of 64, ny even, 32, 64 or
+    128 layers; elsewhere it runs as rows = 2), changes where the values come
+    from, not the arithmetic: the smoother's output is bitwise identical."""
     import paper_1402_3545_amd as G
     nx, ny, nz = grid
     dt = torch.float64 if prec == 0 else torch.float32
     outs = []
-    for rows in (4, 2):
+    for rows in (4, 2, 3):
         ctx, _, _ = problem(nx, ny, nz, seed=22)
         G.gmg_set_launch(ctx, "smooth", 0, prec, rows, 0)
         n = nx * ny * nz
@@ -80,6 +83,29 @@ def test_staged_smoother_bitwise_equal_to_per_lane_loads(grid, prec):
         G.line_smooth(ctx, 0, f, u, nsweeps=3)
         outs.append(ctx.from_device(u))    # the grid's elements (padding is not part of u)
     assert np.array_equal(outs[0], outs[1])
+    assert np.array_equal(outs[0], outs[2])
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("grid", [(128, 6, 128), (64, 4, 64), (192, 2, 32)])
+def test_two_wavefront_smoother_norm(grid, prec):
+    """The norm-computing smoother of the multigrid solve in the two-wavefront
+    form: the same iterate as the one-wavefront form, and the same
+    ||f - A u||^2 up to the summation order of its workgroup partials."""
+    import paper_1402_3545_amd as G
+    nx, ny, nz = grid
+    ctx, orc, _ = problem(nx, ny, nz, nlevels=1, seed=29)
+    f = W.uniform_pm1(34, 2, nx * ny * nz)
+    fd = ctx.to_device(f)
+    res = []
+    for rows in (2, 3):
+        G.gmg_set_launch(ctx, "smooth", 0, prec, rows, 0)
+        G.gmg_set_graphs(ctx, False)
+        ud = ctx.empty()
+        it, rel, hist, st = G.gmg_solve(ctx, fd, ud, rtol=1e-300, maxit=3, check=False)
+        res.append((ctx.from_device(ud), hist))
+    assert np.array_equal(res[0][0], res[1][0])
+    assert np.allclose(res[0][1], res[1][1], rtol=1e-12, atol=0)
 
 
 @pytest.mark.parametrize("prec_precond", [0, 1])
@@ -96,11 +122,11 @@ def test_autotune_then_solve_matches_oracle(prec_precond):
     table = G.launch_table(ctx)
     assert all(r in (1, 4, 8, 16) and 0 <= g <= 8 for k, (r, g) in table.items()
                if not k.startswith(("smooth/", "prolong_smooth/")))
-    # the folded prolongation is on (2) or off (4)
-    assert all(r in (2, 4) and 0 <= g <= 8 for k, (r, g) in table.items()
+    # the folded prolongation is on (2, 3) or off (4)
+    assert all(r in (2, 3, 4) and 0 <= g <= 8 for k, (r, g) in table.items()
                if k.startswith("prolong_smooth/"))
-    # the smoother may also take the staged-neighbour form (rows = 2)
-    assert all(r in (1, 2, 4) and 0 <= g <= 8 for k, (r, g) in table.items()
+    # the smoother may also take the staged-neighbour forms (rows = 2, 3)
+    assert all(r in (1, 2, 3, 4) and 0 <= g <= 8 for k, (r, g) in table.items()
                if k.startswith("smooth/"))
     ud = ctx.empty()
     it, rel, _, st = G.gmg_solve(ctx, fd, ud, rtol=1e-10, maxit=60)
@@ -126,10 +152,13 @@ def test_launch_shape_validation():
     assert G.gmg_get_launch(ctx, "line_solve", 0, G.GMG_F64) == (1, 0)
     G.gmg_set_launch(ctx, "smooth", 1, G.GMG_F32, 2, 4)         # staged neighbours
     assert G.gmg_get_launch(ctx, "smooth", 1, G.GMG_F32) == (2, 4)
+    G.gmg_set_launch(ctx, "smooth", 0, G.GMG_F64, 3, 0)         # two wavefronts per column
+    G.gmg_set_launch(ctx, "prolong_smooth", 0, G.GMG_F64, 3, 2)
+    assert G.gmg_get_launch(ctx, "prolong_smooth", 0, G.GMG_F64) == (3, 2)
     for bad in [("spmv", 2, 0, 4, 0), ("spmv", 0, 2, 4, 0), ("spmv", 0, 0, 5, 0),
                 ("spmv", 0, 0, 4, -1), ("spmv", 0, 0, 4, 5000), (99, 0, 0, 4, 0),
                 ("spmv", 0, 0, 1, 0), ("cg_tridiag", 0, 0, 1, 0), ("line_solve", 0, 0, 2, 0),
-                ("spmv", 0, 0, 2, 0)]:
+                ("spmv", 0, 0, 2, 0), ("line_solve", 0, 0, 3, 0), ("prolong_smooth", 0, 0, 1, 0)]:
         with pytest.raises(G.GmgError):
             G.gmg_set_launch(ctx, *bad)
     with pytest.raises(G.GmgError):
