@@ -732,7 +732,9 @@ def main():
     # the line, never as value
     host = None
     if "mg_f64" in solves:
-        uh = np.zeros_like(f)
+        # a caller's guess array holds written pages (np.zeros_like would hand
+        # over untouched ones, whose first writes fault inside the copy out)
+        uh = np.full_like(f, 0.0)
         it_h, rel_h, tm_h, st_h = G.gmg_solve_host(ctx64, f, uh, "mg", w.rtol, 100)
         total = sum(tm_h.values())
         host = {"solve": "mg_f64", "iters": it_h, "relres": rel_h, "total_ms": round(total, 3),

@@ -270,12 +270,16 @@ int gmg_transpose_out(gmg_ctx *c, int level, int prec, const void *src_x, void *
  * device, converts their layout, runs gmg_solve (method 0: multigrid, or
  * refinement with FP32 cycles when the context's preconditioner is FP32) or
  * pcg_solve (method 1: line preconditioner, 2: V-cycle preconditioner,
- * flexible CG), converts u back and copies it into u_host.  The context
- * allocates three level-0 FP64 device fields on first use and keeps them
- * until gmg_destroy.  timings_ms (may be NULL) receives 5 values: host to
- * device copies, layout conversion in, solve, layout conversion out, device
- * to host copy.  Synchronises `stream`.  Returns the solve's status
- * (GMG_ENOCONV still copies the last iterate out). */
+ * flexible CG), converts u back and copies it into u_host.  The copies go
+ * through two pinned host buffers of up to 128 MiB, in chunks: host threads
+ * fill (or empty) one buffer while the DMA engine drains (or fills) the other.
+ * On first use the context allocates three level-0 FP64 device fields and
+ * the two pinned buffers, and keeps them until gmg_destroy (GMG_ENOMEM when
+ * either allocation fails).  timings_ms (may be NULL) receives 5 host-clock
+ * values, each step ending in a synchronisation: host to device copies,
+ * layout conversion in, solve, layout conversion out, device to host copy.
+ * Synchronises `stream`; not safe for concurrent calls on one context.
+ * Returns the solve's status (GMG_ENOCONV still copies the last iterate out). */
 int gmg_solve_host(gmg_ctx *c, int method, const double *f_host, double *u_host, double rtol,
                    int maxit, int *iters, double *relres, double *timings_ms, void *stream);
 
@@ -292,12 +296,17 @@ int gmg_solve_host(gmg_ctx *c, int method, const double *f_host, double *u_host,
  *           (n_z <= 128), for levels with too few columns to fill the GPU;
  *           the smoother also takes rows = 2: the twisted elimination with
  *           the horizontal neighbours staged in LDS by the workgroup (each u
- *           value of the tile and its halo read once) instead of read per lane.
+ *           value of the tile and its halo read once) instead of read per lane,
+ *           and rows = 3: the same staging with the two halves of each column
+ *           in two wavefronts (tiles of 64 columns by 2 grid rows), for
+ *           levels with n_z of 32, 64 or 128, n_x a multiple of 64 and n_y
+ *           even; on other levels rows = 3 runs as rows = 2.
  *           GMG_K_PROLONG_SMOOTH of level l (l < nlevels - 1) takes rows = 4
  *           (the default: the V-cycle prolongates from level l+1 and then
- *           post-smooths level l, two kernels) or rows = 2 (one kernel: the
- *           staged smoother adds the prolongated correction to every value
- *           it stages, so u + P u_c is never stored; the same arithmetic).
+ *           post-smooths level l, two kernels) or rows = 2 or 3 (one kernel:
+ *           the staged smoother of that shape adds the prolongated correction
+ *           to every value it stages, so u + P u_c is never stored; the same
+ *           arithmetic).
  *   group - tile columns per dispatch group: tiles are walked group by group
  *           and tile rows follow each other inside a group, so that a tile's
  *           neighbours run close in time and share an XCD's L2; 0 walks the
@@ -306,15 +315,17 @@ int gmg_solve_host(gmg_ctx *c, int method, const double *f_host, double *u_host,
  * the FP64 reductions (norms and dot products).
  * gmg_set_launch / gmg_get_launch: one entry of the context's table;
  * GMG_EINVAL for a bad kernel id, level or precision, rows not in {4, 8, 16}
- * (or 1 for the line solve and smoother, 2 for the smoother; GMG_K_PROLONG_SMOOTH
- * takes 4 or 2 only), group outside [0, 4096], and for batched contexts.
+ * (or 1 for the line solve and smoother, 2 or 3 for the smoother;
+ * GMG_K_PROLONG_SMOOTH takes 4, 2 or 3 only), group outside [0, 4096], and for
+ * batched contexts.
  * gmg_autotune: for every level and for the precisions the context's solvers
- * use, runs each candidate shape (rows 4/8/16, 4/1 or 4/1/2, group 0/1/2/4/8) of each kernel
- * kind `reps` times on the context's own work buffers (their contents are
+ * use, runs each candidate shape (rows 4/8/16, 4/1 or 4/1/2/3, group 0/1/2/4/8) of
+ * each kernel kind `reps` times on the context's own work buffers (their contents are
  * overwritten; caller memory is not touched), times it with HIP events on
- * `stream` and keeps the fastest; the folded prolongation (rows = 2 of
+ * `stream` and keeps the fastest; the folded prolongation (rows = 2 or 3 of
  * GMG_K_PROLONG_SMOOTH, groups 0/1/2/4/8) is kept for a level where it beats
- * the best prolongation plus the best smoother.  Synchronises `stream`.  reps in [1, 1000]. */
+ * the best prolongation plus the best smoother.  Synchronises `stream`.
+ * reps in [1, 1000]. */
 int gmg_set_launch(gmg_ctx *c, int kernel, int level, int prec, int rows, int group);
 int gmg_get_launch(const gmg_ctx *c, int kernel, int level, int prec, int *rows, int *group);
 int gmg_autotune(gmg_ctx *c, int reps, void *stream);

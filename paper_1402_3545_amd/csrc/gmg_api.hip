@@ -9,7 +9,10 @@
 #include <string.h>
 
 #include <algorithm>
+#include <chrono>
 #include <new>
+#include <thread>
+#include <vector>
 
 #include <type_traits>
 
@@ -157,6 +160,10 @@ int gmg_destroy(gmg_ctx* c) {
   dfree(c->vr); dfree(c->vz); dfree(c->vp); dfree(c->vq); dfree(c->vt);
   dfree(c->er32); dfree(c->eu32);
   dfree(c->hz); dfree(c->hf); dfree(c->hu);
+  for (int b = 0; b < 2; ++b) {
+    if (c->stage[b]) (void)hipHostFree(c->stage[b]);
+    if (c->stage_ev[b]) (void)hipEventDestroy(c->stage_ev[b]);
+  }
   dfree(c->partials);
   dfree(c->state);
   dfree(c->dhist);
@@ -1084,6 +1091,102 @@ int gmg_transpose_out(gmg_ctx* c, int level, int prec, const void* src_x, void* 
   return GMG_OK;
 }
 
+}  // extern "C"
+
+namespace {
+
+// Host-side copy of one staged chunk, split over a few threads: a single
+// thread's memcpy from pageable memory runs well below the link's rate.
+void par_memcpy(void* dst, const void* src, size_t n) {
+  const unsigned hw = std::thread::hardware_concurrency();
+  const size_t nt = std::max<size_t>(1, std::min<size_t>(8, hw ? hw / 2 : 1));
+  const size_t per = (n / nt + 4095) / 4096 * 4096;
+  if (nt == 1 || n < (4u << 20)) {
+    memcpy(dst, src, n);
+    return;
+  }
+  std::vector<std::thread> th;
+  for (size_t t = 0; t < nt; ++t) {
+    const size_t a = t * per;
+    if (a >= n) break;
+    const size_t len = std::min(per, n - a);
+    th.emplace_back([=] { memcpy(static_cast<char*>(dst) + a, static_cast<const char*>(src) + a, len); });
+  }
+  for (std::thread& t : th) t.join();
+}
+
+// Pinned staging for the host transfers of gmg_solve_host: two buffers of up
+// to kStageBytes, allocated at first use.
+constexpr size_t kStageBytes = size_t(128) << 20;
+
+int ensure_stage(gmg_ctx* c, size_t bytes) {
+  if (c->stage_bytes) return GMG_OK;
+  const size_t sz = std::min(kStageBytes, std::max<size_t>(bytes, 1));
+  hipError_t e = hipSuccess;
+  for (int b = 0; b < 2 && e == hipSuccess; ++b) {
+    e = hipHostMalloc(&c->stage[b], sz, hipHostMallocDefault);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&c->stage_ev[b], hipEventDisableTiming);
+  }
+  if (e != hipSuccess) {
+    for (int b = 0; b < 2; ++b) {
+      if (c->stage[b]) (void)hipHostFree(c->stage[b]);
+      if (c->stage_ev[b]) (void)hipEventDestroy(c->stage_ev[b]);
+      c->stage[b] = nullptr;
+      c->stage_ev[b] = nullptr;
+    }
+    return fail(GMG_ENOMEM, "pinned staging: %s", hipGetErrorString(e));
+  }
+  c->stage_bytes = sz;
+  return GMG_OK;
+}
+
+// host (pageable) -> device through the two pinned buffers: the host fills
+// one while the DMA engine drains the other
+int upload(gmg_ctx* c, const void* src, void* dst, size_t bytes, hipStream_t s) {
+  const size_t ch = c->stage_bytes;
+  for (size_t q = 0, off = 0; off < bytes; ++q, off += ch) {
+    const int b = (int)(q & 1);
+    const size_t len = std::min(ch, bytes - off);
+    if (q >= 2) HIP_TRY(hipEventSynchronize(c->stage_ev[b]));  // its last DMA has read it
+    par_memcpy(c->stage[b], static_cast<const char*>(src) + off, len);
+    HIP_TRY(hipMemcpyAsync(static_cast<char*>(dst) + off, c->stage[b], len,
+                           hipMemcpyHostToDevice, s));
+    HIP_TRY(hipEventRecord(c->stage_ev[b], s));
+  }
+  return GMG_OK;
+}
+
+// device -> host (pageable): the DMA fills one buffer while the host empties
+// the other
+int download(gmg_ctx* c, const void* src, void* dst, size_t bytes, hipStream_t s) {
+  const size_t ch = c->stage_bytes;
+  size_t prev_off = 0, prev_len = 0;
+  int prev_b = -1;
+  for (size_t q = 0, off = 0; off < bytes; ++q, off += ch) {
+    const int b = (int)(q & 1);
+    const size_t len = std::min(ch, bytes - off);
+    HIP_TRY(hipMemcpyAsync(c->stage[b], static_cast<const char*>(src) + off, len,
+                           hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipEventRecord(c->stage_ev[b], s));
+    if (prev_b >= 0) {
+      HIP_TRY(hipEventSynchronize(c->stage_ev[prev_b]));
+      par_memcpy(static_cast<char*>(dst) + prev_off, c->stage[prev_b], prev_len);
+    }
+    prev_b = b;
+    prev_off = off;
+    prev_len = len;
+  }
+  if (prev_b >= 0) {
+    HIP_TRY(hipEventSynchronize(c->stage_ev[prev_b]));
+    par_memcpy(static_cast<char*>(dst) + prev_off, c->stage[prev_b], prev_len);
+  }
+  return GMG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
 int gmg_solve_host(gmg_ctx* c, int method, const double* f_host, double* u_host, double rtol,
                    int maxit, int* iters, double* relres, double* timings_ms, void* stream) {
   if (!c || c->batch) return fail(GMG_EINVAL, "context is NULL or batched");
@@ -1101,55 +1204,52 @@ int gmg_solve_host(gmg_ctx* c, int method, const double* f_host, double* u_host,
       return fail(GMG_ENOMEM, "host-solve buffers: %s", hipGetErrorString(e));
     }
   }
-  hipStream_t s = as_stream(stream);
-  // events between the steps: copy f in | layout f | copy u in | layout u |
-  // solve | layout u out | copy u out
-  hipEvent_t ev[8] = {};
-  for (hipEvent_t& e : ev) HIP_TRY(hipEventCreate(&e));
-  auto done = [&](int code) {
-    for (hipEvent_t e : ev) (void)hipEventDestroy(e);
-    return code;
-  };
-  auto step = [&](hipError_t e, const char* what) {
-    return e == hipSuccess ? GMG_OK : hip_fail(e, what);
-  };
   int st;
-  if ((st = step(hipEventRecord(ev[0], s), "event")) ||
-      (st = step(hipMemcpyAsync(c->hz, f_host, bytes, hipMemcpyHostToDevice, s), "copy f in")) ||
-      (st = step(hipEventRecord(ev[1], s), "event")) ||
-      (st = step(gmg::launch_transpose<double>(c->hz, c->hf, B.nx, B.ny, B.nz, B.ldx, true, s),
-                 "layout f in")) ||
-      (st = step(hipEventRecord(ev[2], s), "event")) ||
-      (st = step(hipMemcpyAsync(c->hz, u_host, bytes, hipMemcpyHostToDevice, s), "copy u in")) ||
-      (st = step(hipEventRecord(ev[3], s), "event")) ||
-      (st = step(gmg::launch_transpose<double>(c->hz, c->hu, B.nx, B.ny, B.nz, B.ldx, true, s),
-                 "layout u in")) ||
-      (st = step(hipEventRecord(ev[4], s), "event")))
-    return done(st);
+  if ((st = ensure_stage(c, bytes))) return st;
+  hipStream_t s = as_stream(stream);
+  using clock = std::chrono::steady_clock;
+  auto ms_since = [](clock::time_point t0) {
+    return std::chrono::duration<double, std::milli>(clock::now() - t0).count();
+  };
+  auto sync = [&]() -> int { HIP_TRY(hipStreamSynchronize(s)); return GMG_OK; };
+  // copies in: f, then the initial guess u, each converted to the solver's
+  // layout once it is on the device (each step timed on the host clock)
+  HIP_TRY(hipStreamSynchronize(s));
+  double t_copy_in = 0.0, t_layout_in = 0.0;
+  for (int fld = 0; fld < 2; ++fld) {
+    const void* src = fld == 0 ? (const void*)f_host : (const void*)u_host;
+    double* dst = fld == 0 ? c->hf : c->hu;
+    auto tc = clock::now();
+    if ((st = upload(c, src, c->hz, bytes, s)) || (st = sync())) return st;
+    t_copy_in += ms_since(tc);
+    auto tl = clock::now();
+    HIP_TRY(gmg::launch_transpose<double>(c->hz, dst, B.nx, B.ny, B.nz, B.ldx, true, s));
+    if ((st = sync())) return st;
+    t_layout_in += ms_since(tl);
+  }
+  auto ts = clock::now();
   const int solve_st =
       method == 0 ? gmg_solve(c, c->hf, c->hu, rtol, maxit, iters, relres, nullptr, stream)
                   : pcg_solve(c, c->hf, c->hu, rtol, maxit, method == 2 ? 1 : 0, iters, relres,
                               nullptr, stream);
-  if (solve_st != GMG_OK && solve_st != GMG_ENOCONV) return done(solve_st);
-  if ((st = step(hipEventRecord(ev[5], s), "event")) ||
-      (st = step(gmg::launch_transpose<double>(c->hu, c->hz, B.nx, B.ny, B.nz, B.ldx, false, s),
-                 "layout u out")) ||
-      (st = step(hipEventRecord(ev[6], s), "event")) ||
-      (st = step(hipMemcpyAsync(u_host, c->hz, bytes, hipMemcpyDeviceToHost, s), "copy u out")) ||
-      (st = step(hipEventRecord(ev[7], s), "event")) ||
-      (st = step(hipStreamSynchronize(s), "sync")))
-    return done(st);
+  if (solve_st != GMG_OK && solve_st != GMG_ENOCONV) return solve_st;
+  if ((st = sync())) return st;
+  const double t_solve = ms_since(ts);
+  auto tl = clock::now();
+  HIP_TRY(gmg::launch_transpose<double>(c->hu, c->hz, B.nx, B.ny, B.nz, B.ldx, false, s));
+  if ((st = sync())) return st;
+  const double t_layout_out = ms_since(tl);
+  auto tc = clock::now();
+  if ((st = download(c, c->hz, u_host, bytes, s))) return st;
+  const double t_copy_out = ms_since(tc);
   if (timings_ms) {
-    float ms[7] = {};
-    for (int q = 0; q < 7; ++q)
-      if ((st = step(hipEventElapsedTime(&ms[q], ev[q], ev[q + 1]), "elapsed"))) return done(st);
-    timings_ms[0] = (double)ms[0] + ms[2];  // host -> device copies
-    timings_ms[1] = (double)ms[1] + ms[3];  // layout conversions in
-    timings_ms[2] = ms[4];                  // solve
-    timings_ms[3] = ms[5];                  // layout conversion out
-    timings_ms[4] = ms[6];                  // device -> host copy
+    timings_ms[0] = t_copy_in;     // host -> device copies (host staging included)
+    timings_ms[1] = t_layout_in;   // layout conversions in
+    timings_ms[2] = t_solve;       // solve
+    timings_ms[3] = t_layout_out;  // layout conversion out
+    timings_ms[4] = t_copy_out;    // device -> host copy (host staging included)
   }
-  return done(solve_st);
+  return solve_st;  // GMG_ENOCONV keeps the solve's message
 }
 
 int gmg_set_launch(gmg_ctx* c, int kernel, int level, int prec, int rows, int group) {

@@ -180,6 +180,11 @@ struct gmg_ctx {
   // gmg_solve_host: z-contiguous staging and x-contiguous f, u (FP64, level
   // 0), allocated on first use
   double *hz = nullptr, *hf = nullptr, *hu = nullptr;
+  // gmg_solve_host: two pinned host staging buffers of stage_bytes each and
+  // the events of their last copies, allocated on first use
+  void* stage[2] = {};
+  hipEvent_t stage_ev[2] = {};
+  size_t stage_bytes = 0;
 };
 
 namespace gmg {

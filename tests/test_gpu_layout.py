@@ -80,6 +80,27 @@ def test_host_solve_equals_device_solve(method, prec_precond):
     assert st3 == 0 and it3 == it and np.array_equal(u2, u)
 
 
+def test_host_solve_in_several_staging_chunks():
+    """388 MiB per field: three full 128 MiB staging chunks and a ragged
+    tail, with both pinned buffers reused, for the right-hand side, the
+    initial guess and the solution; the iterate after two V-cycles must be
+    bitwise that of the device-resident solve from the same guess."""
+    import paper_1402_3545_amd as G
+    nx, ny, nz = 512, 776, 128
+    kh = W.kh_uniform(29, nx, ny)
+    ctx = G.GmgContext(nx, ny, nz, 3, kv=1e3, sigma=1.0, zfaces=W.quadratic_faces(nz), kh=kh)
+    f = W.rhs(29, 0, nx, ny, nz)
+    u0 = W.rhs(29, 1, nx, ny, nz)
+    u = u0.copy()
+    it, rel, tm, st = G.gmg_solve_host(ctx, f, u, method="mg", rtol=1e-14, maxit=2)
+    assert st == G.GMG_ENOCONV and it == 2
+    assert all(np.isfinite(v) and v >= 0.0 for v in tm.values())
+    fd, ud = ctx.to_device(f), ctx.to_device(u0)
+    it2, rel2, _, st2 = G.gmg_solve(ctx, fd, ud, rtol=1e-14, maxit=2, check=False)
+    assert st2 == st and it2 == it and rel2 == rel
+    assert np.array_equal(u, ctx.from_device(ud))
+
+
 def test_host_solve_validation():
     import paper_1402_3545_amd as G
     ctx, _, _ = problem(16, 16, 8, nlevels=2)
