@@ -9,7 +9,9 @@
 // Two kernel shapes:
 //  * stencil kernels (SpMV, Residual, the CG SpMV step, Prolongate): one thread
 //    per column segment of KSEG layers, vertical neighbours rolled through
-//    registers, horizontal neighbours loaded directly (they hit L1/L2).
+//    registers; east/west neighbours passed between the lanes of a wavefront
+//    (DPP wave shifts, only the two edge lanes load theirs), north/south
+//    neighbours loaded directly (they hit L1/L2).
 //  * line kernels (Tridiag, Smooth, ResSmooth): the tridiagonal system of each
 //    column is solved by two lanes of one wavefront.  Lane l < 32 eliminates
 //    upwards from the bottom layer, lane l + 32 downwards from the top layer;
@@ -119,6 +121,7 @@ struct Geo {
   int j, jn, js;   // the wavefront's grid row and its periodic neighbours
   int ic, ie, iw;  // the lane's column (clamped into the grid) and its neighbours
   bool row, act;   // the row exists (wave-uniform); the lane's column exists
+  bool ft;         // all 64 columns of the tile exist (wave-uniform)
   int k0, n;       // first layer and number of layers of the segment (uniform)
 };
 
@@ -160,6 +163,7 @@ __device__ __forceinline__ Geo stencil_geo(int nx, int ny, int nz, int nti, int 
   g.jn = (g.j + 1 == ny) ? 0 : g.j + 1;
   g.js = (g.j == 0) ? ny - 1 : g.j - 1;
   g.act = i < nx;
+  g.ft = ti * 64 + 64 <= nx;
   g.ic = min(i, nx - 1);
   g.ie = (g.ic + 1 == nx) ? 0 : g.ic + 1;
   g.iw = (g.ic == 0) ? nx - 1 : g.ic - 1;
@@ -267,16 +271,43 @@ __device__ __forceinline__ void walk(P& pol, int n) {
   }
 }
 
+// A value from another lane of the wavefront by a DPP wave shift: CTRL
+// kWaveShl1 gives lane l the value of lane l+1, kWaveShr1 that of lane l-1
+// (the lane at the end receives 0).  Every lane of the wavefront must be
+// active.
+constexpr int kWaveShl1 = 0x130;
+constexpr int kWaveShr1 = 0x138;
+template <int CTRL, typename T>
+__device__ __forceinline__ T wave_shift(T v) {
+  if constexpr (sizeof(T) == 8) {
+    const uint64_t b = __builtin_bit_cast(uint64_t, v);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)b, CTRL, 0xf,
+                                                              0xf, false);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(b >> 32), CTRL,
+                                                              0xf, 0xf, false);
+    return __builtin_bit_cast(T, ((uint64_t)hi << 32) | lo);
+  } else {
+    return __builtin_bit_cast(
+        T, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, 0xf, 0xf, false));
+  }
+}
+
 // The 7-point operator on one lane's column, rolled through registers:
 // (A x)_k = (dg_k + dz_k S) x_k - dz_k (Kh-weighted sum of the four horizontal
 // neighbours) + sub_k x_{k-1} + sup_k x_{k+1}, x_{-1} = x_{nz} = 0.
 // x is stored as TS (FP32 for the mixed-precision flexible CG), the
 // arithmetic is in T.  Byte offsets oc/oe/ow and kb refer to TS elements.
-template <typename T, typename TS = T>
+// X (tiles whose 64 columns all exist): the east and west values of layer k
+// are the neighbouring lanes' own x_k, passed by wave shifts; one load per
+// layer brings lane 0 its west and lane 63 its east value (the tile's halo)
+// in the xe slot, and the other lanes their own x_k again (an L1 hit; no
+// branch, so the loads of a chunk stay one straight-line batch).
+template <typename T, typename TS = T, bool X = false>
 struct ColumnOp {
   const char *rx, *rxn, *rxs;
-  uint32_t oc, oe, ow, kb;
+  uint32_t oc, oe, ow, kb, oh;
   int nz, k0;
+  bool ew, ee;  // X: the lane is the tile's west / east edge
   Cf<T> c;
   const Prof<T>* sp;
   T xm, xc;
@@ -295,22 +326,39 @@ struct ColumnOp {
     k0 = g.k0;
     c = cf;
     sp = prof;
+    if constexpr (X) {
+      const int lane = (int)(threadIdx.x & 63);
+      ew = lane == 0;
+      ee = lane == 63;
+      oh = ew ? ow : ee ? oe : oc;
+    }
     xm = k0 > 0 ? (T)ldo<TS>(rx, oc + (uint32_t)(k0 - 1) * kb) : T(0);
     xc = (T)ldo<TS>(rx, oc + (uint32_t)k0 * kb);
   }
-  // x at k+1 (clamped address), and the four horizontal neighbours at k
+  // x at k+1 (clamped address), and the horizontal neighbours at k (X: the
+  // edge lanes' halo value in xe, xw unused)
   __device__ __forceinline__ void load(uint32_t ok, uint32_t okp, T& xp, T& xe, T& xw, T& xn,
                                        T& xs) const {
     xp = (T)ldo<TS>(rx, oc + okp);
-    xe = (T)ldo<TS>(rx, oe + ok);
-    xw = (T)ldo<TS>(rx, ow + ok);
+    if constexpr (X) {
+      xe = (T)ldo<TS>(rx, oh + ok);
+    } else {
+      xe = (T)ldo<TS>(rx, oe + ok);
+      xw = (T)ldo<TS>(rx, ow + ok);
+    }
     xn = (T)ldo<TS>(rxn, oc + ok);
     xs = (T)ldo<TS>(rxs, oc + ok);
   }
   // (A x) at layer k0+s; advances the rolled column
-  __device__ __forceinline__ T apply(int s, T xp_raw, T xe, T xw, T xn, T xs) {
+  __device__ __forceinline__ T apply(int s, T xp_raw, T xe_in, T xw_in, T xn, T xs) {
     const Prof<T> pr = sp[s];
     const T xp = (k0 + s + 1 < nz) ? xp_raw : T(0);
+    T xe = xe_in, xw = xw_in;
+    if constexpr (X) {
+      const T de = wave_shift<kWaveShl1>(xc), dw = wave_shift<kWaveShr1>(xc);
+      xe = ee ? xe_in : de;
+      xw = ew ? xe_in : dw;
+    }
     const T h = c.ce * xe + c.cw * xw + c.cn * xn + c.cs * xs;
     const T ax = (pr.dg + pr.dz * c.S) * xc - pr.dz * h + pr.sub * xm + pr.sup * xp;
     xm = xc;
@@ -327,12 +375,12 @@ __device__ __forceinline__ uint32_t layer_off(int k, int nz, uint32_t kb) {
 
 // SpMV (y = Ax) and Residual (r = f - Ax, optional ||r||^2 partials and an
 // FP32 copy of r for the mixed-precision refinement).
-template <typename T, int MODE, bool FULL>
+template <typename T, int MODE, bool FULL, bool X>
 struct StencilPol {
   struct In {
     T xp, xe, xw, xn, xs, f;
   };
-  ColumnOp<T> op;
+  ColumnOp<T, T, X> op;
   const char* rf;
   char *ry, *rd;
   double nrm;
@@ -376,24 +424,27 @@ __global__ __launch_bounds__(64 * SR) void k_stencil(Lvl<T> L, const T* __restri
     const int64_t jstride = (int64_t)L.nz * L.ldx;
     const uint32_t kb = (uint32_t)(L.ldx * sizeof(T));
     const Cf<T> cf = col_coef(L, g);
-    if (g.n == KSEG) {
-      StencilPol<T, MODE, true> pol;
+    auto run = [&](auto full, auto xch) {
+      constexpr bool F = decltype(full)::value, XC = decltype(xch)::value;
+      StencilPol<T, MODE, F, XC> pol;
       pol.op.init(x, g, jstride, kb, cf, sp, L.nz);
       pol.rf = MODE != (int)Stencil::SPMV ? rowc(f, g.j, jstride) : nullptr;
       pol.ry = roww(y, g.j, jstride);
       pol.rd = MODE == (int)Stencil::RESIDUAL_NORM_DOWN ? roww(ydown, g.j, jstride) : nullptr;
       pol.nrm = 0.0;
-      walk<CH, true>(pol, g.n);
+      walk<CH, F>(pol, g.n);
       nrm[0] = pol.nrm;
+    };
+    if (g.ft) {
+      if (g.n == KSEG)
+        run(std::true_type{}, std::true_type{});
+      else
+        run(std::false_type{}, std::true_type{});
     } else {
-      StencilPol<T, MODE, false> pol;
-      pol.op.init(x, g, jstride, kb, cf, sp, L.nz);
-      pol.rf = MODE != (int)Stencil::SPMV ? rowc(f, g.j, jstride) : nullptr;
-      pol.ry = roww(y, g.j, jstride);
-      pol.rd = MODE == (int)Stencil::RESIDUAL_NORM_DOWN ? roww(ydown, g.j, jstride) : nullptr;
-      pol.nrm = 0.0;
-      walk<CH, false>(pol, g.n);
-      nrm[0] = pol.nrm;
+      if (g.n == KSEG)
+        run(std::true_type{}, std::false_type{});
+      else
+        run(std::false_type{}, std::false_type{});
     }
   }
   if constexpr (MODE >= (int)Stencil::RESIDUAL_NORM) block_partials<1, SR>(nrm, partials);
@@ -1246,16 +1297,21 @@ __global__ __launch_bounds__(NTHREADS) void k_line_pcr(Lvl<T> L, LineArgs<T> a, 
 // residual itself is never stored.  A wavefront covers 64 coarse = 128 fine
 // columns and reads each fine row pair with 16-byte vector loads.
 // ---------------------------------------------------------------------------
-template <typename T, bool FULL>
+template <typename T, bool FULL, bool X>
 struct ResRestrictPol {
   using V2 = typename Vec2<T>::type;
+  // X (all 64 lanes hold coarse columns): the fine columns west of a / c and
+  // east of b / d are the neighbouring lanes' b / d and a / c values of the
+  // same layer, passed by wave shifts; uWa and uWc then hold the halo value
+  // of the row (lane 0: west, lane 63: east, other lanes their own a / c)
   struct In {
     V2 p0, p1, sS, sN, f0, f1;
     T uWa, uEb, uWc, uEd;
   };
   const char *ra, *rc, *rS, *rN, *fa, *fb;
   char* ro;
-  uint32_t o2, ow, oe, oo, fkb, ckb;
+  uint32_t o2, ow, oe, oo, fkb, ckb, oh;
+  bool lw, le;
   int nz, k0;
   // face couplings of the 2x2 block: a = (i0,j0), b = (i0+1,j0),
   // c = (i0,j0+1), d = (i0+1,j0+1)
@@ -1269,10 +1325,15 @@ struct ResRestrictPol {
     const uint32_t okp = (uint32_t)min(k + 1, nz - 1) * fkb;
     v.p0 = ldo<V2>(ra, o2 + okp);
     v.p1 = ldo<V2>(rc, o2 + okp);
-    v.uWa = ldo<T>(ra, ow + ok);
-    v.uEb = ldo<T>(ra, oe + ok);
-    v.uWc = ldo<T>(rc, ow + ok);
-    v.uEd = ldo<T>(rc, oe + ok);
+    if constexpr (X) {
+      v.uWa = ldo<T>(ra, oh + ok);
+      v.uWc = ldo<T>(rc, oh + ok);
+    } else {
+      v.uWa = ldo<T>(ra, ow + ok);
+      v.uEb = ldo<T>(ra, oe + ok);
+      v.uWc = ldo<T>(rc, ow + ok);
+      v.uEd = ldo<T>(rc, oe + ok);
+    }
     v.sS = ldo<V2>(rS, o2 + ok);
     v.sN = ldo<V2>(rN, o2 + ok);
     v.f0 = ldn2<V2>(fa, o2 + ok);
@@ -1285,17 +1346,26 @@ struct ResRestrictPol {
     const V2 p0 = top ? v.p0 : V2{T(0), T(0)};
     const V2 p1 = top ? v.p1 : V2{T(0), T(0)};
     const T dzk = pr.dz, dgk = pr.dg, sub = pr.sub, sup = pr.sup;
+    T uWa = v.uWa, uEb = v.uEb, uWc = v.uWc, uEd = v.uEd;
+    if constexpr (X) {
+      const T wa = wave_shift<kWaveShr1>(c0.y), eb = wave_shift<kWaveShl1>(c0.x);
+      const T wc = wave_shift<kWaveShr1>(c1.y), ed = wave_shift<kWaveShl1>(c1.x);
+      uWa = lw ? v.uWa : wa;
+      uEb = le ? v.uWa : eb;
+      uWc = lw ? v.uWc : wc;
+      uEd = le ? v.uWc : ed;
+    }
     const T ra_ = v.f0.x - ((dgk + dzk * Sa) * c0.x -
-                            dzk * (xab * c0.y + xWa * v.uWa + yac * c1.x + ySa * v.sS.x) +
+                            dzk * (xab * c0.y + xWa * uWa + yac * c1.x + ySa * v.sS.x) +
                             sub * m0.x + sup * p0.x);
     const T rb_ = v.f0.y - ((dgk + dzk * Sb) * c0.y -
-                            dzk * (xbE * v.uEb + xab * c0.x + ybd * c1.y + ySb * v.sS.y) +
+                            dzk * (xbE * uEb + xab * c0.x + ybd * c1.y + ySb * v.sS.y) +
                             sub * m0.y + sup * p0.y);
     const T rc_ = v.f1.x - ((dgk + dzk * Sc) * c1.x -
-                            dzk * (xcd * c1.y + xWc * v.uWc + ycN * v.sN.x + yac * c0.x) +
+                            dzk * (xcd * c1.y + xWc * uWc + ycN * v.sN.x + yac * c0.x) +
                             sub * m1.x + sup * p1.x);
     const T rd_ = v.f1.y - ((dgk + dzk * Sd) * c1.y -
-                            dzk * (xdE * v.uEd + xcd * c1.x + ydN * v.sN.y + ybd * c0.y) +
+                            dzk * (xdE * uEd + xcd * c1.x + ydN * v.sN.y + ybd * c0.y) +
                             sub * m1.y + sup * p1.y);
     sto<T>(ro, oo + layer_off<FULL>(k, nz, ckb), ra_ + rb_ + rc_ + rd_);
     m0 = c0;
@@ -1328,9 +1398,9 @@ __device__ __forceinline__ void resrestrict_body(const Lvl<T>& F, const Lvl<T>& 
   const int jn = (j0 + 2 == ny) ? 0 : j0 + 2;
   const int64_t jst = (int64_t)nz * F.ldx;
   const uint32_t ES = sizeof(T);
-  auto run = [&](auto full) {
-    constexpr bool FL = decltype(full)::value;
-    ResRestrictPol<T, FL> P;
+  auto run = [&](auto full, auto xch) {
+    constexpr bool FL = decltype(full)::value, XC = decltype(xch)::value;
+    ResRestrictPol<T, FL, XC> P;
     const int64_t r0 = (int64_t)j0 * nx, r1c = (int64_t)(j0 + 1) * nx, rs = (int64_t)js * nx;
     P.xab = F.cx[r0 + i0];
     P.xbE = F.cx[r0 + i0 + 1];
@@ -1358,6 +1428,12 @@ __device__ __forceinline__ void resrestrict_body(const Lvl<T>& F, const Lvl<T>& 
     P.o2 = (uint32_t)i0 * ES;
     P.ow = (uint32_t)iw * ES;
     P.oe = (uint32_t)ie * ES;
+    if constexpr (XC) {
+      const int lane = (int)(threadIdx.x & 63);
+      P.lw = lane == 0;
+      P.le = lane == 63;
+      P.oh = P.lw ? P.ow : P.le ? P.oe : P.o2;
+    }
     P.oo = (uint32_t)I * ES;
     P.fkb = (uint32_t)F.ldx * ES;
     P.ckb = (uint32_t)C.ldx * ES;
@@ -1375,10 +1451,17 @@ __device__ __forceinline__ void resrestrict_body(const Lvl<T>& F, const Lvl<T>& 
     P.c1 = ldo<V2>(P.rc, P.o2 + (uint32_t)g.k0 * P.fkb);
     walk<CH, FL>(P, g.n);
   };
-  if (g.n == KSEG)
-    run(std::true_type{});
-  else
-    run(std::false_type{});
+  if (g.ft) {
+    if (g.n == KSEG)
+      run(std::true_type{}, std::true_type{});
+    else
+      run(std::false_type{}, std::true_type{});
+  } else {
+    if (g.n == KSEG)
+      run(std::true_type{}, std::false_type{});
+    else
+      run(std::false_type{}, std::false_type{});
+  }
 }
 
 template <typename T, int SR>
@@ -1396,7 +1479,11 @@ __global__ __launch_bounds__(64 * SR) void k_resrestrict(Lvl<T> F, Lvl<T> C,
 // r = f - A u', r32 = (float) r, partial ||r||^2.  u' goes to a different
 // buffer (neighbouring threads still read u and e).
 // ---------------------------------------------------------------------------
-template <bool FULL>
+// X (all 64 columns of the tile exist): the east and west values of u + e at
+// layer k are the neighbouring lanes' own, passed by wave shifts; ue / ee
+// then hold the halo column's u and e (lane 0: west, lane 63: east, other
+// lanes their own column).
+template <bool FULL, bool X>
 struct CorrectPol {
   struct In {
     double up, ue, uw, un, us, f;
@@ -1404,7 +1491,8 @@ struct CorrectPol {
   };
   const char *ru, *run, *rus, *re, *ren, *res, *rf;
   char *ruo, *rr32;
-  uint32_t oc8, oe8, ow8, oc4, oe4, ow4, kb8, kb4;
+  uint32_t oc8, oe8, ow8, oc4, oe4, ow4, kb8, kb4, oh8, oh4;
+  bool lw, le;
   int nz, k0;
   Cf<double> c;
   const Prof<double>* sp;
@@ -1417,10 +1505,15 @@ struct CorrectPol {
     const uint32_t o8 = (uint32_t)kc * kb8, o4 = (uint32_t)kc * kb4;
     v.up = ldo<double>(ru, oc8 + (uint32_t)kp * kb8);
     v.ep = ldo<float>(re, oc4 + (uint32_t)kp * kb4);
-    v.ue = ldo<double>(ru, oe8 + o8);
-    v.ee = ldo<float>(re, oe4 + o4);
-    v.uw = ldo<double>(ru, ow8 + o8);
-    v.ew = ldo<float>(re, ow4 + o4);
+    if constexpr (X) {
+      v.ue = ldo<double>(ru, oh8 + o8);
+      v.ee = ldo<float>(re, oh4 + o4);
+    } else {
+      v.ue = ldo<double>(ru, oe8 + o8);
+      v.ee = ldo<float>(re, oe4 + o4);
+      v.uw = ldo<double>(ru, ow8 + o8);
+      v.ew = ldo<float>(re, ow4 + o4);
+    }
     v.un = ldo<double>(run, oc8 + o8);
     v.en = ldo<float>(ren, oc4 + o4);
     v.us = ldo<double>(rus, oc8 + o8);
@@ -1431,8 +1524,18 @@ struct CorrectPol {
     const int k = k0 + s;
     const Prof<double> pr = sp[s];
     const double xp = (k + 1 < nz) ? v.up + (double)v.ep : 0.0;
-    const double h = c.ce * (v.ue + (double)v.ee) + c.cw * (v.uw + (double)v.ew) +
-                     c.cn * (v.un + (double)v.en) + c.cs * (v.us + (double)v.es);
+    double xe, xw;
+    if constexpr (X) {
+      const double xh = v.ue + (double)v.ee;
+      const double de = wave_shift<kWaveShl1>(xc), dw = wave_shift<kWaveShr1>(xc);
+      xe = le ? xh : de;
+      xw = lw ? xh : dw;
+    } else {
+      xe = v.ue + (double)v.ee;
+      xw = v.uw + (double)v.ew;
+    }
+    const double h = c.ce * xe + c.cw * xw + c.cn * (v.un + (double)v.en) +
+                     c.cs * (v.us + (double)v.es);
     const double au = (pr.dg + pr.dz * c.S) * xc - pr.dz * h + pr.sub * xm + pr.sup * xp;
     const double rr = v.f - au;
     const int kc = FULL ? k : min(k, nz - 1);
@@ -1455,9 +1558,9 @@ __device__ __forceinline__ void correct_residual_body(
   double nrm[1] = {0.0};
   if (g.row && g.act) {
     const int64_t jst = (int64_t)L.nz * L.ldx;
-    auto run = [&](auto full) {
-      constexpr bool FL = decltype(full)::value;
-      CorrectPol<FL> P;
+    auto run = [&](auto full, auto xch) {
+      constexpr bool FL = decltype(full)::value, XC = decltype(xch)::value;
+      CorrectPol<FL, XC> P;
       P.ru = rowc(u, g.j, jst);
       P.run = rowc(u, g.jn, jst);
       P.rus = rowc(u, g.js, jst);
@@ -1475,6 +1578,14 @@ __device__ __forceinline__ void correct_residual_body(
       P.ow4 = (uint32_t)g.iw * 4;
       P.kb8 = (uint32_t)L.ldx * 8;
       P.kb4 = (uint32_t)L.ldx * 4;
+      if constexpr (XC) {
+        const int lane = (int)(threadIdx.x & 63);
+        P.lw = lane == 0;
+        P.le = lane == 63;
+        const int ih = P.lw ? g.iw : P.le ? g.ie : g.ic;
+        P.oh8 = (uint32_t)ih * 8;
+        P.oh4 = (uint32_t)ih * 4;
+      }
       P.nz = L.nz;
       P.k0 = g.k0;
       P.c = col_coef(L, g);
@@ -1488,10 +1599,17 @@ __device__ __forceinline__ void correct_residual_body(
       walk<2, FL>(P, g.n);
       nrm[0] = P.nrm;
     };
-    if (g.n == KSEG)
-      run(std::true_type{});
-    else
-      run(std::false_type{});
+    if (g.ft) {
+      if (g.n == KSEG)
+        run(std::true_type{}, std::true_type{});
+      else
+        run(std::false_type{}, std::true_type{});
+    } else {
+      if (g.n == KSEG)
+        run(std::true_type{}, std::false_type{});
+      else
+        run(std::false_type{}, std::false_type{});
+    }
   }
   block_partials<1, SR>(nrm, partials);
 }
