@@ -93,7 +93,9 @@ def test_roofline_tables():
     assert b.WORDS_PER_CELL["prolong_smooth"] == 3.25
     for key, rec in b.MEASURED_TRAFFIC.items():
         assert len(rec["shape"]) == 2 and rec["fetch_kib"] > 0 and rec["write_kib"] > 0
-        assert 2.0 < rec["copy_fetch_scale"] < 2.7 and 0.9 < rec["copy_write_scale"] < 1.1
+        # FETCH_SIZE counts a 128-byte read request as 64 bytes on gfx950, so a
+        # plain copy reads about half its bytes (some boxes a little less)
+        assert 1.9 < rec["copy_fetch_scale"] < 2.7 and 0.9 < rec["copy_write_scale"] < 1.1
         assert len(rec["source_sha256"]) == 64
     # the counters are used only while the kernel source is the one measured
     rec = b.MEASURED_TRAFFIC[("cg_spmv", 0, "f64")]
