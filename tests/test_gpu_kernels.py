@@ -33,6 +33,8 @@ SHAPES = [
     (96, 32, 2),      # minimum nz
     (34, 10, 128),    # maximum nz, ragged
     (16, 18, 127),    # odd maximum
+    (192, 6, 37),     # three full 64-column tiles (east/west by lane shifts, periodic halo)
+    (200, 5, 64),     # three full tiles and a ragged one
 ]
 F64 = 1e-12
 F32_STENCIL = 2e-6

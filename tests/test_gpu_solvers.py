@@ -27,7 +27,11 @@ def _need_gpu():
 
 
 VC = [((4, 4, 8), 1, 2), ((8, 8, 4), 2, 2), ((8, 8, 3), 3, 3), ((64, 64, 64), 4, 2),
-      ((40, 24, 37), 3, 2), ((32, 64, 128), 5, 2)]
+      ((40, 24, 37), 3, 2), ((32, 64, 128), 5, 2),
+      # full 64-column tiles on the fine and coarse levels (the fused
+      # residual-restriction passes neighbours by lane shifts there), and
+      # full tiles beside a ragged one
+      ((256, 4, 33), 3, 2), ((264, 6, 40), 2, 2)]
 
 
 @pytest.mark.parametrize("shape,L,nc", VC)
@@ -112,9 +116,14 @@ def test_pcg_line_matches_oracle():
         assert true_rel == pytest.approx(rel, rel=1e-6)
 
 
-def test_mixed_precision_refinement_reaches_fp64_tolerance():
+@pytest.mark.parametrize("grid", ["small", "wide"])
+def test_mixed_precision_refinement_reaches_fp64_tolerance(grid):
     import paper_1402_3545_amd as G
     w = W.SMALL
+    if grid == "wide":
+        # full 64-column tiles beside a ragged one in the FP64 update +
+        # residual (east/west of u + e by lane shifts)
+        w = W.Workload("wide-200x8x40", 200, 8, 40, 3, 1e5, 1.0, 6, "uniform", 1e-8)
     ctx, orc, _ = problem(w.nx, w.ny, w.nz, nlevels=w.nlevels, kv=w.kv, seed=w.seed,
                           kh_model=w.kh_model, prec_precond=1)
     f = w.rhs()
