@@ -1106,12 +1106,20 @@ void par_memcpy(void* dst, const void* src, size_t n) {
     return;
   }
   std::vector<std::thread> th;
-  for (size_t t = 0; t < nt; ++t) {
-    const size_t a = t * per;
-    if (a >= n) break;
-    const size_t len = std::min(per, n - a);
-    th.emplace_back([=] { memcpy(static_cast<char*>(dst) + a, static_cast<const char*>(src) + a, len); });
+  size_t done = 0;  // bytes handed to threads
+  try {
+    for (size_t t = 0; t < nt; ++t) {
+      const size_t a = t * per;
+      if (a >= n) break;
+      const size_t len = std::min(per, n - a);
+      th.emplace_back(
+          [=] { memcpy(static_cast<char*>(dst) + a, static_cast<const char*>(src) + a, len); });
+      done = a + len;
+    }
+  } catch (...) {
+    // no thread to be had: the caller's thread copies the rest
   }
+  if (done < n) memcpy(static_cast<char*>(dst) + done, static_cast<const char*>(src) + done, n - done);
   for (std::thread& t : th) t.join();
 }
 
