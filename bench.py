@@ -53,7 +53,10 @@ WORDS_PER_CELL = {
     # (inside the V-cycle each coarse level starts with a scaled line solve,
     # timed as line_solve of that level)
     "prolongate": 2.25,      # per FINE cell: read/write u_f, read 1/4 u_c
-    "cg_spmv": 7.0,          # read u, p, z, q, write u, p, q
+    # line-PCG's direction step alternates: odd iterations read z, p, q and
+    # write p', q (5 words); even ones also take the two pending steps of the
+    # iterate, reading u and the direction before last and writing u (8)
+    "cg_spmv": 6.5,
     "cg_tridiag": 4.0,       # read r, q, write r, z
     "correct": 4.0,          # read u, f (8 B), e (4 B), write u (8 B), r (4 B): 32 B
     "residual_restrict": 2.25,  # per FINE cell: read u, f, write 1/4 f_c
@@ -724,10 +727,15 @@ def main():
     # (the returned launches' few us stay in the total).
     n_dom, ms_dom = table[dom]
     n_work = n_dom
-    if dom[:2] == ("cg_spmv", 0) and all("pcg_f64" in r for r in runs):
-        n_work = sum(r["pcg_f64"]["iters"] for r in runs)
-    avg_ms = ms_dom / n_work
     bytes_dom = algorithmic_bytes(*dom, w)
+    if dom[:2] == ("cg_spmv", 0) and all("pcg_f64" in r for r in runs):
+        its = [r["pcg_f64"]["iters"] for r in runs]
+        n_work = sum(its)
+        # the exact mix of odd (5-word) and even (8-word) direction steps
+        n_even = sum(i // 2 for i in its)
+        words = (5.0 * (n_work - n_even) + 8.0 * n_even) / n_work
+        bytes_dom = words * w.nx * w.ny * w.nz * 8
+    avg_ms = ms_dom / n_work
     achieved = bytes_dom / (avg_ms / 1e3) / 1e9
     log("[bench] kernel breakdown (one fully timed step): " + json.dumps(breakdown))
 

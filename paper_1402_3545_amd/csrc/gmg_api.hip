@@ -962,8 +962,9 @@ int tune_solver(gmg_ctx* c, int reps, hipStream_t s, hipEvent_t ea, hipEvent_t e
   int64_t nb = 0;
   int st;
   if ((st = tune_kind(c, GMG_K_CG_SPMV, 0, GMG_F64, Cand::STENCIL, nts, reps, s, ea, eb, [&](Shape sh) {
-         return gmg::launch_cg_p1(V, c->vt, c->vp, c->vz, c->vq, c->state, c->partials, &nb, s,
-                                  sh);
+         // the heavier (even, paired) form of line-PCG's direction step
+         return gmg::launch_cg_p1(V, c->vt, c->vp, c->vr, c->vz, c->vq, c->state, true,
+                                  c->partials, &nb, s, sh);
        })))
     return st;
   if ((st = tune_kind(c, GMG_K_CG_TRIDIAG, 0, GMG_F64, Cand::LINE, ntl, reps, s, ea, eb,
@@ -1611,15 +1612,19 @@ int pcg_solve(gmg_ctx* c, const double* f, double* u, double rtol, int maxit, in
                 [&] { return gmg::launch_fill<double>(c->vp, n0, 0.0, s); }));
   HIP_TRY(timed(c, GMG_K_AUX, 0, GMG_F64, s,
                 [&] { return gmg::launch_fill<double>(c->vq, n0, 0.0, s); }));
-  // iterations in predicted batches; kernels of iterations after convergence
-  // return at once
+  // iterations in predicted batches of pairs; kernels of iterations after
+  // convergence return at once.  Direction i goes to buffer i & 1 (vp, vt):
+  // odd iterations leave u alone, even ones apply the two pending steps.
   {
     GateScope gate(c);
-    auto unit = [&](hipStream_t q, int) -> int {
+    auto unit = [&](hipStream_t q, int r) -> int {
       const Lvl<double> Vg = gmg::view<double>(c, 0);
       int64_t nb1 = 0, nb2 = 0;
+      double* pr = r == 0 ? c->vp : c->vt;
+      double* pw = r == 0 ? c->vt : c->vp;
       HIP_TRY(timed(c, GMG_K_CG_SPMV, 0, GMG_F64, q, [&](gmg::Shape sh) {
-        return gmg::launch_cg_p1(Vg, u, c->vp, c->vz, c->vq, c->state, c->partials, &nb1, q, sh);
+        return gmg::launch_cg_p1(Vg, u, pr, pw, c->vz, c->vq, c->state, r == 1, c->partials,
+                                 &nb1, q, sh);
       }));
       HIP_TRY(timed(c, GMG_K_REDUCE, 0, GMG_F64, q,
                     [&] { return gmg::launch_cg_fin1(c->state, c->partials, nb1, q); }));
@@ -1631,10 +1636,11 @@ int pcg_solve(gmg_ctx* c, const double* f, double* u, double rtol, int maxit, in
       }));
       return GMG_OK;
     };
-    if ((st = run_iterations(c, s, GK_PCG, f, u, kPcgKinds, maxit, 1, 4, unit))) return st;
+    if ((st = run_iterations(c, s, GK_PCG, f, u, kPcgKinds, maxit, 2, 4, unit))) return st;
   }
-  HIP_TRY(timed(c, GMG_K_AUX, 0, GMG_F64, s,
-                [&] { return gmg::launch_cg_final_update(V, u, c->vp, c->state, s); }));
+  HIP_TRY(timed(c, GMG_K_AUX, 0, GMG_F64, s, [&] {
+    return gmg::launch_pcg_final_update(V, u, c->vp, c->vt, c->state, s);
+  }));
   const CgState hs = *c->hstate;
   if (history && hs.iter >= 0) memcpy(history, c->hhist, (size_t)(hs.iter + 1) * sizeof(double));
   double rr = 0.0;

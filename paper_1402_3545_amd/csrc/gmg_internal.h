@@ -48,6 +48,7 @@ struct CgState {
   int iter, done, maxit, status;     // status: 0 running/converged, 1 maxit,
                                      // 2 non-finite, 3 breakdown
   double rtol;                       // multigrid / refinement stopping test
+  double alpha_prev;                 // line-PCG: the step before alpha
 };
 
 // One work item of a grouped launch: one kernel applied to one level of one
@@ -248,8 +249,13 @@ template <typename T>
 hipError_t launch_prolongate(const Lvl<T>& C, const Lvl<T>& F, const T* uc, T* uf,
                              hipStream_t s, Shape sh = {});
 
-hipError_t launch_cg_p1(const Lvl<double>& L, double* u, double* p, const double* z, double* q,
-                        const CgState* st, double* partials, int64_t* nblocks, hipStream_t s, Shape sh = {});
+// CG direction step: p_new = z + beta p_old, q = A z + beta q, <p_new, q>.
+// p_old is read from pr and p_new written to pw (distinct buffers).
+// paired: also u += alpha_prev pw_old + alpha pr (pw's old contents are the
+// direction before p_old), the two pending steps of the iterate.
+hipError_t launch_cg_p1(const Lvl<double>& L, double* u, const double* pr, double* pw,
+                        const double* z, double* q, const CgState* st, bool paired,
+                        double* partials, int64_t* nblocks, hipStream_t s, Shape sh = {});
 hipError_t launch_cg_p2(const Lvl<double>& L, double* r, const double* q, double* z,
                         const CgState* st, int init, double* partials, int64_t* nblocks,
                         hipStream_t s, Shape sh = {});
@@ -259,6 +265,10 @@ hipError_t launch_cg_fin2(CgState* st, const double* partials, int64_t nblocks, 
                           double* hist, hipStream_t s);
 hipError_t launch_cg_final_update(const Lvl<double>& L, double* u, const double* p,
                                   const CgState* st, hipStream_t s);
+// line-PCG with paired updates: the steps of the directions not yet applied
+// to u (direction j lives in p[j & 1])
+hipError_t launch_pcg_final_update(const Lvl<double>& L, double* u, const double* p0,
+                                   const double* p1, const CgState* st, hipStream_t s);
 hipError_t launch_reduce(const double* partials, int64_t nblocks, int ncomp, double* out,
                          hipStream_t s);
 // multigrid / refinement: ||f - A u||^2 from the partials -> relative

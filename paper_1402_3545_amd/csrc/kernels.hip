@@ -1723,14 +1723,19 @@ __global__ __launch_bounds__(64 * SR) void k_prolongate(Lvl<T> C, Lvl<T> F,
 // CG, first fused kernel ("SpMV" of Sec. 3.1):
 //   u += alpha p;  p = z + beta p;  q = A z + beta q;  partial <p, q>
 // ---------------------------------------------------------------------------
-template <bool FULL>
+// PAIR (even iterations of line-PCG): the iterate also takes the two steps
+// not yet applied, u += alpha_prev p_{i-2} + alpha p_{i-1}, with p_{i-2} read
+// from the buffer that p_i then overwrites; odd iterations touch neither u nor
+// p_{i-2} (5 words per cell instead of 7; even ones 8).
+template <bool FULL, bool PAIR>
 struct CgP1Pol {
   struct In {
-    double xp, xe, xw, xn, xs, p, q, u;
+    double xp, xe, xw, xn, xs, p, q, u, p2;
   };
   ColumnOp<double> op;  // on z
-  char *ru, *rp, *rq;
-  double alpha, beta, pq;
+  char *ru, *rw, *rq;
+  const char* rp;
+  double alpha, alpha_prev, beta, pq;
 
   __device__ __forceinline__ void load(int s, In& v) {
     const int k = op.k0 + s;
@@ -1739,7 +1744,10 @@ struct CgP1Pol {
     op.load(ok, okp, v.xp, v.xe, v.xw, v.xn, v.xs);
     v.p = ldn<double>(rp, op.oc + ok);
     v.q = ldn<double>(rq, op.oc + ok);
-    v.u = ldn<double>(ru, op.oc + ok);
+    if constexpr (PAIR) {
+      v.u = ldn<double>(ru, op.oc + ok);
+      v.p2 = ldn<double>(rw, op.oc + ok);
+    }
   }
   __device__ __forceinline__ void step(int s, const In& v) {
     const uint32_t o = op.oc + layer_off<FULL>(op.k0 + s, op.nz, op.kb);
@@ -1747,16 +1755,18 @@ struct CgP1Pol {
     const double az = op.apply(s, v.xp, v.xe, v.xw, v.xn, v.xs);
     const double pn = zc + beta * v.p;
     const double qn = az + beta * v.q;
-    sto<double>(ru, o, v.u + alpha * v.p);
-    sto<double>(rp, o, pn);
+    // the two steps in the order of the iterations they belong to
+    if constexpr (PAIR) sto<double>(ru, o, fma(alpha, v.p, fma(alpha_prev, v.p2, v.u)));
+    sto<double>(rw, o, pn);
     sto<double>(rq, o, qn);
     pq += pn * qn;
   }
 };
 
-template <int SR>
+template <int SR, bool PAIR>
 __global__ __launch_bounds__(64 * SR) void k_cg_p1(Lvl<double> L, double* __restrict__ u,
-                                                   double* __restrict__ p,
+                                                   const double* __restrict__ pr,
+                                                   double* __restrict__ pw,
                                                    const double* __restrict__ z,
                                                    double* __restrict__ q,
                                                    const CgState* __restrict__ st,
@@ -1764,7 +1774,7 @@ __global__ __launch_bounds__(64 * SR) void k_cg_p1(Lvl<double> L, double* __rest
                                                    int ntj, int group) {
   if (st->done || gated(L)) return;  // uniform: the solve has already stopped
   constexpr int CH = 2;
-  const double alpha = st->alpha, beta = st->beta;
+  const double alpha = st->alpha, alpha_prev = st->alpha_prev, beta = st->beta;
   const Geo g =
       stencil_geo<SR>(L.nx, L.ny, L.nz, nti, ntj, group, xcd_remap(blockIdx.x, gridDim.x));
   __shared__ Prof<double> sp[KSEG];
@@ -1776,12 +1786,14 @@ __global__ __launch_bounds__(64 * SR) void k_cg_p1(Lvl<double> L, double* __rest
     const Cf<double> cf = col_coef(L, g);
     auto run = [&](auto full) {
       constexpr bool F = decltype(full)::value;
-      CgP1Pol<F> pol;
+      CgP1Pol<F, PAIR> pol;
       pol.op.init(z, g, jstride, kb, cf, sp, L.nz);
-      pol.ru = roww(u, g.j, jstride);
-      pol.rp = roww(p, g.j, jstride);
+      pol.ru = PAIR ? roww(u, g.j, jstride) : nullptr;
+      pol.rp = rowc(pr, g.j, jstride);
+      pol.rw = roww(pw, g.j, jstride);
       pol.rq = roww(q, g.j, jstride);
       pol.alpha = alpha;
+      pol.alpha_prev = alpha_prev;
       pol.beta = beta;
       pol.pq = 0.0;
       walk<CH, F>(pol, g.n);
@@ -2115,6 +2127,7 @@ __global__ __launch_bounds__(NTHREADS) void k_cg_fin1(CgState* st,
       st->status = 3;  // breakdown before the step: keep the previous iterate
       st->done = 1;
     } else {
+      st->alpha_prev = st->alpha;
       st->alpha = st->kappa / sigma;
     }
   }
@@ -2136,6 +2149,7 @@ __global__ __launch_bounds__(NTHREADS) void k_cg_fin2(CgState* st,
       st->kappa = rz;
       st->iter = 0;
       st->alpha = 0.0;
+      st->alpha_prev = 0.0;
       st->beta = 0.0;
       hist[0] = 1.0;
       if (rr == 0.0) st->done = 1;
@@ -2303,6 +2317,37 @@ __global__ __launch_bounds__(NTHREADS) void k_cg_final_update(Lvl<double> L,
   for (int64_t g = (int64_t)blockIdx.x * NTHREADS + threadIdx.x; g < n;
        g += (int64_t)gridDim.x * NTHREADS)
     u[g] += alpha * p[g];
+}
+
+// Line-PCG with paired updates: after n completed iterations (n = iter) the
+// directions j <= n not yet in u are applied, in order.  The last direction
+// step kernel that ran is iteration n + 1 after a breakdown before its step
+// (status 3), else n; an even one (m) applied the directions up to m - 1, so
+// one or two remain: n alone, or n - 1 and n.  Direction j lives in p_{j & 1}
+// (an even step m overwrote p_{(m) & 1} only after reading it).
+__global__ __launch_bounds__(NTHREADS) void k_pcg_final_update(Lvl<double> L,
+                                                               double* __restrict__ u,
+                                                               const double* __restrict__ p0,
+                                                               const double* __restrict__ p1,
+                                                               const CgState* __restrict__ st) {
+  const int n = st->iter;
+  if (n <= 0) return;
+  const int last = n + (st->status == 3 ? 1 : 0);
+  const int applied = (last & 1) ? last - 2 : last - 1;
+  if (applied >= n) return;
+  const double* pn = (n & 1) ? p1 : p0;
+  const double* pm = (n & 1) ? p0 : p1;  // direction n - 1
+  const double an = st->alpha, am = st->alpha_prev;
+  const bool two = applied < n - 1;
+  // the grid's cells only: the padding columns of the direction buffers are
+  // never written
+  const int64_t cnt = (int64_t)L.ny * L.nz * L.ldx;
+  for (int64_t g = (int64_t)blockIdx.x * NTHREADS + threadIdx.x; g < cnt;
+       g += (int64_t)gridDim.x * NTHREADS) {
+    if (g % L.ldx >= L.nx) continue;
+    const double v = two ? fma(am, pm[g], u[g]) : u[g];
+    u[g] = fma(an, pn[g], v);
+  }
 }
 
 // dst = src over a level's field (both in its layout), gated like the
@@ -2635,15 +2680,19 @@ hipError_t launch_prolongate(const Lvl<T>& C, const Lvl<T>& F, const T* uc, T* u
   });
 }
 
-hipError_t launch_cg_p1(const Lvl<double>& L, double* u, double* p, const double* z, double* q,
-                        const CgState* st, double* partials, int64_t* nblocks, hipStream_t s,
-                        Shape sh) {
+hipError_t launch_cg_p1(const Lvl<double>& L, double* u, const double* pr, double* pw,
+                        const double* z, double* q, const CgState* st, bool paired,
+                        double* partials, int64_t* nblocks, hipStream_t s, Shape sh) {
   return with_rows(sh.rows, [&](auto R) {
     constexpr int SR = decltype(R)::value;
     const int nti = cdiv(L.nx, 64), ntj = cdiv(L.ny, SR), nkb = cdiv(L.nz, KSEG);
     *nblocks = (int64_t)nti * ntj * nkb;
-    hipLaunchKernelGGL(k_cg_p1<SR>, dim3(nti * ntj * nkb), dim3(64 * SR), 0, s, L, u, p, z, q, st,
-                       partials, nti, ntj, sh.group);
+    if (paired)
+      hipLaunchKernelGGL((k_cg_p1<SR, true>), dim3(nti * ntj * nkb), dim3(64 * SR), 0, s, L, u,
+                         pr, pw, z, q, st, partials, nti, ntj, sh.group);
+    else
+      hipLaunchKernelGGL((k_cg_p1<SR, false>), dim3(nti * ntj * nkb), dim3(64 * SR), 0, s, L, u,
+                         pr, pw, z, q, st, partials, nti, ntj, sh.group);
   });
 }
 
@@ -2736,6 +2785,14 @@ hipError_t launch_cg_final_update(const Lvl<double>& L, double* u, const double*
   const int64_t n = (int64_t)L.ny * L.nz * L.ldx;
   hipLaunchKernelGGL(k_cg_final_update, dim3(grid_stride_blocks(n)), dim3(NTHREADS), 0, s, L, u,
                      p, st);
+  return hipGetLastError();
+}
+
+hipError_t launch_pcg_final_update(const Lvl<double>& L, double* u, const double* p0,
+                                   const double* p1, const CgState* st, hipStream_t s) {
+  const int64_t n = (int64_t)L.ny * L.nz * L.ldx;
+  hipLaunchKernelGGL(k_pcg_final_update, dim3(grid_stride_blocks(n)), dim3(NTHREADS), 0, s, L,
+                     u, p0, p1, st);
   return hipGetLastError();
 }
 

@@ -89,7 +89,7 @@ def test_roofline_tables():
         if k in ("reduce", "aux", "fcg"):
             continue
         assert k in b.WORDS_PER_CELL, k
-    assert b.WORDS_PER_CELL["cg_spmv"] == 7.0   # u, p, z, q in; u, p, q out
+    assert b.WORDS_PER_CELL["cg_spmv"] == 6.5   # 5 and 8 words on alternate iterations
     assert b.WORDS_PER_CELL["prolong_smooth"] == 3.25
     for key, rec in b.MEASURED_TRAFFIC.items():
         assert len(rec["shape"]) == 2 and rec["fetch_kib"] > 0 and rec["write_kib"] > 0
