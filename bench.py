@@ -76,17 +76,18 @@ SOLVES = ("mg_f64", "pcg_f64", "mg_mixed", "fcg_mixed")
 # dispatches) scaled by what the same counters read for a plain copy of known
 # size.  Reported only while the kernel source hashes to the recorded value.
 MEASURED_TRAFFIC = {
-    # k_cg_p1, 64x16 workgroups, tile groups of 8 (the stored launch shape);
-    # profiles/cg_p1_1024x1024x128_pmc.md.  Averages over the 162 dispatches
-    # that did the work (the two enqueued past convergence return at once).
-    # Plain-copy calibration: 2 GiB read + 2 GiB written read FETCH_SIZE
-    # 1048592.4 KiB, WRITE_SIZE 2097186.1 KiB.
+    # k_cg_p1 (both forms), 64x16 workgroups, tile groups of 8 (the stored
+    # launch shape); profiles/cg_p1_1024x1024x128_pmc.md.  Averages over the
+    # 162 dispatches that did the work (82 odd-iteration, 80 even-iteration
+    # forms; the two enqueued past convergence return at once).  Plain-copy
+    # calibration: 2 GiB read + 2 GiB written read FETCH_SIZE 1048592.6 KiB,
+    # WRITE_SIZE 2097192.0 KiB.
     ("cg_spmv", 0, "f64"): {
-        "fetch_kib": 2326983.8854,
-        "write_kib": 3145864.2340,
-        "copy_fetch_scale": 2097152.0 / 1048592.3958,
-        "copy_write_scale": 2097152.0 / 2097186.1458,
-        "source_sha256": "05c9191309c571151bce36096a0a1a376a345f82795f3ae100f5792bf75c199e",
+        "fetch_kib": 2313138.6825,
+        "write_kib": 2615100.3993,
+        "copy_fetch_scale": 2097152.0 / 1048592.6146,
+        "copy_write_scale": 2097152.0 / 2097191.9792,
+        "source_sha256": "54c9e0c7b9d5d2e1f6817304c8aea7d5ee16bd33b40fb83577d01439fec01ded",
         "shape": [16, 8],
     },
 }
