@@ -62,11 +62,13 @@ WORDS_PER_CELL = {
     "residual_restrict": 2.25,  # per FINE cell: read u, f, write 1/4 f_c
     "prolong_smooth": 3.25,  # read u, f, write u', read 1/4 u_c (u + P u_c not stored)
     # the three vector kernels of a flexible-CG iteration with an FP32
-    # preconditioner move 100 B per cell together: <z,q> reads z (4 B) and q;
-    # the direction kernel reads z, u, p, q, r and writes u, p, q (60 B); the
-    # update reads r, q and writes r and its FP32 copy (28 B).  They share one
-    # timing kind, so each launch counts as a third of the iteration.
-    "fcg": 100.0 / 3.0 / 8.0,
+    # preconditioner move 96 B per cell together on average: <z,q> reads z
+    # (4 B) and q; the direction kernel reads z, p, q, r and writes p, q
+    # (44 B), on even iterations also reading u and the direction before last
+    # and writing u (68 B); the update reads r, q and writes r and its FP32
+    # copy (28 B).  They share one timing kind, so each launch counts as a
+    # third of the iteration.
+    "fcg": 96.0 / 3.0 / 8.0,
 }
 
 SOLVES = ("mg_f64", "pcg_f64", "mg_mixed", "fcg_mixed")

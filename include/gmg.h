@@ -338,7 +338,8 @@ int gmg_autotune(gmg_ctx *c, int reps, void *stream);
  * host round trip per cycle).  enable = 1 (the default): each batch of the
  * multigrid, refinement and flexible-CG solves is replayed from a hipGraph of
  * one iteration (two for the refinement, whose iterate alternates between two
- * buffers; line-PCG's four-kernel iteration is always launched directly),
+ * buffers, and for flexible CG, whose directions do; line-PCG's four-kernel
+ * iteration is always launched directly),
  * captured on the context's own
  * stream at the first solve with a given pair of caller fields and kept until
  * gmg_destroy, a launch-shape change (gmg_set_launch, gmg_autotune) or

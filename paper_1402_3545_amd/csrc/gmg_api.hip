@@ -738,8 +738,10 @@ int fcg_impl(gmg_ctx* c, const double* f, double* u, double rtol, int maxit, int
   const TZ* rin = mixed ? reinterpret_cast<const TZ*>(c->er32) : reinterpret_cast<const TZ*>(c->vr);
   {
     GateScope gate(c);
-    // one iteration; every kernel returns at once once the state is done
-    auto unit = [&](hipStream_t q, int) -> int {
+    // one iteration; every kernel returns at once once the state is done.
+    // Direction i goes to buffer i & 1 (vp, vt); odd iterations leave u
+    // alone, even ones apply the two pending steps.
+    auto unit = [&](hipStream_t q, int ri) -> int {
       const Lvl<TZ> VZg = gmg::view<TZ>(c, 0);
       const Lvl<double> Vg = gmg::view<double>(c, 0);
       if (line_only) {
@@ -759,8 +761,8 @@ int fcg_impl(gmg_ctx* c, const double* f, double* u, double rtol, int maxit, int
         return gmg::launch_fcg_fin(0, c->state, c->partials, nb, nullptr, q);
       }));
       HIP_TRY(timed(c, GMG_K_FCG, 0, GMG_F64, q, [&](gmg::Shape sh) {
-        return gmg::launch_fcg_dir<TZ>(Vg, z, u, c->vp, c->vq, c->vr, c->state, c->partials, &nb,
-                                       q, sh);
+        return gmg::launch_fcg_dir<TZ>(Vg, z, u, ri == 0 ? c->vp : c->vt, ri == 0 ? c->vt : c->vp,
+                                       c->vq, c->vr, c->state, ri == 1, c->partials, &nb, q, sh);
       }));
       HIP_TRY(timed(c, GMG_K_REDUCE, 0, GMG_F64, q, [&] {
         return gmg::launch_fcg_fin(1, c->state, c->partials, nb, nullptr, q);
@@ -774,14 +776,15 @@ int fcg_impl(gmg_ctx* c, const double* f, double* u, double rtol, int maxit, int
       }));
       return GMG_OK;
     };
-    if ((st = run_iterations(c, s, line_only ? GK_FCG_LINE : GK_FCG, f, u, kFcgKinds, maxit, 1,
+    if ((st = run_iterations(c, s, line_only ? GK_FCG_LINE : GK_FCG, f, u, kFcgKinds, maxit, 2,
                              4, unit)))
       return st;
   }
-  // the last step (the direction kernels apply each earlier one); skipped
-  // after a breakdown before the step
-  HIP_TRY(timed(c, GMG_K_AUX, 0, GMG_F64, s,
-                [&] { return gmg::launch_cg_final_update(V, u, c->vp, c->state, s); }));
+  // the steps still owed to the iterate (the direction kernels of even
+  // iterations apply the earlier ones in pairs)
+  HIP_TRY(timed(c, GMG_K_AUX, 0, GMG_F64, s, [&] {
+    return gmg::launch_pcg_final_update(V, u, c->vp, c->vt, c->state, s);
+  }));
   const CgState hs = *c->hstate;
   if (history) memcpy(history, c->hhist, (size_t)(hs.iter + 1) * sizeof(double));
   double rr = 0.0;
@@ -989,12 +992,12 @@ int tune_solver(gmg_ctx* c, int reps, hipStream_t s, hipEvent_t ea, hipEvent_t e
       return st;
   }
   if ((st = tune_kind(c, GMG_K_FCG, 0, GMG_F64, Cand::STENCIL, nts, reps, s, ea, eb, [&](Shape sh) {
-         // vt stands in for u (alpha = 0 writes it unchanged)
+         // the odd-iteration form (it leaves u alone), vp -> vt
          hipError_t e =
-             mixed ? gmg::launch_fcg_dir<float>(V, c->eu32, c->vt, c->vp, c->vq, c->vr, c->state,
-                                                c->partials, &nb, s, sh)
-                   : gmg::launch_fcg_dir<double>(V, c->vz, c->vt, c->vp, c->vq, c->vr, c->state,
-                                                 c->partials, &nb, s, sh);
+             mixed ? gmg::launch_fcg_dir<float>(V, c->eu32, nullptr, c->vp, c->vt, c->vq, c->vr,
+                                                c->state, false, c->partials, &nb, s, sh)
+                   : gmg::launch_fcg_dir<double>(V, c->vz, nullptr, c->vp, c->vt, c->vq, c->vr,
+                                                 c->state, false, c->partials, &nb, s, sh);
          if (e != hipSuccess) return e;
          return gmg::launch_fcg_update(V, c->vr, c->vq, mixed ? c->er32 : nullptr, c->state,
                                        c->partials, &nb, s, sh);

@@ -263,10 +263,8 @@ hipError_t launch_cg_p2(const Lvl<double>& L, double* r, const double* q, double
 hipError_t launch_cg_fin1(CgState* st, const double* partials, int64_t nblocks, hipStream_t s);
 hipError_t launch_cg_fin2(CgState* st, const double* partials, int64_t nblocks, int init,
                           double* hist, hipStream_t s);
-hipError_t launch_cg_final_update(const Lvl<double>& L, double* u, const double* p,
-                                  const CgState* st, hipStream_t s);
-// line-PCG with paired updates: the steps of the directions not yet applied
-// to u (direction j lives in p[j & 1])
+// line-PCG and flexible CG with paired updates: the steps of the
+// directions not yet applied to u (direction j lives in p[j & 1])
 hipError_t launch_pcg_final_update(const Lvl<double>& L, double* u, const double* p0,
                                    const double* p1, const CgState* st, hipStream_t s);
 hipError_t launch_reduce(const double* partials, int64_t nblocks, int ncomp, double* out,
@@ -279,11 +277,13 @@ hipError_t launch_mg_fin(CgState* st, const double* partials, int64_t nblocks, i
 template <typename TZ>
 hipError_t launch_fcg_zq(const Lvl<double>& L, const TZ* z, const double* q, double* partials,
                          int64_t* nblocks, hipStream_t s);
-// u += alpha_prev p_old; p = z + beta p; q = A z + beta q; <p,q>, <p,r>
+// p_new = z + beta p_old (p_old from pr, p_new to pw, distinct buffers);
+// q = A z + beta q; <p_new,q>, <p_new,r>; paired: also
+// u += alpha_prev pw_old + alpha pr (the two pending steps of the iterate)
 template <typename TZ>
-hipError_t launch_fcg_dir(const Lvl<double>& L, const TZ* z, double* u, double* p, double* q,
-                          const double* r, const CgState* st, double* partials, int64_t* nblocks,
-                          hipStream_t s, Shape sh = {});
+hipError_t launch_fcg_dir(const Lvl<double>& L, const TZ* z, double* u, const double* pr,
+                          double* pw, double* q, const double* r, const CgState* st, bool paired,
+                          double* partials, int64_t* nblocks, hipStream_t s, Shape sh = {});
 // r -= alpha q (+ FP32 copy), ||r||^2
 hipError_t launch_fcg_update(const Lvl<double>& L, double* r, const double* q, float* rdown,
                              const CgState* st, double* partials, int64_t* nblocks,

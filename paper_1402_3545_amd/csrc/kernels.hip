@@ -1841,16 +1841,19 @@ __global__ __launch_bounds__(NTHREADS) void k_fcg_zq(Lvl<double> L, const TZ* __
   block_partials<1>(acc, partials);
 }
 
-template <typename TZ, bool FULL>
+// PAIR: as in line-PCG, even iterations also apply the two pending steps of
+// the iterate (u += alpha_prev p_{i-2} + alpha p_{i-1}, p_{i-2} read from the
+// buffer that p_i overwrites); odd ones leave u alone.
+template <typename TZ, bool FULL, bool PAIR>
 struct FcgDirPol {
   struct In {
-    double xp, xe, xw, xn, xs, p, q, r, u;
+    double xp, xe, xw, xn, xs, p, q, r, u, p2;
   };
   ColumnOp<double, TZ> op;  // on z
-  char *rp, *rq, *ru;
-  const char* rr;
+  char *rw, *rq, *ru;
+  const char *rp, *rr;
   uint32_t oc, kb;
-  double beta, aprev, pq, pr;
+  double beta, alpha, alpha_prev, pq, pr;
 
   __device__ __forceinline__ void load(int s, In& v) {
     const int k = op.k0 + s;
@@ -1860,36 +1863,41 @@ struct FcgDirPol {
     v.p = ldn<double>(rp, o);
     v.q = ldn<double>(rq, o);
     v.r = ldn<double>(rr, o);
-    v.u = ldn<double>(ru, o);
+    if constexpr (PAIR) {
+      v.u = ldn<double>(ru, o);
+      v.p2 = ldn<double>(rw, o);
+    }
   }
   __device__ __forceinline__ void step(int s, const In& v) {
     const uint32_t o = oc + layer_off<FULL>(op.k0 + s, op.nz, kb);
     const double zc = op.xc;
     const double az = op.apply(s, v.xp, v.xe, v.xw, v.xn, v.xs);
-    sto<double>(ru, o, v.u + aprev * v.p);  // the previous step, with its direction
+    // the two pending steps, in the order of their iterations
+    if constexpr (PAIR) sto<double>(ru, o, fma(alpha, v.p, fma(alpha_prev, v.p2, v.u)));
     const double pn = zc + beta * v.p;
     const double qn = az + beta * v.q;
-    sto<double>(rp, o, pn);
+    sto<double>(rw, o, pn);
     sto<double>(rq, o, qn);
     pq += pn * qn;
     pr += pn * v.r;
   }
 };
 
-// The previous iteration's update of the iterate, u += alpha p, is applied
-// here, where the old direction is read anyway (alpha = 0 before the first
-// step); the last one after the loop.
-template <typename TZ, int SR>
+// The updates of the iterate, u += alpha p, are applied here in pairs, where
+// the old directions are read anyway (alpha = 0 before the first step); the
+// ones still pending after the loop by a final kernel.
+template <typename TZ, int SR, bool PAIR>
 __global__ __launch_bounds__(64 * SR) void k_fcg_dir(Lvl<double> L, const TZ* __restrict__ z,
                                                      double* __restrict__ u,
-                                                     double* __restrict__ p,
+                                                     const double* __restrict__ pr,
+                                                     double* __restrict__ pw,
                                                      double* __restrict__ q,
                                                      const double* __restrict__ r,
                                                      const CgState* __restrict__ st,
                                                      double* __restrict__ partials, int nti,
                                                      int ntj, int group) {
   if (st->done || gated(L)) return;
-  const double beta = st->beta, aprev = st->alpha;
+  const double beta = st->beta, alpha = st->alpha, alpha_prev = st->alpha_prev;
   const Geo g =
       stencil_geo<SR>(L.nx, L.ny, L.nz, nti, ntj, group, xcd_remap(blockIdx.x, gridDim.x));
   __shared__ Prof<double> sp[KSEG];
@@ -1899,16 +1907,18 @@ __global__ __launch_bounds__(64 * SR) void k_fcg_dir(Lvl<double> L, const TZ* __
     const int64_t jst = (int64_t)L.nz * L.ldx;
     auto run = [&](auto full) {
       constexpr bool FL = decltype(full)::value;
-      FcgDirPol<TZ, FL> P;
+      FcgDirPol<TZ, FL, PAIR> P;
       P.op.init(z, g, jst, (uint32_t)(L.ldx * sizeof(TZ)), col_coef(L, g), sp, L.nz);
-      P.rp = roww(p, g.j, jst);
+      P.rp = rowc(pr, g.j, jst);
+      P.rw = roww(pw, g.j, jst);
       P.rq = roww(q, g.j, jst);
       P.rr = rowc(r, g.j, jst);
-      P.ru = roww(u, g.j, jst);
+      P.ru = PAIR ? roww(u, g.j, jst) : nullptr;
       P.oc = (uint32_t)g.ic * 8;
       P.kb = (uint32_t)L.ldx * 8;
       P.beta = beta;
-      P.aprev = aprev;
+      P.alpha = alpha;
+      P.alpha_prev = alpha_prev;
       P.pq = 0.0;
       P.pr = 0.0;
       walk<2, FL>(P, g.n);
@@ -2194,10 +2204,12 @@ __global__ __launch_bounds__(NTHREADS) void k_fcg_fin_alpha(CgState* st,
   if (threadIdx.x == 0) {
     st->sigma = r[0];
     if (!(r[0] > 0.0) || !isfinite(r[0])) {
+      // breakdown before the step: alpha keeps the last step taken, which
+      // the final update may still owe the iterate
       st->status = 3;
       st->done = 1;
-      st->alpha = 0.0;
     } else {
+      st->alpha_prev = st->alpha;
       st->alpha = r[1] / r[0];
     }
   }
@@ -2307,19 +2319,8 @@ __global__ __launch_bounds__(NTHREADS) void k_pair_reduce(PairState* __restrict_
   }
 }
 
-__global__ __launch_bounds__(NTHREADS) void k_cg_final_update(Lvl<double> L,
-                                                              double* __restrict__ u,
-                                                              const double* __restrict__ p,
-                                                              const CgState* __restrict__ st) {
-  if (st->status == 3 || st->iter == 0) return;
-  const double alpha = st->alpha;
-  const int64_t n = (int64_t)L.ny * L.nz * L.ldx;
-  for (int64_t g = (int64_t)blockIdx.x * NTHREADS + threadIdx.x; g < n;
-       g += (int64_t)gridDim.x * NTHREADS)
-    u[g] += alpha * p[g];
-}
-
-// Line-PCG with paired updates: after n completed iterations (n = iter) the
+// Line-PCG and flexible CG with paired updates: after n completed
+// iterations (n = iter) the
 // directions j <= n not yet in u are applied, in order.  The last direction
 // step kernel that ran is iteration n + 1 after a breakdown before its step
 // (status 3), else n; an even one (m) applied the directions up to m - 1, so
@@ -2721,15 +2722,19 @@ hipError_t launch_fcg_zq(const Lvl<double>& L, const TZ* z, const double* q, dou
 }
 
 template <typename TZ>
-hipError_t launch_fcg_dir(const Lvl<double>& L, const TZ* z, double* u, double* p, double* q,
-                          const double* r, const CgState* st, double* partials, int64_t* nblocks,
-                          hipStream_t s, Shape sh) {
+hipError_t launch_fcg_dir(const Lvl<double>& L, const TZ* z, double* u, const double* pr,
+                          double* pw, double* q, const double* r, const CgState* st, bool paired,
+                          double* partials, int64_t* nblocks, hipStream_t s, Shape sh) {
   return with_rows(sh.rows, [&](auto R) {
     constexpr int SR = decltype(R)::value;
     const int nti = cdiv(L.nx, 64), ntj = cdiv(L.ny, SR), nkb = cdiv(L.nz, KSEG);
     *nblocks = (int64_t)nti * ntj * nkb;
-    hipLaunchKernelGGL((k_fcg_dir<TZ, SR>), dim3(nti * ntj * nkb), dim3(64 * SR), 0, s, L, z, u,
-                       p, q, r, st, partials, nti, ntj, sh.group);
+    if (paired)
+      hipLaunchKernelGGL((k_fcg_dir<TZ, SR, true>), dim3(nti * ntj * nkb), dim3(64 * SR), 0, s, L,
+                         z, u, pr, pw, q, r, st, partials, nti, ntj, sh.group);
+    else
+      hipLaunchKernelGGL((k_fcg_dir<TZ, SR, false>), dim3(nti * ntj * nkb), dim3(64 * SR), 0, s,
+                         L, z, u, pr, pw, q, r, st, partials, nti, ntj, sh.group);
   });
 }
 
@@ -2761,12 +2766,14 @@ template hipError_t launch_fcg_zq<double>(const Lvl<double>&, const double*, con
                                           double*, int64_t*, hipStream_t);
 template hipError_t launch_fcg_zq<float>(const Lvl<double>&, const float*, const double*,
                                          double*, int64_t*, hipStream_t);
-template hipError_t launch_fcg_dir<double>(const Lvl<double>&, const double*, double*, double*,
-                                           double*, const double*, const CgState*, double*,
-                                           int64_t*, hipStream_t, Shape);
-template hipError_t launch_fcg_dir<float>(const Lvl<double>&, const float*, double*, double*,
-                                          double*, const double*, const CgState*, double*,
-                                          int64_t*, hipStream_t, Shape);
+template hipError_t launch_fcg_dir<double>(const Lvl<double>&, const double*, double*,
+                                           const double*, double*, double*, const double*,
+                                           const CgState*, bool, double*, int64_t*, hipStream_t,
+                                           Shape);
+template hipError_t launch_fcg_dir<float>(const Lvl<double>&, const float*, double*,
+                                          const double*, double*, double*, const double*,
+                                          const CgState*, bool, double*, int64_t*, hipStream_t,
+                                          Shape);
 
 hipError_t launch_cg_fin1(CgState* st, const double* partials, int64_t nblocks, hipStream_t s) {
   hipLaunchKernelGGL(k_cg_fin1, dim3(1), dim3(NTHREADS), 0, s, st, partials, nblocks);
@@ -2777,14 +2784,6 @@ hipError_t launch_cg_fin2(CgState* st, const double* partials, int64_t nblocks, 
                           double* hist, hipStream_t s) {
   hipLaunchKernelGGL(k_cg_fin2, dim3(1), dim3(NTHREADS), 0, s, st, partials, nblocks, init,
                      hist);
-  return hipGetLastError();
-}
-
-hipError_t launch_cg_final_update(const Lvl<double>& L, double* u, const double* p,
-                                  const CgState* st, hipStream_t s) {
-  const int64_t n = (int64_t)L.ny * L.nz * L.ldx;
-  hipLaunchKernelGGL(k_cg_final_update, dim3(grid_stride_blocks(n)), dim3(NTHREADS), 0, s, L, u,
-                     p, st);
   return hipGetLastError();
 }
 
