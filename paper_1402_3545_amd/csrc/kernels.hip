@@ -150,7 +150,7 @@ __device__ __forceinline__ void tile_coords(int b, int nti, int ntj, int group, 
   ti = g0 + (r - tj * w);
 }
 
-template <int SR>
+template <int SR, int KS = KSEG>
 __device__ __forceinline__ Geo stencil_geo(int nx, int ny, int nz, int nti, int ntj, int group,
                                            int b) {
   Geo g;
@@ -167,8 +167,8 @@ __device__ __forceinline__ Geo stencil_geo(int nx, int ny, int nz, int nti, int 
   g.ic = min(i, nx - 1);
   g.ie = (g.ic + 1 == nx) ? 0 : g.ic + 1;
   g.iw = (g.ic == 0) ? nx - 1 : g.ic - 1;
-  g.k0 = kb * KSEG;
-  g.n = min(nz - g.k0, KSEG);
+  g.k0 = kb * KS;
+  g.n = min(nz - g.k0, KS);
   return g;
 }
 
@@ -177,10 +177,10 @@ struct Prof {
   T sub, sup, dg, dz;
 };
 
-// Vertical profiles of layers k0 .. k0+KSEG-1 (clamped) into LDS.
-template <typename T>
+// Vertical profiles of layers k0 .. k0+KS-1 (clamped) into LDS.
+template <typename T, int KS = KSEG>
 __device__ __forceinline__ void stage_prof(const Lvl<T>& L, int k0, Prof<T>* sp) {
-  for (int t = threadIdx.x; t < KSEG; t += blockDim.x) {
+  for (int t = threadIdx.x; t < KS; t += blockDim.x) {
     const int k = min(k0 + t, L.nz - 1);
     sp[t] = Prof<T>{L.sub[k], L.sup[k], L.dg[k], L.dz[k]};
   }
@@ -247,11 +247,12 @@ __device__ __forceinline__ void sto(char* base, uint32_t off, T v) {
 
 // The layer walk shared by the stencil kernels: P supplies the per-layer
 // input record In, load(s, In&) for layer k0+s and step(s, const In&) that
-// computes and stores layer k0+s.  FULL: the segment has all KSEG layers.
-template <int CH, bool FULL, typename P>
+// computes and stores layer k0+s.  FULL: the segment has all KS layers.
+template <int CH, bool FULL, int KS = KSEG, typename P>
 __device__ __forceinline__ void walk(P& pol, int n) {
   using In = typename P::In;
-  constexpr int NCH = KSEG / CH;
+  static_assert(KS % CH == 0, "whole chunks per segment");
+  constexpr int NCH = KS / CH;
   In buf[2][CH];
 #pragma unroll
   for (int t = 0; t < CH; ++t) pol.load(t, buf[0][t]);
@@ -1355,18 +1356,26 @@ struct ResRestrictPol {
       uWc = lw ? v.uWc : wc;
       uEd = le ? v.uWc : ed;
     }
-    const T ra_ = v.f0.x - ((dgk + dzk * Sa) * c0.x -
-                            dzk * (xab * c0.y + xWa * uWa + yac * c1.x + ySa * v.sS.x) +
-                            sub * m0.x + sup * p0.x);
-    const T rb_ = v.f0.y - ((dgk + dzk * Sb) * c0.y -
-                            dzk * (xbE * uEb + xab * c0.x + ybd * c1.y + ySb * v.sS.y) +
-                            sub * m0.y + sup * p0.y);
-    const T rc_ = v.f1.x - ((dgk + dzk * Sc) * c1.x -
-                            dzk * (xcd * c1.y + xWc * uWc + ycN * v.sN.x + yac * c0.x) +
-                            sub * m1.x + sup * p1.x);
-    const T rd_ = v.f1.y - ((dgk + dzk * Sd) * c1.y -
-                            dzk * (xdE * uEd + xcd * c1.x + ydN * v.sN.y + ybd * c0.y) +
-                            sub * m1.y + sup * p1.y);
+    // f - A u of one child, with every multiply-add spelled out, so that each
+    // instantiation (segment length, tile form, grouped launches) rounds the
+    // same way: (dg + dz S) u - dz (sum of the four coupled neighbours)
+    //   + sub u_below + sup u_above
+    auto res = [&](T f, T S, T uc, T c1_, T n1, T c2_, T n2, T c3_, T n3, T c4_, T n4, T um,
+                   T up) {
+      T h = c1_ * n1;
+      h = fma(c2_, n2, h);
+      h = fma(c3_, n3, h);
+      h = fma(c4_, n4, h);
+      T a = fma(dzk, S, dgk) * uc;
+      a = fma(-dzk, h, a);
+      a = fma(sub, um, a);
+      a = fma(sup, up, a);
+      return f - a;
+    };
+    const T ra_ = res(v.f0.x, Sa, c0.x, xab, c0.y, xWa, uWa, yac, c1.x, ySa, v.sS.x, m0.x, p0.x);
+    const T rb_ = res(v.f0.y, Sb, c0.y, xbE, uEb, xab, c0.x, ybd, c1.y, ySb, v.sS.y, m0.y, p0.y);
+    const T rc_ = res(v.f1.x, Sc, c1.x, xcd, c1.y, xWc, uWc, ycN, v.sN.x, yac, c0.x, m1.x, p1.x);
+    const T rd_ = res(v.f1.y, Sd, c1.y, xdE, uEd, xcd, c1.x, ydN, v.sN.y, ybd, c0.y, m1.y, p1.y);
     sto<T>(ro, oo + layer_off<FULL>(k, nz, ckb), ra_ + rb_ + rc_ + rd_);
     m0 = c0;
     m1 = c1;
@@ -1379,15 +1388,15 @@ struct ResRestrictPol {
 // residual is only needed restricted): f_c(I,J) = sum over the 2x2 children of
 // (f - A u).  One lane per coarse column; its four children are read as two
 // 2-vectors per layer.  The fine residual itself is never stored.
-template <typename T, int SR>
+template <typename T, int SR, int KS = KSEG>
 __device__ __forceinline__ void resrestrict_body(const Lvl<T>& F, const Lvl<T>& C,
                                                  const T* __restrict__ u,
                                                  const T* __restrict__ f, T* __restrict__ fc,
                                                  int nti, int ntj, int group, int b) {
   constexpr int CH = sizeof(T) == 8 ? 1 : 2;
-  const Geo g = stencil_geo<SR>(C.nx, C.ny, C.nz, nti, ntj, group, b);
-  __shared__ Prof<T> sp[KSEG];
-  stage_prof(F, g.k0, sp);
+  const Geo g = stencil_geo<SR, KS>(C.nx, C.ny, C.nz, nti, ntj, group, b);
+  __shared__ Prof<T> sp[KS];
+  stage_prof<T, KS>(F, g.k0, sp);
   if (!(g.row && g.act)) return;
   const int nx = F.nx, ny = F.ny, nz = F.nz;
   const int I = g.ic, J = g.j;
@@ -1449,29 +1458,30 @@ __device__ __forceinline__ void resrestrict_body(const Lvl<T>& F, const Lvl<T>& 
     }
     P.c0 = ldo<V2>(P.ra, P.o2 + (uint32_t)g.k0 * P.fkb);
     P.c1 = ldo<V2>(P.rc, P.o2 + (uint32_t)g.k0 * P.fkb);
-    walk<CH, FL>(P, g.n);
+    walk<CH, FL, KS>(P, g.n);
   };
   if (g.ft) {
-    if (g.n == KSEG)
+    if (g.n == KS)
       run(std::true_type{}, std::true_type{});
     else
       run(std::false_type{}, std::true_type{});
   } else {
-    if (g.n == KSEG)
+    if (g.n == KS)
       run(std::true_type{}, std::false_type{});
     else
       run(std::false_type{}, std::false_type{});
   }
 }
 
-template <typename T, int SR>
+template <typename T, int SR, int KS>
 __global__ __launch_bounds__(64 * SR) void k_resrestrict(Lvl<T> F, Lvl<T> C,
                                                          const T* __restrict__ u,
                                                          const T* __restrict__ f,
                                                          T* __restrict__ fc, int nti, int ntj,
                                                          int group) {
   if (gated(F)) return;
-  resrestrict_body<T, SR>(F, C, u, f, fc, nti, ntj, group, xcd_remap(blockIdx.x, gridDim.x));
+  resrestrict_body<T, SR, KS>(F, C, u, f, fc, nti, ntj, group,
+                              xcd_remap(blockIdx.x, gridDim.x));
 }
 
 // ---------------------------------------------------------------------------
@@ -1658,11 +1668,11 @@ struct ProlongPol {
 // 9/3/3/1 over 16.  Periodic boundaries wrap; behind a Dirichlet wall the
 // neighbour is the parent's mirror image with opposite sign (the linear
 // interpolant that vanishes on the wall).
-template <typename T, int SR>
+template <typename T, int SR, int KS = KSEG>
 __device__ __forceinline__ void prolongate_body(const Lvl<T>& C, const Lvl<T>& F,
                                                 const T* __restrict__ uc, T* __restrict__ uf,
                                                 int nti, int ntj, int group, int b) {
-  const Geo g = stencil_geo<SR>(F.nx, F.ny, F.nz, nti, ntj, group, b);
+  const Geo g = stencil_geo<SR, KS>(F.nx, F.ny, F.nz, nti, ntj, group, b);
   if (!(g.row && g.act)) return;
   const int I = g.ic >> 1, J = g.j >> 1;
   int I2 = I + ((g.ic & 1) ? 1 : -1);
@@ -1702,26 +1712,27 @@ __device__ __forceinline__ void prolongate_body(const Lvl<T>& C, const Lvl<T>& F
     P.wb = T(3) * sx;
     P.wc = T(3) * sy;
     P.wd = sx * sy;
-    walk<4, FL>(P, g.n);
+    walk<4, FL, KS>(P, g.n);
   };
-  if (g.n == KSEG)
+  if (g.n == KS)
     run(std::true_type{});
   else
     run(std::false_type{});
 }
 
-template <typename T, int SR>
+template <typename T, int SR, int KS>
 __global__ __launch_bounds__(64 * SR) void k_prolongate(Lvl<T> C, Lvl<T> F,
                                                         const T* __restrict__ uc,
                                                         T* __restrict__ uf, int nti, int ntj,
                                                         int group) {
   if (gated(F)) return;
-  prolongate_body<T, SR>(C, F, uc, uf, nti, ntj, group, xcd_remap(blockIdx.x, gridDim.x));
+  prolongate_body<T, SR, KS>(C, F, uc, uf, nti, ntj, group, xcd_remap(blockIdx.x, gridDim.x));
 }
 
 // ---------------------------------------------------------------------------
 // CG, first fused kernel ("SpMV" of Sec. 3.1):
-//   u += alpha p;  p = z + beta p;  q = A z + beta q;  partial <p, q>
+//   p = z + beta p;  q = A z + beta q;  partial <p, q>  (+ the pending steps
+//   of the iterate, u += alpha p, on every other iteration)
 // ---------------------------------------------------------------------------
 // PAIR (even iterations of line-PCG): the iterate also takes the two steps
 // not yet applied, u += alpha_prev p_{i-2} + alpha p_{i-1}, with p_{i-2} read
@@ -2647,14 +2658,29 @@ hipError_t launch_smooth_norm(const Lvl<T>& L, const T* f, const T* uin, T* uout
   return line_dispatch<T, LINE_SMOOTH_NORM>(L, a, s, sh.group, sh.rows);
 }
 
+// Levels with at most kShortSegCols lane columns walk segments of KSHORT
+// layers instead of KSEG: their kernels are bound by the chain of dependent
+// loads along a segment, not by bandwidth, and shorter segments give more
+// workgroups to overlap those waits (the FP64 residual-restriction onto
+// 64^2 and 32^2: 23 -> 12 and 19 -> 10 us; onto 128^2, which reads a 256^2
+// level, they cost 10 %).
+constexpr int KSHORT = 8;
+constexpr int64_t kShortSegCols = 64 * 64;
+
 template <typename T>
 hipError_t launch_resrestrict(const Lvl<T>& F, const Lvl<T>& C, const T* u, const T* f, T* fc,
                               hipStream_t s, Shape sh) {
+  const bool shortseg = (int64_t)C.nx * C.ny <= kShortSegCols;
   return with_rows(sh.rows, [&](auto R) {
     constexpr int SR = decltype(R)::value;
-    const int nti = cdiv(C.nx, 64), ntj = cdiv(C.ny, SR), nkb = cdiv(C.nz, KSEG);
-    hipLaunchKernelGGL((k_resrestrict<T, SR>), dim3(nti * ntj * nkb), dim3(64 * SR), 0, s, F, C,
-                       u, f, fc, nti, ntj, sh.group);
+    const int ks = shortseg ? KSHORT : KSEG;
+    const int nti = cdiv(C.nx, 64), ntj = cdiv(C.ny, SR), nkb = cdiv(C.nz, ks);
+    if (shortseg)
+      hipLaunchKernelGGL((k_resrestrict<T, SR, KSHORT>), dim3(nti * ntj * nkb), dim3(64 * SR), 0,
+                         s, F, C, u, f, fc, nti, ntj, sh.group);
+    else
+      hipLaunchKernelGGL((k_resrestrict<T, SR, KSEG>), dim3(nti * ntj * nkb), dim3(64 * SR), 0,
+                         s, F, C, u, f, fc, nti, ntj, sh.group);
   });
 }
 
@@ -2673,11 +2699,17 @@ hipError_t launch_correct_residual(const Lvl<double>& L, const double* u, const 
 template <typename T>
 hipError_t launch_prolongate(const Lvl<T>& C, const Lvl<T>& F, const T* uc, T* uf,
                              hipStream_t s, Shape sh) {
+  const bool shortseg = (int64_t)F.nx * F.ny <= kShortSegCols;
   return with_rows(sh.rows, [&](auto R) {
     constexpr int SR = decltype(R)::value;
-    const int nti = cdiv(F.nx, 64), ntj = cdiv(F.ny, SR), nkb = cdiv(F.nz, KSEG);
-    hipLaunchKernelGGL((k_prolongate<T, SR>), dim3(nti * ntj * nkb), dim3(64 * SR), 0, s, C, F,
-                       uc, uf, nti, ntj, sh.group);
+    const int ks = shortseg ? KSHORT : KSEG;
+    const int nti = cdiv(F.nx, 64), ntj = cdiv(F.ny, SR), nkb = cdiv(F.nz, ks);
+    if (shortseg)
+      hipLaunchKernelGGL((k_prolongate<T, SR, KSHORT>), dim3(nti * ntj * nkb), dim3(64 * SR), 0,
+                         s, C, F, uc, uf, nti, ntj, sh.group);
+    else
+      hipLaunchKernelGGL((k_prolongate<T, SR, KSEG>), dim3(nti * ntj * nkb), dim3(64 * SR), 0, s,
+                         C, F, uc, uf, nti, ntj, sh.group);
   });
 }
 
