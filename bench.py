@@ -82,14 +82,14 @@ MEASURED_TRAFFIC = {
     # launch shape); profiles/cg_p1_1024x1024x128_pmc.md.  Averages over the
     # 162 dispatches that did the work (82 odd-iteration, 80 even-iteration
     # forms; the two enqueued past convergence return at once).  Plain-copy
-    # calibration: 2 GiB read + 2 GiB written read FETCH_SIZE 1048592.6 KiB,
-    # WRITE_SIZE 2097192.0 KiB.
+    # calibration: 2 GiB read + 2 GiB written read FETCH_SIZE 1048592.2 KiB,
+    # WRITE_SIZE 2097191.3 KiB.
     ("cg_spmv", 0, "f64"): {
-        "fetch_kib": 2313138.6825,
-        "write_kib": 2615100.3993,
-        "copy_fetch_scale": 2097152.0 / 1048592.6146,
-        "copy_write_scale": 2097152.0 / 2097191.9792,
-        "source_sha256": "54c9e0c7b9d5d2e1f6817304c8aea7d5ee16bd33b40fb83577d01439fec01ded",
+        "fetch_kib": 2312138.2454,
+        "write_kib": 2615100.5048,
+        "copy_fetch_scale": 2097152.0 / 1048592.2188,
+        "copy_write_scale": 2097152.0 / 2097191.25,
+        "source_sha256": "e13ebc6011fb327a0adffe14bff5e817f326e4a48b0e21e40bcb500f77b1e181",
         "shape": [16, 8],
     },
 }
