@@ -78,19 +78,19 @@ SOLVES = ("mg_f64", "pcg_f64", "mg_mixed", "fcg_mixed")
 # dispatches) scaled by what the same counters read for a plain copy of known
 # size.  Reported only while the kernel source hashes to the recorded value.
 MEASURED_TRAFFIC = {
-    # k_cg_p1 (both forms), 64x16 workgroups, tile groups of 8 (the stored
+    # k_cg_p1 (both forms), 64x8 workgroups, tile groups of 8 (the stored
     # launch shape); profiles/cg_p1_1024x1024x128_pmc.md.  Averages over the
     # 162 dispatches that did the work (82 odd-iteration, 80 even-iteration
     # forms; the two enqueued past convergence return at once).  Plain-copy
-    # calibration: 2 GiB read + 2 GiB written read FETCH_SIZE 1048592.2 KiB,
-    # WRITE_SIZE 2097191.3 KiB.
+    # calibration: 2 GiB read + 2 GiB written read FETCH_SIZE 1048592.7 KiB,
+    # WRITE_SIZE 2097202.8 KiB.
     ("cg_spmv", 0, "f64"): {
-        "fetch_kib": 2312138.2454,
-        "write_kib": 2615100.5048,
-        "copy_fetch_scale": 2097152.0 / 1048592.2188,
-        "copy_write_scale": 2097152.0 / 2097191.25,
-        "source_sha256": "e13ebc6011fb327a0adffe14bff5e817f326e4a48b0e21e40bcb500f77b1e181",
-        "shape": [16, 8],
+        "fetch_kib": 2260215.5706,
+        "write_kib": 2615227.9307,
+        "copy_fetch_scale": 2097152.0 / 1048592.7396,
+        "copy_write_scale": 2097152.0 / 2097202.8333,
+        "source_sha256": "90375692ce45f916daae59124867b0fc028eb98ad150c5c25ae43c7f028299a1",
+        "shape": [8, 8],
     },
 }
 KERNEL_SOURCE = os.path.join(ROOT, "paper_1402_3545_amd", "csrc", "kernels.hip")
