@@ -834,6 +834,26 @@ def main():
         batched, batch_sample = batched_comparison(torch)
         if not want_oracle:
             batch_sample = None
+        # bandwidth estimates: the per-cell, per-iteration algorithmic bytes
+        # of the same solves on the share (its per-kernel tables), applied to
+        # the other grids' unknowns x iterations (their hierarchies have the
+        # same structure; coarse levels add under 2 %)
+        def est(rate, name):
+            if name not in solve_rates:
+                return None
+            gbs = rate * solve_rates[name]["words_per_cell_iteration"] * 8.0 / 1e9
+            return {"algorithmic_gbs_estimate": gbs, "frac_of_peak_estimate": gbs / HBM_PEAK_GBS,
+                    "bytes_per_cell_iteration_from": f"{name} on the share"}
+        try:
+            for tag in ("mg_f64", "mg_mixed"):
+                e = est(largest[tag]["unknowns_iterations_per_s"], tag)
+                if e:
+                    largest[tag].update(e)
+            e = est(batched["unknowns_iterations_per_s"], "mg_mixed")
+            if e:
+                batched.update(e)
+        except (KeyError, TypeError) as ex:  # an estimate never costs the line
+            log(f"[bench] bandwidth estimates skipped: {ex!r}")
 
     base = checks = None
     if want_oracle:
