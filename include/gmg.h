@@ -174,7 +174,10 @@ int gmg_solve(gmg_ctx *c, const double *f, double *u, double rtol, int maxit, in
 
 /* Preconditioned CG (Sec. 2.2; fused kernels of Sec. 3.1).  precond = 0: the
  * vertical line preconditioner M in FP64, with the two fused kernels
- * (SpMV + vector updates + <p,q>; line solve + residual update + <r,r>, <r,z>).
+ * (SpMV + vector updates + <p,q>; line solve + residual update + <r,r>, <r,z>);
+ * the iterate takes its steps alpha p two at a time, in the first kernel of
+ * every other iteration, and those still pending at exit in a final update
+ * (the same iterates as one step per iteration).
  * precond = 1: flexible CG with one V-cycle (in prec_precond) as the
  * preconditioner.  precond = 2: flexible CG with the line preconditioner M
  * applied in prec_precond (with GMG_F32: FP32 Thomas on the FP32-rounded
