@@ -82,14 +82,14 @@ MEASURED_TRAFFIC = {
     # launch shape); profiles/cg_p1_1024x1024x128_pmc.md.  Averages over the
     # 162 dispatches that did the work (82 odd-iteration, 80 even-iteration
     # forms; the two enqueued past convergence return at once).  Plain-copy
-    # calibration: 2 GiB read + 2 GiB written read FETCH_SIZE 1048592.4 KiB,
-    # WRITE_SIZE 2097192.1 KiB.
+    # calibration: 2 GiB read + 2 GiB written read FETCH_SIZE 1048592.3 KiB,
+    # WRITE_SIZE 2097192.6 KiB.
     ("cg_spmv", 0, "f64"): {
-        "fetch_kib": 2249788.5293,
-        "write_kib": 2615227.8682,
-        "copy_fetch_scale": 2097152.0 / 1048592.3958,
-        "copy_write_scale": 2097152.0 / 2097192.0625,
-        "source_sha256": "79a207f96573200bf16812b36961c54391b03d5ce781f421c58dfc4eacd08018",
+        "fetch_kib": 2249939.0212,
+        "write_kib": 2615226.2820,
+        "copy_fetch_scale": 2097152.0 / 1048592.3438,
+        "copy_write_scale": 2097152.0 / 2097192.5625,
+        "source_sha256": "dd7b0d13b8c51558879fab40ede78327423d077c36128b4dd5adb5d4bc1ea7cd",
         "shape": [8, 8],
     },
 }

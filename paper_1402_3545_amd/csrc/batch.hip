@@ -37,6 +37,7 @@ struct PairBufs {
 struct Launch {
   int kind;  // GKind value
   int half;
+  int exact;  // line kinds: every item's columns have exactly 2 * half layers
   size_t item_off;
   int nitems;
   int nblocks;
@@ -100,8 +101,8 @@ namespace {
 // Enqueue one refinement step (parity 0: uA -> uB, 1: uB -> uA) on stream s.
 int enqueue_step(Batch* b, int parity, hipStream_t s) {
   for (const Launch& l : b->vc)
-    BTRY(launch_grouped_f32((GKind)l.kind, l.half, b->ditems + l.item_off, l.nitems, l.nblocks,
-                            b->dactive, b->rho, s));
+    BTRY(launch_grouped_f32((GKind)l.kind, l.half, l.exact != 0, b->ditems + l.item_off,
+                            l.nitems, l.nblocks, b->dactive, b->rho, s));
   BTRY(launch_grouped_cr(b->dcr[parity], b->cr_nitems, b->cr_nblocks, b->dactive, b->partials, s));
   BTRY(launch_pair_reduce(b->dstate, b->dactive, b->partials, b->npairs, 0, s));
   return GMG_OK;
@@ -158,7 +159,10 @@ int build(Batch* b, hipStream_t s) {
   std::vector<GItem<float>> items;
   auto emit = [&](GKind kind, int half, std::vector<GItem<float>>& its) {
     if (its.empty()) return;
-    Launch l{(int)kind, half, items.size(), (int)its.size(), 0};
+    // the exact-height line kernels exist for columns of 32, 64 and 128 layers
+    bool exact = half >= 16;
+    for (const GItem<float>& it : its) exact = exact && it.L.nz == 2 * half;
+    Launch l{(int)kind, half, exact ? 1 : 0, items.size(), (int)its.size(), 0};
     int blk = 0;
     for (GItem<float>& it : its) {
       it.blk0 = blk;

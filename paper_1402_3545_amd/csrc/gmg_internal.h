@@ -307,8 +307,10 @@ hipError_t launch_add_f32_to_f64(double* u, const float* e, int64_t n, hipStream
 
 // grouped launches (batched solves)
 enum class GKind { LINE_SOLVE = 0, SMOOTH = 1, RESRESTRICT = 2, PROLONGATE = 3, PROLONG_SMOOTH = 4 };
-hipError_t launch_grouped_f32(GKind kind, int half, const GItem<float>* items, int nitems,
-                              int nblocks, const int* active, float rho, hipStream_t s);
+// exact: every item has columns of exactly 2 * half layers (32, 64 or 128)
+hipError_t launch_grouped_f32(GKind kind, int half, bool exact, const GItem<float>* items,
+                              int nitems, int nblocks, const int* active, float rho,
+                              hipStream_t s);
 hipError_t launch_grouped_cr(const GItemCR* items, int nitems, int nblocks, const int* active,
                              double* partials, hipStream_t s);
 // one workgroup per pair: sum its partials, update its state and activity

@@ -2036,8 +2036,10 @@ __device__ __forceinline__ int find_item(const I* __restrict__ items, int nitems
   return lo;
 }
 
-template <int HALF, int MODE>
-__global__ __launch_bounds__(NTHREADS) void k_line_grouped(const GItem<float>* __restrict__ items,
+// EX: every item of the launch has columns of exactly 2 HALF layers (the host
+// checks), so the exact-height form serves them all.
+template <int HALF, int MODE, bool EX>
+__global__ __launch_bounds__(NTHREADS) __attribute__((amdgpu_waves_per_eu(3))) void k_line_grouped(const GItem<float>* __restrict__ items,
                                                            int nitems,
                                                            const int* __restrict__ active,
                                                            float rho) {
@@ -2052,9 +2054,11 @@ __global__ __launch_bounds__(NTHREADS) void k_line_grouped(const GItem<float>* _
   if constexpr (MODE == LINE_PROLONG_SMOOTH) {
     a.C = it.X;
     a.uc = it.c;
-    line_body<float, HALF, MODE, true>(it.L, a, it.nti, it.ntj, 0, B - it.blk0);
+    line_body<float, HALF, MODE, true, EX>(it.L, a, it.nti, it.ntj, 0, B - it.blk0);
   } else {
-    line_body<float, HALF, MODE>(it.L, a, it.nti, it.ntj, 0, B - it.blk0);
+    // the smoother stages its horizontal neighbours in LDS
+    line_body<float, HALF, MODE, MODE == LINE_SMOOTH, EX>(it.L, a, it.nti, it.ntj, 0,
+                                                          B - it.blk0);
   }
 }
 
@@ -2063,7 +2067,7 @@ __global__ __launch_bounds__(NTHREADS) void k_resrestrict_grouped(
   const int B = xcd_remap(blockIdx.x, gridDim.x);
   const GItem<float> it = items[find_item(items, nitems, B)];
   if (!active[it.pair]) return;
-  resrestrict_body<float, SROWS>(it.L, it.X, it.a, it.b, it.o, it.nti, it.ntj, 0, B - it.blk0);
+  resrestrict_body<float, SROWS, KSEG, 4>(it.L, it.X, it.a, it.b, it.o, it.nti, it.ntj, 0, B - it.blk0);
 }
 
 __global__ __launch_bounds__(NTHREADS) void k_prolongate_grouped(
@@ -2081,7 +2085,7 @@ __global__ __launch_bounds__(NTHREADS) void k_correct_residual_grouped(
   const GItemCR it = items[find_item(items, nitems, B)];
   if (!active[it.pair]) return;
   // partial of workgroup B of the item goes to slot B (the pair's segment)
-  correct_residual_body<SROWS>(it.L, it.u, it.e, it.f, it.uout, it.r32,
+  correct_residual_body<SROWS, 4>(it.L, it.u, it.e, it.f, it.uout, it.r32,
                                partials - blockIdx.x + B, it.nti, it.ntj, 0, B - it.blk0);
 }
 
@@ -2487,8 +2491,9 @@ int64_t stencil_tiles_x(int nx) { return cdiv(nx, 64); }
 int64_t stencil_tiles_y(int ny) { return cdiv(ny, SROWS); }
 int64_t stencil_tiles_k(int nz) { return cdiv(nz, KSEG); }
 
-hipError_t launch_grouped_f32(GKind kind, int half, const GItem<float>* items, int nitems,
-                              int nblocks, const int* active, float rho, hipStream_t s) {
+hipError_t launch_grouped_f32(GKind kind, int half, bool exact, const GItem<float>* items,
+                              int nitems, int nblocks, const int* active, float rho,
+                              hipStream_t s) {
   const dim3 grid(nblocks), block(NTHREADS);
   switch (kind) {
     case GKind::LINE_SOLVE:
@@ -2496,24 +2501,27 @@ hipError_t launch_grouped_f32(GKind kind, int half, const GItem<float>* items, i
     case GKind::PROLONG_SMOOTH: {
       const bool sm = kind == GKind::SMOOTH;
       const bool ps = kind == GKind::PROLONG_SMOOTH;
-#define GMG_GLINE(H)                                                                         \
-  if (half == H) {                                                                           \
+#define GMG_GLINE(H, EX)                                                                     \
+  if (half == H && exact == EX) {                                                            \
     if (ps)                                                                                  \
-      hipLaunchKernelGGL((k_line_grouped<H, LINE_PROLONG_SMOOTH>), grid, block, 0, s, items, \
-                         nitems, active, rho);                                               \
+      hipLaunchKernelGGL((k_line_grouped<H, LINE_PROLONG_SMOOTH, EX>), grid, block, 0, s,    \
+                         items, nitems, active, rho);                                        \
     else if (sm)                                                                             \
-      hipLaunchKernelGGL((k_line_grouped<H, LINE_SMOOTH>), grid, block, 0, s, items, nitems, \
-                         active, rho);                                                       \
+      hipLaunchKernelGGL((k_line_grouped<H, LINE_SMOOTH, EX>), grid, block, 0, s, items,     \
+                         nitems, active, rho);                                               \
     else                                                                                     \
-      hipLaunchKernelGGL((k_line_grouped<H, LINE_SOLVE>), grid, block, 0, s, items, nitems,  \
-                         active, rho);                                                       \
+      hipLaunchKernelGGL((k_line_grouped<H, LINE_SOLVE, EX>), grid, block, 0, s, items,      \
+                         nitems, active, rho);                                               \
     return hipGetLastError();                                                                \
   }
-      GMG_GLINE(4)
-      GMG_GLINE(8)
-      GMG_GLINE(16)
-      GMG_GLINE(32)
-      GMG_GLINE(64)
+      GMG_GLINE(4, false)
+      GMG_GLINE(8, false)
+      GMG_GLINE(16, false)
+      GMG_GLINE(32, false)
+      GMG_GLINE(64, false)
+      GMG_GLINE(16, true)
+      GMG_GLINE(32, true)
+      GMG_GLINE(64, true)
 #undef GMG_GLINE
       return hipErrorInvalidValue;
     }

@@ -14,9 +14,11 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
 # (n, nz, levels): uneven sizes, column heights in every compile-time class,
-# coarsest levels at different depths, a single-level instance
+# coarsest levels at different depths, a single-level instance; 32 and 128
+# layers alone in their class (the exact-height grouped launches), 50 beside
+# 64 (one launch of the general form for both)
 INSTANCES = [(32, 8, 3), (64, 16, 4), (48, 5, 2), (16, 32, 3), (40, 64, 2), (24, 3, 1),
-             (64, 128, 4)]
+             (64, 128, 4), (32, 50, 2)]
 NRHS = 2
 
 
