@@ -209,7 +209,9 @@ def test_mixed_and_flexible_with_walls(precond):
 def test_batched_solve_with_walls():
     import oracle
     import paper_1402_3545_amd as G
-    shapes = [(32, 8, 3), (48, 16, 3), (64, 32, 4)]
+    # 32 and 128 layers alone in their height class: the exact-height grouped
+    # forms behind walls, the 128-layer one in ragged 32-column tiles (n = 40)
+    shapes = [(32, 8, 3), (48, 16, 3), (64, 32, 4), (40, 128, 3)]
     kws = []
     for q, (n, nz, L) in enumerate(shapes):
         K = (4.2 / n) ** 2
